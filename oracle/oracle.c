@@ -1,0 +1,378 @@
+/*
+ * oracle.c - plain, slow, FP64 CPU reference for the sparse products.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library links, loads or calls this
+ * file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header or helper with the GPU library.
+ *
+ * Every routine is the plain definition written out as loops, in double
+ * precision, with no blocking, fusion or reordering beyond the definition.
+ * Where a routine is parallel (OpenMP over output rows), each output element is
+ * still produced by one thread in the definition's order, so results do not
+ * depend on the thread count.
+ *
+ * Sources:
+ *   - SpMM, Section II-A, Eq. (1): Y = A X with A sparse, X dense.
+ *   - SDDMM, Section II-A, Eq. (2): Y = A (.) (B C), evaluated only where A has a
+ *     stored entry (Section II-A and Section III-B: workers hold row index,
+ *     column index and value of each nonzero and produce one output per
+ *     nonzero).  The paper's B, C are this library's U and V^T.
+ *   - CSR input with 32-bit column indices and 32-bit float values,
+ *     Section III-A.
+ *   - Backward of SpMM: for L(C) with C = A B, dL/dB = A^T G and
+ *     dL/dvals[p] = <G[row(p),:], B[col(p),:]> (chain rule on Eq. (1)).
+ *   - bfloat16 rounding: IEEE-754 binary32 -> 8-bit-significand rounding to
+ *     nearest, ties to even, by integer manipulation of the bit pattern.
+ *   - MLP: three affine layers with ReLU between them, masked mean-squared
+ *     error, hand-derived gradients, and the Adam update (Kingma and Ba, ICLR
+ *     2015, Algorithm 1).
+ *
+ * All row_ptr arrays may start at any offset: entries of row i are the
+ * positions row_ptr[i] .. row_ptr[i+1]-1 of col_idx / vals, so a caller can
+ * pass a slice of rows together with the full index arrays.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------- */
+/* SpMM, Eq. (1):  C[i,k] = sum_{p in row i} v_p * B[col_p, k].            */
+/* vals == NULL means every stored entry is 1 (the pattern alone).         */
+/* bound (optional) receives sum |v_p| * |B[col_p, k]|, the scale of the    */
+/* error allowed for a floating-point evaluation of C[i,k].                */
+/* ---------------------------------------------------------------------- */
+void oracle_spmm(int64_t m, int64_t K, const int32_t *row_ptr, const int32_t *col_idx,
+                 const double *vals, const double *B, int64_t ldb, double *C, int64_t ldc,
+                 double *bound) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t k = 0; k < K; ++k) {
+            double acc = 0.0, mag = 0.0;
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                double v = vals ? vals[p] : 1.0;
+                double b = B[(int64_t)col_idx[p] * ldb + k];
+                acc += v * b;
+                mag += fabs(v) * fabs(b);
+            }
+            C[i * ldc + k] = acc;
+            if (bound) bound[i * ldc + k] = mag;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* SDDMM, Eq. (2):  S[p] = v_p * sum_k U[row_p, k] * V[col_p, k]           */
+/* for every stored entry p; (U V^T) is never formed densely.              */
+/* ---------------------------------------------------------------------- */
+void oracle_sddmm(int64_t m, int64_t K, const int32_t *row_ptr, const int32_t *col_idx,
+                  const double *vals, const double *U, int64_t ldu, const double *V,
+                  int64_t ldv, double *S, double *bound) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            int64_t j = col_idx[p];
+            double dot = 0.0, mag = 0.0;
+            for (int64_t k = 0; k < K; ++k) {
+                dot += U[i * ldu + k] * V[j * ldv + k];
+                mag += fabs(U[i * ldu + k]) * fabs(V[j * ldv + k]);
+            }
+            double v = vals ? vals[p] : 1.0;
+            S[p] = v * dot;
+            if (bound) bound[p] = fabs(v) * mag;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Transpose of a CSR pattern, by a stable counting sort on the column.    */
+/* Entries of A are visited in storage order (row-major); entry p with     */
+/* column j becomes the next entry of row j of A^T, so rows of A^T list    */
+/* their columns (rows of A) in increasing order and perm[q] = p records   */
+/* where entry q of A^T came from.  row_ptr of A must start at 0 here.      */
+/* ---------------------------------------------------------------------- */
+void oracle_csr_transpose(int64_t m, int64_t n, const int32_t *row_ptr,
+                          const int32_t *col_idx, int32_t *t_row_ptr, int32_t *t_col_idx,
+                          int32_t *perm) {
+    int64_t nnz = row_ptr[m];
+    int64_t *next = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t p = 0; p < nnz; ++p) next[col_idx[p] + 1] += 1;
+    for (int64_t j = 0; j < n; ++j) next[j + 1] += next[j];
+    for (int64_t j = 0; j <= n; ++j) t_row_ptr[j] = (int32_t)next[j];
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            int64_t q = next[col_idx[p]]++;
+            t_col_idx[q] = (int32_t)i;
+            perm[q] = (int32_t)p;
+        }
+    }
+    free(next);
+}
+
+/* ---------------------------------------------------------------------- */
+/* A^T G by its definition: (A^T G)[j,k] = sum over entries p of A with     */
+/* column j of v_p * G[row_p, k].  Evaluated as a scatter over A's entries */
+/* in storage order (so it does not use the transpose routine above).      */
+/* ---------------------------------------------------------------------- */
+void oracle_spmm_t(int64_t m, int64_t n, int64_t K, const int32_t *row_ptr,
+                   const int32_t *col_idx, const double *vals, const double *G, int64_t ldg,
+                   double *D, int64_t ldd, double *bound) {
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = 0; k < K; ++k) {
+            D[j * ldd + k] = 0.0;
+            if (bound) bound[j * ldd + k] = 0.0;
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < K; ++k) {
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                double v = vals ? vals[p] : 1.0;
+                double g = G[i * ldg + k];
+                D[(int64_t)col_idx[p] * ldd + k] += v * g;
+                if (bound) bound[(int64_t)col_idx[p] * ldd + k] += fabs(v) * fabs(g);
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* bfloat16 rounding of binary32 values, round to nearest, ties to even.   */
+/* The result is returned as a binary32 value whose low 16 bits are zero.  */
+/* NaN inputs stay NaN (quiet bit forced); infinities are kept.            */
+/* ---------------------------------------------------------------------- */
+void oracle_round_bf16(const float *in, float *out, int64_t count) {
+    for (int64_t i = 0; i < count; ++i) {
+        uint32_t u;
+        memcpy(&u, &in[i], 4);
+        uint32_t r;
+        if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0) {
+            r = (u | 0x00400000u) & 0xFFFF0000u;
+        } else {
+            uint32_t lower = u & 0xFFFFu;
+            uint32_t upper = u & 0xFFFF0000u;
+            uint32_t half = 0x8000u;
+            int round_up = lower > half || (lower == half && (upper & 0x10000u));
+            r = upper + (round_up ? 0x10000u : 0u);
+        }
+        memcpy(&out[i], &r, 4);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Structural features of a CSR pattern (all integer counts):               */
+/*   f[0] m, f[1] n, f[2] nnz,                                              */
+/*   f[3..22] row-length histogram: bin 0 = empty rows, bin b in 1..18 =    */
+/*            lengths in [2^(b-1), 2^b), bin 19 = lengths >= 2^18,          */
+/*   f[23] max row length, f[24] sum of squared row lengths,                 */
+/*   f[25] max |i - j| over entries, f[26] sum of |i - j| over entries,      */
+/*   f[27] number of 4x4 blocks (aligned at multiples of 4) holding at      */
+/*         least one entry.                                                  */
+/* ---------------------------------------------------------------------- */
+#define ORACLE_NFEAT 28
+int oracle_feature_count(void) { return ORACLE_NFEAT; }
+
+void oracle_features(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     int64_t *f) {
+    for (int i = 0; i < ORACLE_NFEAT; ++i) f[i] = 0;
+    f[0] = m;
+    f[1] = n;
+    f[2] = (int64_t)row_ptr[m] - row_ptr[0];
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t L = (int64_t)row_ptr[i + 1] - row_ptr[i];
+        int bin;
+        if (L == 0) {
+            bin = 0;
+        } else {
+            bin = 1;
+            while (bin < 19 && L >= ((int64_t)1 << bin)) ++bin;
+        }
+        f[3 + bin] += 1;
+        if (L > f[23]) f[23] = L;
+        f[24] += L * L;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            int64_t d = i - (int64_t)col_idx[p];
+            if (d < 0) d = -d;
+            if (d > f[25]) f[25] = d;
+            f[26] += d;
+        }
+    }
+    /* Count distinct (i/4, j/4) pairs: mark block columns per block row. */
+    int64_t nbc = (n + 3) / 4;
+    unsigned char *seen = (unsigned char *)calloc((size_t)(nbc > 0 ? nbc : 1), 1);
+    for (int64_t I = 0; I * 4 < m; ++I) {
+        int64_t r1 = (I * 4 + 4 < m) ? I * 4 + 4 : m;
+        for (int64_t i = I * 4; i < r1; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                int64_t J = col_idx[p] / 4;
+                if (!seen[J]) { seen[J] = 1; f[27] += 1; }
+            }
+        for (int64_t i = I * 4; i < r1; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) seen[col_idx[p] / 4] = 0;
+    }
+    free(seen);
+}
+
+/* ---------------------------------------------------------------------- */
+/* CSR -> 4x4 block CSR.  Block (I, J) exists when any entry (i, j) has     */
+/* i/4 == I and j/4 == J.  Block values are dense row-major 4x4 tiles with   */
+/* zeros where A has no entry; block columns ascend within a block row.     */
+/* Count pass: b_col == NULL, returns the number of blocks and fills        */
+/* b_row_ptr.  Fill pass: writes b_col and b_vals (16 per block).            */
+/* ---------------------------------------------------------------------- */
+int64_t oracle_csr_to_bsr4(int64_t m, int64_t n, const int32_t *row_ptr,
+                           const int32_t *col_idx, const double *vals, int32_t *b_row_ptr,
+                           int32_t *b_col, double *b_vals) {
+    int64_t mb = (m + 3) / 4, nbc = (n + 3) / 4;
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nbc > 0 ? nbc : 1));
+    for (int64_t J = 0; J < nbc; ++J) slot[J] = -1;
+    int64_t total = 0;
+    for (int64_t I = 0; I < mb; ++I) {
+        int64_t r1 = (I * 4 + 4 < m) ? I * 4 + 4 : m;
+        int64_t start = total;
+        /* ascending block columns: sweep J over the sorted union */
+        int64_t cnt = 0;
+        for (int64_t i = I * 4; i < r1; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                int64_t J = col_idx[p] / 4;
+                if (slot[J] < 0) { slot[J] = 0; ++cnt; }
+            }
+        if (b_col) {
+            int64_t k = start;
+            for (int64_t J = 0; J < nbc; ++J)
+                if (slot[J] >= 0) { slot[J] = k; b_col[k] = (int32_t)J; ++k; }
+            for (int64_t q = start * 16; q < (start + cnt) * 16; ++q) b_vals[q] = 0.0;
+            for (int64_t i = I * 4; i < r1; ++i)
+                for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                    int64_t J = col_idx[p] / 4;
+                    b_vals[slot[J] * 16 + (i - I * 4) * 4 + (col_idx[p] - J * 4)] +=
+                        vals ? vals[p] : 1.0;
+                }
+        } else {
+            b_row_ptr[I] = (int32_t)start;
+        }
+        for (int64_t i = I * 4; i < r1; ++i)
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) slot[col_idx[p] / 4] = -1;
+        total += cnt;
+    }
+    if (!b_col) b_row_ptr[mb] = (int32_t)total;
+    free(slot);
+    return total;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Three-layer perceptron  y = W3 relu(W2 relu(W1 x + b1) + b2) + b3.       */
+/* Weights are row-major [out][in].  X is [batch][F], Y is [batch][P].      */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t F, H, P;
+    const double *W1, *b1, *W2, *b2, *W3, *b3;
+} oracle_mlp;
+
+static void affine(int64_t nout, int64_t nin, const double *W, const double *b,
+                   const double *x, double *y) {
+    for (int64_t o = 0; o < nout; ++o) {
+        double acc = b[o];
+        for (int64_t i = 0; i < nin; ++i) acc += W[o * nin + i] * x[i];
+        y[o] = acc;
+    }
+}
+
+void oracle_mlp_forward(int64_t F, int64_t H, int64_t P, const double *W1, const double *b1,
+                        const double *W2, const double *b2, const double *W3,
+                        const double *b3, int64_t batch, const double *X, double *Y) {
+    double *h1 = (double *)malloc(sizeof(double) * (size_t)H);
+    double *h2 = (double *)malloc(sizeof(double) * (size_t)H);
+    for (int64_t s = 0; s < batch; ++s) {
+        affine(H, F, W1, b1, X + s * F, h1);
+        for (int64_t o = 0; o < H; ++o) h1[o] = h1[o] > 0.0 ? h1[o] : 0.0;
+        affine(H, H, W2, b2, h1, h2);
+        for (int64_t o = 0; o < H; ++o) h2[o] = h2[o] > 0.0 ? h2[o] : 0.0;
+        affine(P, H, W3, b3, h2, Y + s * P);
+    }
+    free(h1);
+    free(h2);
+}
+
+/* Masked mean-squared error  L = (1 / (2 * count)) * sum mask * (y - t)^2, */
+/* count = number of nonzero mask entries, and its gradient with respect    */
+/* to every weight and bias (accumulated over the batch).  Returns L.       */
+double oracle_mlp_loss_grad(int64_t F, int64_t H, int64_t P, const double *W1,
+                            const double *b1, const double *W2, const double *b2,
+                            const double *W3, const double *b3, int64_t batch,
+                            const double *X, const double *T, const double *mask,
+                            double *gW1, double *gb1, double *gW2, double *gb2,
+                            double *gW3, double *gb3) {
+    memset(gW1, 0, sizeof(double) * (size_t)(H * F));
+    memset(gb1, 0, sizeof(double) * (size_t)H);
+    memset(gW2, 0, sizeof(double) * (size_t)(H * H));
+    memset(gb2, 0, sizeof(double) * (size_t)H);
+    memset(gW3, 0, sizeof(double) * (size_t)(P * H));
+    memset(gb3, 0, sizeof(double) * (size_t)P);
+    double count = 0.0;
+    for (int64_t q = 0; q < batch * P; ++q) count += mask[q] != 0.0 ? 1.0 : 0.0;
+    if (count == 0.0) return 0.0;
+    double *z1 = (double *)malloc(sizeof(double) * (size_t)H);
+    double *a1 = (double *)malloc(sizeof(double) * (size_t)H);
+    double *z2 = (double *)malloc(sizeof(double) * (size_t)H);
+    double *a2 = (double *)malloc(sizeof(double) * (size_t)H);
+    double *y = (double *)malloc(sizeof(double) * (size_t)P);
+    double *dy = (double *)malloc(sizeof(double) * (size_t)P);
+    double *d2 = (double *)malloc(sizeof(double) * (size_t)H);
+    double *d1 = (double *)malloc(sizeof(double) * (size_t)H);
+    double loss = 0.0;
+    for (int64_t s = 0; s < batch; ++s) {
+        const double *x = X + s * F;
+        affine(H, F, W1, b1, x, z1);
+        for (int64_t o = 0; o < H; ++o) a1[o] = z1[o] > 0.0 ? z1[o] : 0.0;
+        affine(H, H, W2, b2, a1, z2);
+        for (int64_t o = 0; o < H; ++o) a2[o] = z2[o] > 0.0 ? z2[o] : 0.0;
+        affine(P, H, W3, b3, a2, y);
+        for (int64_t o = 0; o < P; ++o) {
+            double w = mask[s * P + o] != 0.0 ? 1.0 : 0.0;
+            double e = y[o] - T[s * P + o];
+            loss += w * e * e;
+            dy[o] = w * e / count; /* dL/dy */
+        }
+        /* layer 3 */
+        for (int64_t o = 0; o < P; ++o) {
+            gb3[o] += dy[o];
+            for (int64_t i = 0; i < H; ++i) gW3[o * H + i] += dy[o] * a2[i];
+        }
+        for (int64_t i = 0; i < H; ++i) {
+            double acc = 0.0;
+            for (int64_t o = 0; o < P; ++o) acc += W3[o * H + i] * dy[o];
+            d2[i] = z2[i] > 0.0 ? acc : 0.0;
+        }
+        /* layer 2 */
+        for (int64_t o = 0; o < H; ++o) {
+            gb2[o] += d2[o];
+            for (int64_t i = 0; i < H; ++i) gW2[o * H + i] += d2[o] * a1[i];
+        }
+        for (int64_t i = 0; i < H; ++i) {
+            double acc = 0.0;
+            for (int64_t o = 0; o < H; ++o) acc += W2[o * H + i] * d2[o];
+            d1[i] = z1[i] > 0.0 ? acc : 0.0;
+        }
+        /* layer 1 */
+        for (int64_t o = 0; o < H; ++o) {
+            gb1[o] += d1[o];
+            for (int64_t i = 0; i < F; ++i) gW1[o * F + i] += d1[o] * x[i];
+        }
+    }
+    free(z1); free(a1); free(z2); free(a2); free(y); free(dy); free(d2); free(d1);
+    return loss / (2.0 * count);
+}
+
+/* Adam (Kingma and Ba, Algorithm 1), step number t >= 1, in place. */
+void oracle_adam(int64_t count, double *w, const double *g, double *mom, double *vel,
+                 double lr, double beta1, double beta2, double eps, int64_t t) {
+    double c1 = 1.0 - pow(beta1, (double)t);
+    double c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t i = 0; i < count; ++i) {
+        mom[i] = beta1 * mom[i] + (1.0 - beta1) * g[i];
+        vel[i] = beta2 * vel[i] + (1.0 - beta2) * g[i] * g[i];
+        double mh = mom[i] / c1;
+        double vh = vel[i] / c2;
+        w[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}

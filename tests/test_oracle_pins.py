@@ -1,0 +1,307 @@
+"""Pins of the FP64 oracle against facts fixed outside it (CPU only).
+
+Each test checks the oracle against something other than itself: hand-worked
+examples, dense brute force through numpy's matmul, closed-form special
+cases, identities between the two products, and library routines (scipy's
+CSR transpose, torch's bfloat16 conversion).
+"""
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from paper_2604_27985_amd import synth
+
+
+def dense_of(rp, ci, vals, m, n):
+    D = np.zeros((m, n), np.float64)
+    for i in range(m):
+        for p in range(rp[i], rp[i + 1]):
+            D[i, ci[p]] += 1.0 if vals is None else float(vals[p])
+    return D
+
+
+def rand_csr(m, n, d, seed):
+    A = synth.bernoulli(m, n, d, seed)
+    v = synth.normal(A.nnz, seed, synth.S_VALS)
+    return A, v
+
+
+# ---------------------------------------------------------------- hand-worked
+def test_spmm_hand_example(golden):
+    g = golden["spmm"]
+    C, M = oracle.spmm(g["row_ptr"], g["col_idx"], g["vals"], np.array(g["B"], float))
+    assert np.array_equal(C, np.array(g["C"], float))
+    assert M[1].tolist() == [0.0, 0.0]
+
+
+def test_sddmm_hand_example(golden):
+    g, s = golden["spmm"], golden["sddmm"]
+    S, _ = oracle.sddmm(g["row_ptr"], g["col_idx"], g["vals"], np.array(s["U"], float),
+                        np.array(s["V"], float))
+    assert S.tolist() == s["S"]
+    S0, _ = oracle.sddmm(g["row_ptr"], g["col_idx"], None, np.array(s["U"], float),
+                         np.array(s["V"], float))
+    assert S0.tolist() == s["S_pattern"]
+
+
+def test_transpose_hand_example(golden):
+    g, t = golden["spmm"], golden["transpose"]
+    trp, tci, perm = oracle.csr_transpose(g["row_ptr"], g["col_idx"], g["n"])
+    assert trp.tolist() == t["t_row_ptr"]
+    assert tci.tolist() == t["t_col_idx"]
+    assert perm.tolist() == t["perm"]
+
+
+def test_features_hand_example(golden):
+    g = golden["spmm"]
+    f = oracle.features(g["row_ptr"], g["col_idx"], g["n"])
+    assert f.tolist() == golden["features"]["f"]
+
+
+def test_mlp_hand_example(golden):
+    h = golden["mlp"]
+    net = oracle.MLP(np.array(h["W1"], float), np.array(h["b1"], float), np.array(h["W2"], float),
+                     np.array(h["b2"], float), np.array(h["W3"], float), np.array(h["b3"], float))
+    y = net.forward(np.array([h["x"]], float))
+    assert y.tolist() == [h["y"]]
+
+
+# ---------------------------------------------------------------- brute force
+@settings(max_examples=40, deadline=None)
+@given(m=st.integers(0, 40), n=st.integers(1, 40), d=st.sampled_from([0.0, 0.05, 0.3, 1.0]),
+       K=st.integers(1, 9), seed=st.integers(0, 10_000), pattern=st.booleans())
+def test_spmm_matches_dense(m, n, d, K, seed, pattern):
+    A, v = rand_csr(m, n, d, seed)
+    vals = None if pattern else v
+    B = synth.normal((n, K), seed, synth.S_B).astype(np.float64)
+    C, M = oracle.spmm(A.row_ptr, A.col_idx, vals, B)
+    D = dense_of(A.row_ptr, A.col_idx, vals, m, n)
+    ref = D @ B
+    assert np.allclose(C, ref, rtol=1e-12, atol=1e-12)
+    assert np.allclose(M, np.abs(D) @ np.abs(B), rtol=1e-12, atol=1e-12)
+
+
+@settings(max_examples=40, deadline=None)
+@given(m=st.integers(0, 30), n=st.integers(1, 30), d=st.sampled_from([0.0, 0.1, 0.5, 1.0]),
+       K=st.integers(1, 9), seed=st.integers(0, 10_000))
+def test_sddmm_matches_dense(m, n, d, K, seed):
+    A, v = rand_csr(m, n, d, seed)
+    U = synth.normal((m, K), seed, synth.S_U).astype(np.float64)
+    V = synth.normal((n, K), seed, synth.S_V).astype(np.float64)
+    S, _ = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    full = U @ V.T
+    rows = np.repeat(np.arange(m), A.row_lengths())
+    ref = v.astype(np.float64) * full[rows, A.col_idx]
+    assert np.allclose(S, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_sddmm_full_pattern_is_hadamard():
+    m, n, K = 17, 13, 5
+    A, v = rand_csr(m, n, 1.0, 3)
+    assert A.nnz == m * n
+    U = synth.normal((m, K), 3, synth.S_U)
+    V = synth.normal((n, K), 3, synth.S_V)
+    S, _ = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    ref = v.reshape(m, n).astype(np.float64) * (U.astype(np.float64) @ V.astype(np.float64).T)
+    assert np.allclose(S.reshape(m, n), ref, rtol=1e-12, atol=1e-13)
+
+
+def test_spmm_t_matches_dense():
+    m, n, K = 37, 29, 6
+    A, v = rand_csr(m, n, 0.2, 5)
+    G = synth.normal((m, K), 5, synth.S_G)
+    D, M = oracle.spmm_t(A.row_ptr, A.col_idx, v, G, n)
+    Ad = dense_of(A.row_ptr, A.col_idx, v, m, n)
+    assert np.allclose(D, Ad.T @ G.astype(np.float64), rtol=1e-12, atol=1e-12)
+    assert np.allclose(M, np.abs(Ad).T @ np.abs(G.astype(np.float64)), rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- special cases
+def test_spmm_special_cases_exact():
+    n, K = 50, 7
+    B = synth.normal((n, K), 1, synth.S_B).astype(np.float64)
+    eye = np.arange(n + 1, dtype=np.int32)
+    # identity: C = B
+    C, _ = oracle.spmm(eye, np.arange(n, dtype=np.int32), np.ones(n), B)
+    assert np.array_equal(C, B)
+    # permutation: row gather
+    pi = np.random.default_rng(0).permutation(n).astype(np.int32)
+    C, _ = oracle.spmm(eye, pi, None, B)
+    assert np.array_equal(C, B[pi])
+    # diagonal: row scaling, one product per output
+    dvals = synth.normal(n, 1, synth.S_VALS).astype(np.float64)
+    C, _ = oracle.spmm(eye, np.arange(n, dtype=np.int32), dvals, B)
+    assert np.array_equal(C, dvals[:, None] * B)
+    # K = 1 is a sparse matrix-vector product; B = ones gives row sums
+    A, v = rand_csr(n, n, 0.3, 2)
+    C, _ = oracle.spmm(A.row_ptr, A.col_idx, v, np.ones((n, 1)))
+    sums = np.array([v[A.row_ptr[i]:A.row_ptr[i + 1]].astype(np.float64).sum() for i in range(n)])
+    assert np.allclose(C[:, 0], sums, rtol=1e-13, atol=1e-13)
+    # nnz = 0: all zeros
+    C, M = oracle.spmm(np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0), B)
+    assert not C.any() and not M.any()
+
+
+def test_sddmm_identity_pattern_rowwise_dot():
+    n, K = 40, 9
+    U = synth.normal((n, K), 4, synth.S_U).astype(np.float64)
+    V = synth.normal((n, K), 4, synth.S_V).astype(np.float64)
+    S, _ = oracle.sddmm(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), None, U, V)
+    assert np.allclose(S, np.einsum("ik,ik->i", U, V), rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- identities
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sddmm_trace_identity(seed):
+    """sum_p S_p = <A, U V^T>_F = trace(U^T A V), with A dense."""
+    m, n, K = 60, 45, 8
+    A, v = rand_csr(m, n, 0.15, seed)
+    U = synth.normal((m, K), seed, synth.S_U).astype(np.float64)
+    V = synth.normal((n, K), seed, synth.S_V).astype(np.float64)
+    S, _ = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    Ad = dense_of(A.row_ptr, A.col_idx, v, m, n)
+    assert np.isclose(S.sum(), np.trace(U.T @ Ad @ V), rtol=1e-11)
+
+
+@pytest.mark.parametrize("seed", [0, 7])
+def test_adjoint_identity(seed):
+    """<SpMM(A, B), G> = <vals, SDDMM(pattern, G, B)>."""
+    m, n, K = 80, 70, 12
+    A, v = rand_csr(m, n, 0.1, seed)
+    B = synth.normal((n, K), seed, synth.S_B)
+    G = synth.normal((m, K), seed, synth.S_G)
+    C, _ = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    S, _ = oracle.sddmm(A.row_ptr, A.col_idx, None, G, B)
+    lhs = float((C * G.astype(np.float64)).sum())
+    rhs = float((v.astype(np.float64) * S).sum())
+    assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(lhs))
+
+
+def test_transpose_against_scipy_and_involution():
+    import scipy.sparse as sp
+
+    m, n = 123, 77
+    A, v = rand_csr(m, n, 0.07, 11)
+    trp, tci, perm = oracle.csr_transpose(A.row_ptr, A.col_idx, n)
+    ref = sp.csr_matrix((np.arange(A.nnz), A.col_idx, A.row_ptr), shape=(m, n)).T.tocsr()
+    ref.sort_indices()
+    assert np.array_equal(trp, ref.indptr) and np.array_equal(tci, ref.indices)
+    assert np.array_equal(perm, ref.data)
+    assert np.array_equal(np.sort(perm), np.arange(A.nnz))
+    rp2, ci2, perm2 = oracle.csr_transpose(trp, tci, m)
+    assert np.array_equal(rp2, A.row_ptr) and np.array_equal(ci2, A.col_idx)
+    assert np.array_equal(perm[perm2], np.arange(A.nnz))
+
+
+def test_backward_matches_finite_differences():
+    """L(vals, B) = <A B, G> is bilinear, so central differences are exact up to rounding."""
+    m, n, K = 20, 16, 4
+    A, v = rand_csr(m, n, 0.3, 9)
+    B = synth.normal((n, K), 9, synth.S_B).astype(np.float64)
+    G = synth.normal((m, K), 9, synth.S_G).astype(np.float64)
+    v64 = v.astype(np.float64)
+    dB, _, dv, _ = oracle.spmm_backward(A.row_ptr, A.col_idx, v64, B, G, n)
+
+    def L(vv, BB):
+        C, _ = oracle.spmm(A.row_ptr, A.col_idx, vv, BB, with_bound=False)
+        return float((C * G).sum())
+
+    h = 2.0 ** -10
+    for p in range(0, A.nnz, 7):
+        e = np.zeros_like(v64); e[p] = h
+        fd = (L(v64 + e, B) - L(v64 - e, B)) / (2 * h)
+        assert abs(fd - dv[p]) <= 1e-10 * max(1.0, abs(dv).max())
+    for (j, k) in [(0, 0), (3, 2), (n - 1, K - 1), (7, 1)]:
+        E = np.zeros_like(B); E[j, k] = h
+        fd = (L(v64, B + E) - L(v64, B - E)) / (2 * h)
+        assert abs(fd - dB[j, k]) <= 1e-10 * max(1.0, abs(dB).max())
+
+
+# ---------------------------------------------------------------- bf16
+def test_bf16_rounding_against_torch_and_ties():
+    import torch
+
+    x = synth.normal(100_000, 3, synth.S_MISC) * np.float32(1e3)
+    ties = np.array([0x3F808000, 0x3F818000, 0xBF808000, 0x3F80FFFF, 0x7F7FFFFF, 0x00008000,
+                     0x00018000, 0x7F800000, 0xFF800000, 0x00000000, 0x80000000],
+                    dtype=np.uint32).view(np.float32)
+    x = np.concatenate([x, ties])
+    got = oracle.round_bf16(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    # by hand: 1 + 2^-8 is a tie, rounds to even (1.0); 1 + 3*2^-8 rounds up
+    assert got[-11].view(np.uint32) == 0x3F800000
+    assert got[-10].view(np.uint32) == 0x3F820000
+    assert not (got.view(np.uint32) & 0xFFFF).any()
+
+
+# ---------------------------------------------------------------- features, bsr
+def test_features_brute_force():
+    for (m, n, d, seed, kind) in [(70, 90, 0.05, 1, "u"), (64, 64, 0.1, 2, "b"), (33, 33, 0.0, 0, "u")]:
+        A = synth.block4(m, n, d, seed) if kind == "b" else synth.bernoulli(m, n, d, seed)
+        f = oracle.features(A.row_ptr, A.col_idx, n)
+        L = A.row_lengths()
+        rows = np.repeat(np.arange(m), L)
+        bins = np.zeros(20, np.int64)
+        for l in L:
+            b = 0 if l == 0 else min(19, int(np.floor(np.log2(l))) + 1)
+            bins[b] += 1
+        diff = np.abs(rows - A.col_idx)
+        blocks = {(r // 4, c // 4) for r, c in zip(rows.tolist(), A.col_idx.tolist())}
+        exp = [m, n, A.nnz, *bins.tolist(), int(L.max(initial=0)), int((L * L).sum()),
+               int(diff.max(initial=0)), int(diff.sum()), len(blocks)]
+        assert f.tolist() == exp
+
+
+def test_bsr4_reconstructs_dense():
+    for (m, n, kind) in [(30, 22, "u"), (64, 48, "b"), (5, 3, "u")]:
+        A = synth.block4(m, n, 0.2, 4) if kind == "b" else synth.bernoulli(m, n, 0.1, 4)
+        v = synth.normal(A.nnz, 4, synth.S_VALS)
+        brp, bcol, bv = oracle.csr_to_bsr4(A.row_ptr, A.col_idx, v, n)
+        D = np.zeros(((m + 3) // 4 * 4, (n + 3) // 4 * 4))
+        for I in range(len(brp) - 1):
+            assert np.all(np.diff(bcol[brp[I]:brp[I + 1]]) > 0)
+            for q in range(brp[I], brp[I + 1]):
+                D[4 * I:4 * I + 4, 4 * bcol[q]:4 * bcol[q] + 4] += bv[q]
+        assert np.array_equal(D[:m, :n], dense_of(A.row_ptr, A.col_idx, v, m, n))
+        assert not D[m:, :].any() and not D[:, n:].any()
+
+
+# ---------------------------------------------------------------- mlp
+def _rand_mlp(F, H, P, seed):
+    r = np.random.default_rng(seed)
+    return oracle.MLP(r.normal(size=(H, F)), r.normal(size=H), r.normal(size=(H, H)) / 4,
+                      r.normal(size=H), r.normal(size=(P, H)) / 4, r.normal(size=P))
+
+
+def test_mlp_gradients_match_finite_differences():
+    F, H, P, Bsz = 6, 8, 5, 7
+    net = _rand_mlp(F, H, P, 0)
+    r = np.random.default_rng(1)
+    X, T = r.normal(size=(Bsz, F)), r.normal(size=(Bsz, P))
+    mask = (r.random((Bsz, P)) < 0.7).astype(np.float64)
+    loss, grads = net.loss_grad(X, T, mask)
+    Y = net.forward(X)
+    assert np.isclose(loss, ((Y - T) ** 2 * mask).sum() / (2 * mask.sum()), rtol=1e-13)
+    h = 1e-6
+    for W, g in zip(net.params(), grads):
+        flat, gflat = W.reshape(-1), g.reshape(-1)
+        for idx in range(0, flat.size, max(1, flat.size // 11)):
+            old = flat[idx]
+            flat[idx] = old + h; lp, _ = net.loss_grad(X, T, mask)
+            flat[idx] = old - h; lm, _ = net.loss_grad(X, T, mask)
+            flat[idx] = old
+            assert abs((lp - lm) / (2 * h) - gflat[idx]) <= 1e-6 * max(1.0, abs(gflat).max())
+
+
+def test_adam_first_step_closed_form():
+    """First Adam step: m_hat = g and v_hat = g^2, so w moves by -lr g / (|g| + eps)."""
+    r = np.random.default_rng(2)
+    w0 = r.normal(size=50); g = r.normal(size=50)
+    w = w0.copy(); mom = np.zeros(50); vel = np.zeros(50)
+    oracle.adam(w, g, mom, vel, 1e-3, 0.9, 0.999, 1e-8, 1)
+    assert np.allclose(w, w0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    # a constant gradient keeps m_hat = g, v_hat = g^2 at every step
+    oracle.adam(w, g, mom, vel, 1e-3, 0.9, 0.999, 1e-8, 2)
+    assert np.allclose(w, w0 - 2e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)
