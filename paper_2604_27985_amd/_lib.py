@@ -1,0 +1,94 @@
+"""ctypes loader for libspk.so: the C ABI declared in include/spk.h.
+
+Loading fails loudly when the library is not built: there is no fallback
+path of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspk.so")
+
+# enum spk_dtype
+F32, BF16, F64 = 0, 1, 2
+# enum spk_op
+OP_SPMM, OP_SDDMM, OP_BACKWARD, OP_TRANSPOSE = 0, 1, 2, 3
+# enum spk_variant
+VAR_ROWS, VAR_MERGE, VAR_BSR4 = 0, 1, 2
+
+STATUS = {
+    0: "SPK_OK", -1: "SPK_ERR_NULL", -2: "SPK_ERR_SIZE", -3: "SPK_ERR_DTYPE", -4: "SPK_ERR_LD",
+    -5: "SPK_ERR_WORKSPACE", -6: "SPK_ERR_PLAN", -7: "SPK_ERR_HIP", -8: "SPK_ERR_STRUCTURE",
+    -9: "SPK_ERR_OP", -10: "SPK_ERR_NO_MODEL",
+}
+
+
+class spk_csr(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("vals_dtype", ctypes.c_int32)]
+
+
+class spk_plan(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("lanes", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"spk_plan(variant={self.variant}, lanes={self.lanes}, chunk={self.chunk}, flags={self.flags})"
+
+
+class SpkError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({strerror(status)})")
+
+
+# Every exported symbol with its (argtypes, restype); tests check that each
+# one declared in include/spk.h is exported.
+_P = ctypes.c_void_p
+_I32, _I64, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_CSR_P = ctypes.POINTER(spk_csr)
+_PLAN_P = ctypes.POINTER(spk_plan)
+SIGNATURES = {
+    "spk_workspace_bytes": ([_I32, _CSR_P, _I64, _PLAN_P], _SZ),
+    "spk_strerror": ([_I32], ctypes.c_char_p),
+    "spmm_csr": ([_CSR_P, _P, _I64, _I32, _I64, _P, _I64, _PLAN_P, _P, _SZ, _P], _I32),
+    "sddmm_csr": ([_CSR_P, _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P, _SZ, _P], _I32),
+    "csr_transpose": ([_CSR_P, _P, _P, _P, _P, _SZ, _P], _I32),
+    "spmm_csr_backward": ([_CSR_P, _P, _P, _P, _P, _I64, _P, _I64, _I32, _I64, _P, _I64, _P, _PLAN_P, _P,
+                           _SZ, _P], _I32),
+    "spk_csr_validate": ([_CSR_P, _P, _SZ, _P], _I32),
+}
+
+_lib = None
+
+
+def load():
+    """Load libspk.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().spk_strerror(status).decode()
+    except Exception:  # noqa: BLE001 - only used to decorate an error message
+        return "?"
+
+
+def check(status: int, what: str) -> None:
+    if status != 0:
+        raise SpkError(status, what)

@@ -1,0 +1,243 @@
+"""Python binding of the sparse-product library: argument marshalling only.
+
+Every computation runs in the HIP kernels behind the C ABI (include/spk.h);
+torch supplies device memory and the current stream.  Nothing here computes
+on the host or falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from ._lib import BF16, F32, F64, OP_BACKWARD, OP_SDDMM, OP_SPMM, OP_TRANSPOSE, VAR_MERGE, VAR_ROWS
+
+_DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
+
+
+@dataclass(frozen=True)
+class Plan:
+    """Execution plan (mirrors spk_plan)."""
+
+    variant: int = VAR_ROWS
+    lanes: int = 16
+    chunk: int = 0
+    flags: int = 0
+
+    def c(self) -> _lib.spk_plan:
+        return _lib.spk_plan(self.variant, self.lanes, self.chunk, self.flags)
+
+    def name(self) -> str:
+        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4"}[self.variant]
+        s = f"{v}/l{self.lanes}"
+        if self.chunk:
+            s += f"/c{self.chunk}"
+        if self.flags:
+            s += f"/f{self.flags}"
+        return s
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p | None:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _require_device(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("operands must be device tensors (the library runs on the GPU only)")
+
+
+def _rowmajor(t: torch.Tensor, name: str) -> None:
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1) or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} must be a row-major 2-D tensor with unit column stride")
+
+
+@dataclass
+class CSR:
+    """A CSR matrix in device memory (int32 indices; vals float32/float64 or None)."""
+
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    vals: torch.Tensor | None
+    shape: tuple
+    _transpose: tuple | None = field(default=None, repr=False)
+
+    @property
+    def m(self) -> int:
+        return int(self.shape[0])
+
+    @property
+    def n(self) -> int:
+        return int(self.shape[1])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @classmethod
+    def from_host(cls, A, vals=None, device="cuda", vals_dtype=torch.float32) -> "CSR":
+        """From a host pattern (row_ptr, col_idx numpy arrays) and optional values."""
+        rp = torch.from_numpy(A.row_ptr).to(device)
+        ci = torch.from_numpy(A.col_idx).to(device)
+        v = None if vals is None else torch.as_tensor(vals).to(device=device, dtype=vals_dtype)
+        return cls(rp, ci, v, (A.m, A.n))
+
+    def with_vals(self, vals: torch.Tensor | None) -> "CSR":
+        out = CSR(self.row_ptr, self.col_idx, vals, self.shape)
+        out._transpose = self._transpose
+        return out
+
+    def c(self, vals: torch.Tensor | None = None, use_vals: bool = True) -> _lib.spk_csr:
+        v = self.vals if vals is None else vals
+        if not use_vals:
+            v = None
+        if v is not None:
+            if v.dtype not in (torch.float32, torch.float64) or not v.is_contiguous() or v.numel() != self.nnz:
+                raise ValueError("vals must be a contiguous float32/float64 tensor with nnz entries")
+        for t in (self.row_ptr, self.col_idx):
+            if t.dtype != torch.int32 or not t.is_contiguous():
+                raise ValueError("row_ptr and col_idx must be contiguous int32 tensors")
+        return _lib.spk_csr(self.m, self.n, self.nnz, self.row_ptr.data_ptr(),
+                            self.col_idx.data_ptr() if self.nnz else None,
+                            None if v is None else v.data_ptr(), F64 if (v is not None and v.dtype == torch.float64) else F32)
+
+    def transpose(self):
+        """(at_row_ptr, at_col_idx, perm), computed once per pattern on the GPU."""
+        if self._transpose is None:
+            self._transpose = csr_transpose(self)
+        return self._transpose
+
+
+def workspace_bytes(op: int, A: CSR, K: int, plan: Plan | None = None) -> int:
+    lib = _lib.load()
+    ca = A.c(use_vals=False)
+    cp = plan.c() if plan is not None else None
+    return int(lib.spk_workspace_bytes(op, ctypes.byref(ca), K, ctypes.byref(cp) if cp else None))
+
+
+def _workspace(op, A, K, plan, device):
+    nb = workspace_bytes(op, A, K, plan)
+    if nb == 0:
+        return None, 0
+    return torch.empty(nb, dtype=torch.uint8, device=device), nb
+
+
+def spmm(A: CSR, B: torch.Tensor, plan: Plan | None = None, out: torch.Tensor | None = None,
+         vals: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A B (Eq. 1).  B: [n, K] float32/bfloat16 (float64 with float64 values)."""
+    lib = _lib.load()
+    _require_device(A.row_ptr, B)
+    _rowmajor(B, "B")
+    if B.shape[0] != A.n:
+        raise ValueError(f"B has {B.shape[0]} rows, A has {A.n} columns")
+    K = int(B.shape[1])
+    odt = torch.float64 if B.dtype == torch.float64 else torch.float32
+    C = out if out is not None else torch.empty((A.m, K), dtype=odt, device=B.device)
+    _rowmajor(C, "C")
+    ca = A.c(vals)
+    cp = plan.c() if plan is not None else None
+    ws, nb = (workspace, workspace.numel()) if workspace is not None else _workspace(OP_SPMM, A, K, plan, B.device)
+    st = lib.spmm_csr(ctypes.byref(ca), _ptr(B), B.stride(0), _DT[B.dtype], K, _ptr(C), C.stride(0),
+                      ctypes.byref(cp) if cp else None, _ptr(ws), nb, _stream())
+    _lib.check(st, "spmm_csr")
+    return C
+
+
+def sddmm(A: CSR, U: torch.Tensor, V: torch.Tensor, plan: Plan | None = None, out: torch.Tensor | None = None,
+          vals: torch.Tensor | None = None, pattern: bool = False) -> torch.Tensor:
+    """S[p] = a_p <U[row p], V[col p]> (Eq. 2); pattern=True uses a_p = 1."""
+    lib = _lib.load()
+    _require_device(A.row_ptr, U, V)
+    _rowmajor(U, "U")
+    _rowmajor(V, "V")
+    if U.shape[0] != A.m or V.shape[0] != A.n or U.shape[1] != V.shape[1] or U.dtype != V.dtype:
+        raise ValueError("U must be [m, K] and V [n, K] of one dtype")
+    K = int(U.shape[1])
+    odt = torch.float64 if U.dtype == torch.float64 else torch.float32
+    S = out if out is not None else torch.empty(A.nnz, dtype=odt, device=U.device)
+    ca = A.c(vals, use_vals=not pattern)
+    cp = plan.c() if plan is not None else None
+    st = lib.sddmm_csr(ctypes.byref(ca), _ptr(U), U.stride(0), _ptr(V), V.stride(0), _DT[U.dtype], K, _ptr(S),
+                       ctypes.byref(cp) if cp else None, None, 0, _stream())
+    _lib.check(st, "sddmm_csr")
+    return S
+
+
+def csr_transpose(A: CSR):
+    """Stable transpose of A's pattern: (at_row_ptr [n+1], at_col_idx [nnz], perm [nnz])."""
+    lib = _lib.load()
+    _require_device(A.row_ptr)
+    dev = A.row_ptr.device
+    trp = torch.empty(A.n + 1, dtype=torch.int32, device=dev)
+    tci = torch.empty(A.nnz, dtype=torch.int32, device=dev)
+    perm = torch.empty(A.nnz, dtype=torch.int32, device=dev)
+    ca = A.c(use_vals=False)
+    ws, nb = _workspace(OP_TRANSPOSE, A, 0, None, dev)
+    st = lib.csr_transpose(ctypes.byref(ca), _ptr(trp), _ptr(tci), _ptr(perm), _ptr(ws), nb, _stream())
+    _lib.check(st, "csr_transpose")
+    return trp, tci, perm
+
+
+def spmm_backward(A: CSR, B: torch.Tensor, G: torch.Tensor, need_dB: bool = True, need_dvals: bool = True,
+                  plan: Plan | None = None, vals: torch.Tensor | None = None):
+    """(dB, dvals) of C = A B for dL/dC = G: dB = A^T G, dvals = SDDMM(pattern, G, B)."""
+    lib = _lib.load()
+    _require_device(A.row_ptr, B, G)
+    _rowmajor(B, "B")
+    _rowmajor(G, "G")
+    if B.dtype != G.dtype or B.dtype not in (torch.float32, torch.float64):
+        raise ValueError("B and G must share dtype float32 or float64")
+    K = int(B.shape[1])
+    trp, tci, perm = A.transpose() if need_dB else (None, None, None)
+    dB = torch.empty((A.n, K), dtype=B.dtype, device=B.device) if need_dB else None
+    dv = torch.empty(A.nnz, dtype=B.dtype, device=B.device) if need_dvals else None
+    ca = A.c(vals)
+    cp = plan.c() if plan is not None else None
+    ws, nb = _workspace(OP_BACKWARD, A, K, plan, B.device)
+    st = lib.spmm_csr_backward(ctypes.byref(ca), _ptr(trp), _ptr(tci), _ptr(perm), _ptr(B), B.stride(0), _ptr(G),
+                               G.stride(0), _DT[B.dtype], K, _ptr(dB), dB.stride(0) if dB is not None else K,
+                               _ptr(dv), ctypes.byref(cp) if cp else None, _ptr(ws), nb, _stream())
+    _lib.check(st, "spmm_csr_backward")
+    return dB, dv
+
+
+def validate(A: CSR) -> bool:
+    """Opt-in structural check on the GPU (synchronises the stream)."""
+    lib = _lib.load()
+    ws = torch.empty(16, dtype=torch.uint8, device=A.row_ptr.device)
+    ca = A.c(use_vals=False)
+    st = lib.spk_csr_validate(ctypes.byref(ca), _ptr(ws), 16, _stream())
+    if st == -8:
+        return False
+    _lib.check(st, "spk_csr_validate")
+    return True
+
+
+class SpMMFunction(torch.autograd.Function):
+    """C = A(vals) B with gradients for vals and B from the library's backward."""
+
+    @staticmethod
+    def forward(ctx, vals, B, A, plan):
+        C = spmm(A, B, plan=plan, vals=vals)
+        ctx.save_for_backward(vals, B)
+        ctx.A, ctx.plan = A, plan
+        return C
+
+    @staticmethod
+    def backward(ctx, G):
+        vals, B = ctx.saved_tensors
+        G = G.contiguous()
+        dB, dv = spmm_backward(ctx.A, B, G, need_dB=ctx.needs_input_grad[1], need_dvals=ctx.needs_input_grad[0],
+                               plan=ctx.plan, vals=vals)
+        return dv, dB, None, None
+
+
+def spmm_autograd(A: CSR, vals: torch.Tensor, B: torch.Tensor, plan: Plan | None = None) -> torch.Tensor:
+    """Differentiable SpMM in vals and B."""
+    return SpMMFunction.apply(vals, B, A, plan)

@@ -1,0 +1,255 @@
+// api.hip - the library's C ABI: O(1) argument checks, plan defaults and
+// dispatch to the HIP kernels.  Nothing here allocates device memory.
+#include <stdint.h>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace spk;
+
+namespace {
+
+constexpr int64_t kMaxIndex = 0x7FFFFFFF;
+
+bool valid_lanes(int32_t l) { return l == 4 || l == 8 || l == 16 || l == 32 || l == 64; }
+
+int32_t check_csr(const spk_csr *A) {
+    if (!A) return SPK_ERR_NULL;
+    if (A->m < 0 || A->n < 0 || A->nnz < 0) return SPK_ERR_SIZE;
+    if (A->m > kMaxIndex || A->n > kMaxIndex || A->nnz > kMaxIndex) return SPK_ERR_SIZE;
+    if (A->m > 0 && !A->row_ptr) return SPK_ERR_NULL;
+    if (A->nnz > 0 && !A->col_idx) return SPK_ERR_NULL;
+    if (A->vals && A->vals_dtype != SPK_F32 && A->vals_dtype != SPK_F64) return SPK_ERR_DTYPE;
+    return SPK_OK;
+}
+
+bool aligned(const void *p, size_t bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
+
+size_t elem_size(int32_t dt) { return dt == SPK_F64 ? 8 : dt == SPK_BF16 ? 2 : 4; }
+
+// Dense-operand dtype must match the values' dtype family: F64 with F64,
+// F32 or BF16 operands with F32 (or absent) values.
+int32_t check_dtypes(const spk_csr *A, int32_t dense) {
+    if (dense != SPK_F32 && dense != SPK_BF16 && dense != SPK_F64) return SPK_ERR_DTYPE;
+    if (A->vals) {
+        if ((dense == SPK_F64) != (A->vals_dtype == SPK_F64)) return SPK_ERR_DTYPE;
+    }
+    return SPK_OK;
+}
+
+// Elements per lane of the vector path for a dense dtype.
+int32_t native_vec(int32_t dt) { return dt == SPK_F64 ? 2 : 4; }
+
+struct Resolved {
+    int32_t variant, lanes, vec;
+    int64_t chunk;
+};
+
+int32_t default_spmm_lanes(int64_t K) {
+    int32_t l = 4;
+    while (l < 64 && l * 4 < K) l <<= 1;
+    return l;
+}
+
+int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const void *B, int64_t ldb, const void *C,
+                     int64_t ldc, Resolved &r) {
+    r.variant = plan ? plan->variant : SPK_VAR_ROWS;
+    r.lanes = plan ? plan->lanes : default_spmm_lanes(K);
+    r.chunk = plan && plan->chunk > 0 ? plan->chunk : (4 * K > kDefaultChunk ? 4 * K : kDefaultChunk);
+    if (r.variant != SPK_VAR_ROWS && r.variant != SPK_VAR_MERGE) return SPK_ERR_PLAN;
+    if (!valid_lanes(r.lanes)) return SPK_ERR_PLAN;
+    if (plan && (plan->flags & ~1)) return SPK_ERR_PLAN;
+    if (plan && plan->chunk < 0) return SPK_ERR_PLAN;
+    const bool force_scalar = plan && (plan->flags & 1);
+    int32_t v = native_vec(b_dtype);
+    if (b_dtype == SPK_BF16 && r.lanes * 8 <= K && K % 8 == 0 && ldb % 8 == 0 && aligned(B, 16)) v = 8;
+    const size_t es = elem_size(b_dtype);
+    const size_t cs = b_dtype == SPK_F64 ? 8 : 4;
+    const bool ok = !force_scalar && K % v == 0 && ldb % v == 0 && ldc % (v > 4 ? 4 : v) == 0 &&
+                    aligned(B, es * v) && aligned(C, cs * (v > 4 ? 4 : v));
+    r.vec = ok ? v : 1;
+    if ((K + r.lanes * r.vec - 1) / (r.lanes * r.vec) > 65535) return SPK_ERR_PLAN;
+    return SPK_OK;
+}
+
+int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U, int64_t ldu, const void *V,
+                      int64_t ldv, Resolved &r) {
+    const bool force_scalar = plan && (plan->flags & 1);
+    int32_t v = native_vec(dt);
+    const size_t es = elem_size(dt);
+    const bool ok = !force_scalar && K % v == 0 && ldu % v == 0 && ldv % v == 0 && aligned(U, es * v) &&
+                    aligned(V, es * v);
+    r.vec = ok ? v : 1;
+    r.variant = SPK_VAR_ROWS;
+    r.chunk = plan && plan->chunk > 0 ? plan->chunk : kDefaultChunk;
+    if (plan) {
+        if (plan->flags & ~1) return SPK_ERR_PLAN;
+        if (plan->chunk < 0) return SPK_ERR_PLAN;
+        if (!valid_lanes(plan->lanes)) return SPK_ERR_PLAN;
+        r.lanes = plan->lanes;
+    } else {
+        r.lanes = 8;
+    }
+    // At most 8 register slices of lanes*vec columns; widen the group if needed.
+    if (!plan) {
+        while (r.lanes < 64 && (K + r.lanes * r.vec - 1) / (r.lanes * r.vec) > 8) r.lanes <<= 1;
+    }
+    if ((K + r.lanes * r.vec - 1) / (r.lanes * r.vec) > 8) return SPK_ERR_PLAN;
+    return SPK_OK;
+}
+
+int32_t check_ws(size_t need, const void *ws, size_t ws_bytes) {
+    if (need == 0) return SPK_OK;
+    if (!ws || ws_bytes < need) return SPK_ERR_WORKSPACE;
+    return SPK_OK;
+}
+
+int32_t hip_status(hipError_t e) { return e == hipSuccess ? SPK_OK : SPK_ERR_HIP; }
+
+size_t spmm_ws(int64_t m, int64_t nnz, int64_t K, int32_t dt, const Resolved &r) {
+    if (r.variant != SPK_VAR_MERGE || m == 0 || K == 0) return 0;
+    return merge_layout(m, nnz, K, r.chunk, dt == SPK_F64 ? 8 : 4).total;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spk_strerror(int32_t status) {
+    switch (status) {
+    case SPK_OK: return "ok";
+    case SPK_ERR_NULL: return "a required pointer is NULL";
+    case SPK_ERR_SIZE: return "size out of range";
+    case SPK_ERR_DTYPE: return "unsupported dtype combination";
+    case SPK_ERR_LD: return "leading dimension smaller than K";
+    case SPK_ERR_WORKSPACE: return "workspace missing or too small";
+    case SPK_ERR_PLAN: return "plan invalid for this call";
+    case SPK_ERR_HIP: return "HIP runtime error";
+    case SPK_ERR_STRUCTURE: return "CSR is not canonical";
+    case SPK_ERR_OP: return "unknown op";
+    case SPK_ERR_NO_MODEL: return "no selector model loaded";
+    default: return "unknown status";
+    }
+}
+
+size_t spk_workspace_bytes(int32_t op, const spk_csr *A, int64_t K, const spk_plan *plan) {
+    if (check_csr(A) != SPK_OK || K < 0) return 0;
+    Resolved r;
+    switch (op) {
+    case SPK_OP_SPMM:
+        // Alignment does not change the size: resolve with aligned stand-ins.
+        if (resolve_spmm(plan, K, SPK_F64, nullptr, K, nullptr, K, r) != SPK_OK) return 0;
+        return spmm_ws(A->m, A->nnz, K, SPK_F64, r);
+    case SPK_OP_SDDMM: return 0;
+    case SPK_OP_TRANSPOSE: return transpose_ws_bytes(A->m, A->n, A->nnz);
+    case SPK_OP_BACKWARD:
+        if (resolve_spmm(plan, K, SPK_F64, nullptr, K, nullptr, K, r) != SPK_OK) return 0;
+        return spmm_ws(A->n, A->nnz, K, SPK_F64, r);
+    default: return 0;
+    }
+}
+
+int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C, int64_t ldc,
+                 const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if ((st = check_dtypes(A, b_dtype))) return st;
+    if (A->m == 0 || K == 0) return SPK_OK;
+    if (!C || (A->nnz > 0 && !B)) return SPK_ERR_NULL;
+    if (ldc < K || (A->nnz > 0 && ldb < K)) return SPK_ERR_LD;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t out_dt = b_dtype == SPK_F64 ? SPK_F64 : SPK_F32;
+    if (A->nnz == 0) return hip_status(zero_fill(C, A->m, K, ldc, out_dt, s));
+    Resolved r;
+    if ((st = resolve_spmm(plan, K, b_dtype, B, ldb, C, ldc, r))) return st;
+    const size_t need = spmm_ws(A->m, A->nnz, K, b_dtype, r);
+    if ((st = check_ws(need, ws, ws_bytes))) return st;
+    SpmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, nullptr, B, ldb, b_dtype, C, ldc,
+               r.variant, r.lanes, r.vec, r.chunk, ws};
+    return hip_status(spmm_launch(a, s));
+}
+
+int32_t sddmm_csr(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv, int32_t uv_dtype,
+                  int64_t K, void *S, const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+    (void)ws;
+    (void)ws_bytes;
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if ((st = check_dtypes(A, uv_dtype))) return st;
+    if (A->nnz == 0) return SPK_OK;
+    if (!S || !U || !V) return SPK_ERR_NULL;
+    if (K > 0 && (ldu < K || ldv < K)) return SPK_ERR_LD;
+    Resolved r;
+    if ((st = resolve_sddmm(plan, K, uv_dtype, U, ldu, V, ldv, r))) return st;
+    SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, U, ldu, V, ldv, uv_dtype, S, r.lanes, r.vec,
+                r.chunk};
+    return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
+}
+
+int32_t csr_transpose(const spk_csr *A, int32_t *at_row_ptr, int32_t *at_col_idx, int32_t *perm, void *ws,
+                      size_t ws_bytes, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (!at_row_ptr || (A->nnz > 0 && (!at_col_idx || !perm))) return SPK_ERR_NULL;
+    const size_t need = transpose_ws_bytes(A->m, A->n, A->nnz);
+    if ((st = check_ws(need, ws, ws_bytes))) return st;
+    return hip_status(transpose_launch(A->m, A->n, A->nnz, A->row_ptr, A->col_idx, at_row_ptr, at_col_idx, perm, ws,
+                                       static_cast<hipStream_t>(stream)));
+}
+
+int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int32_t *at_col_idx, const int32_t *perm,
+                          const void *B, int64_t ldb, const void *G, int64_t ldg, int32_t dtype, int64_t K, void *dB,
+                          int64_t lddb, void *dvals, const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (dtype != SPK_F32 && dtype != SPK_F64) return SPK_ERR_DTYPE;
+    if ((st = check_dtypes(A, dtype))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dB && A->n > 0 && K > 0) {
+        if (!G && A->nnz > 0) return SPK_ERR_NULL;
+        if (!at_row_ptr || (A->nnz > 0 && (!at_col_idx || !perm))) return SPK_ERR_NULL;
+        if (lddb < K || (A->nnz > 0 && ldg < K)) return SPK_ERR_LD;
+        if (A->nnz == 0) {
+            if ((st = hip_status(zero_fill(dB, A->n, K, lddb, dtype, s)))) return st;
+        } else {
+            Resolved r;
+            if ((st = resolve_spmm(plan, K, dtype, G, ldg, dB, lddb, r))) return st;
+            const size_t need = spmm_ws(A->n, A->nnz, K, dtype, r);
+            if ((st = check_ws(need, ws, ws_bytes))) return st;
+            SpmmArgs a{A->n, A->m, A->nnz, K, at_row_ptr, at_col_idx, A->vals, perm, G, ldg, dtype, dB, lddb,
+                       r.variant, r.lanes, r.vec, r.chunk, ws};
+            if ((st = hip_status(spmm_launch(a, s)))) return st;
+        }
+    }
+    if (dvals && A->nnz > 0) {
+        if (!G || !B) return SPK_ERR_NULL;
+        if (K > 0 && (ldg < K || ldb < K)) return SPK_ERR_LD;
+        spk_csr P = *A;
+        P.vals = nullptr;
+        Resolved r;
+        if ((st = resolve_sddmm(nullptr, K, dtype, G, ldg, B, ldb, r))) return st;
+        SddmmArgs a{P.m, P.n, P.nnz, K, P.row_ptr, P.col_idx, nullptr, G, ldg, B, ldb, dtype, dvals, r.lanes, r.vec,
+                    r.chunk};
+        if ((st = hip_status(sddmm_launch(a, s)))) return st;
+    }
+    return SPK_OK;
+}
+
+int32_t spk_csr_validate(const spk_csr *A, void *ws, size_t ws_bytes, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (!ws || ws_bytes < 16) return SPK_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t *flag = static_cast<int32_t *>(ws);
+    if ((st = hip_status(validate_launch(A->m, A->n, A->nnz, A->row_ptr, A->col_idx, flag, s)))) return st;
+    int32_t host = 0;
+    if (hipMemcpyAsync(&host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return SPK_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPK_ERR_HIP;
+    if (A->m == 0 && A->nnz != 0) return SPK_ERR_STRUCTURE;
+    return host == 0 ? SPK_OK : SPK_ERR_STRUCTURE;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// internal.h - host-side launch descriptors shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/spk.h"
+
+namespace spk {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct SpmmArgs {
+    int64_t m, n, nnz, K;
+    const int32_t *rp, *ci;
+    const void *vals;      // F32 or F64 (nullable: all ones)
+    const int32_t *vperm;  // nullable: value of entry q is vals[vperm[q]]
+    const void *B;
+    int64_t ldb;
+    int32_t b_dtype;
+    void *C;
+    int64_t ldc;
+    int32_t variant, lanes, vec;
+    int64_t chunk;
+    void *ws;
+};
+
+struct SddmmArgs {
+    int64_t m, n, nnz, K;
+    const int32_t *rp, *ci;
+    const void *vals;  // nullable
+    const void *U;
+    int64_t ldu;
+    const void *V;
+    int64_t ldv;
+    int32_t uv_dtype;
+    void *S;
+    int32_t lanes, vec;
+    int64_t chunk;
+};
+
+// Workspace of the merge-path SpMM: share start rows, carry rows, carry sums.
+struct MergeLayout {
+    int64_t items, ngroups;
+    size_t part_off, row_off, val_off, total;
+};
+
+inline MergeLayout merge_layout(int64_t m, int64_t nnz, int64_t K, int64_t chunk, size_t acc_size) {
+    MergeLayout L;
+    L.items = chunk;
+    const int64_t total = m + nnz;
+    L.ngroups = total > 0 ? (total + chunk - 1) / chunk : 0;
+    L.part_off = 0;
+    L.row_off = align_up(sizeof(int32_t) * static_cast<size_t>(L.ngroups + 1));
+    L.val_off = L.row_off + align_up(sizeof(int32_t) * static_cast<size_t>(L.ngroups));
+    L.total = L.val_off + align_up(acc_size * static_cast<size_t>(L.ngroups) * static_cast<size_t>(K));
+    return L;
+}
+
+hipError_t spmm_launch(const SpmmArgs &a, hipStream_t s);
+hipError_t sddmm_launch(const SddmmArgs &a, hipStream_t s);
+hipError_t zero_fill(void *C, int64_t m, int64_t K, int64_t ld, int32_t dtype, hipStream_t s);
+
+// CSR transpose (transpose.hip).
+size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz);
+hipError_t transpose_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                            int32_t *trp, int32_t *tci, int32_t *perm, void *ws, hipStream_t s);
+
+// Structural validation (transpose.hip): writes 0 to *flag_dev when A is
+// canonical, a positive code otherwise.
+hipError_t validate_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                           int32_t *flag_dev, hipStream_t s);
+
+}  // namespace spk

@@ -1,0 +1,277 @@
+// spmm.hip - SpMM C = A B (Section II-A, Eq. (1)) for gfx950.
+//
+// The dense operand stays in HBM and the sparse matrix is streamed: each
+// stored entry (col, val) of a row is read once, coalesced, and the matching
+// row of B is gathered.  This keeps the paper's principle of streaming A
+// past a stationary dense operand (Section III-A), mapped onto wavefronts
+// instead of a PE grid:
+//
+//   - A group of LANES lanes (4..64, a divisor of the 64-lane wavefront)
+//     owns one output row and one slice of LANES*VW columns of C; each lane
+//     keeps VW accumulators in registers.
+//   - The group loads LANES entries of its row at a time (one per lane, so
+//     col_idx/vals reads are coalesced), then broadcasts each entry to the
+//     group with ds_bpermute and gathers the B row slice with one 8/16-byte
+//     load per lane.  Eight gathers are issued before their FMAs so several
+//     B rows are in flight per wave.
+//   - Row-split (ROWS): group g takes row g.  Merge-path (MERGE): group g takes
+//     an equal share of the (row ends + entries) sequence, so a row of a
+//     million entries spreads over thousands of groups; a group's partial sum
+//     of a row that continues past its share is written as a carry, and a
+//     fix-up kernel adds the carries of each row in group order.  No float
+//     atomics: results are bitwise reproducible run to run.
+//
+// The backward's A^T G runs through the same kernels on the transpose's CSR,
+// with each value read through perm (vals[perm[q]]).
+#include "common.h"
+#include "internal.h"
+
+namespace spk {
+
+// acc += sum_{p in [a, b)} val(p) * B[col(p), k0 .. k0+VW).
+// a, b are uniform over the LANES-lane group; lane `lig` handles columns
+// k0 .. k0+VW-1 (inactive for the arithmetic when !kvalid, but it still
+// loads and shares its entry).
+template <typename TB, typename TV, int VW, int LANES>
+__device__ __forceinline__ void accumulate_entries(int64_t a, int64_t b, const int32_t *__restrict__ ci,
+                                                   const TV *__restrict__ vals,
+                                                   const int32_t *__restrict__ vperm,
+                                                   const TB *__restrict__ B, int64_t ldb, int k0,
+                                                   bool kvalid, int gbase, int lig,
+                                                   typename acc_of<TB>::type *acc) {
+    using A = typename acc_of<TB>::type;
+    constexpr int U = LANES < 8 ? LANES : 8;
+    for (int64_t p0 = a; p0 < b; p0 += LANES) {
+        const int64_t p = p0 + lig;
+        int c = 0;
+        A v = A(0);
+        if (p < b) {
+            c = ci[p];
+            if (vals) v = static_cast<A>(vals[vperm ? static_cast<int64_t>(vperm[p]) : p]);
+            else v = A(1);
+        }
+        const int cnt = static_cast<int>(b - p0 < LANES ? b - p0 : LANES);
+        for (int t = 0; t < cnt; t += U) {
+            int cc[U];
+            A vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cc[u] = lane_read(c, gbase + t + u);
+                vv[u] = lane_read(v, gbase + t + u);
+            }
+            A bv[U][VW];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (kvalid && t + u < cnt) {
+                    vec_load<TB, VW>::run(B + static_cast<int64_t>(cc[u]) * ldb + k0, bv[u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) bv[u][e] = A(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < VW; ++e) acc[e] = fma(vv[u], bv[u][e], acc[e]);
+        }
+    }
+}
+
+template <typename TB, typename TV, int VW, int LANES>
+__global__ __launch_bounds__(kBlock) void spmm_rows_kernel(int64_t m, int K, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const TV *__restrict__ vals,
+                                                           const int32_t *__restrict__ vperm,
+                                                           const TB *__restrict__ B, int64_t ldb,
+                                                           typename acc_of<TB>::type *__restrict__ C,
+                                                           int64_t ldc) {
+    using A = typename acc_of<TB>::type;
+    constexpr int GPB = kBlock / LANES;
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = (threadIdx.x & (kWave - 1)) & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row = blk * GPB + threadIdx.x / LANES;
+    if (row >= m) return;  // the whole group leaves together
+    const int k0 = blockIdx.y * (LANES * VW) + lig * VW;
+    const bool kvalid = k0 < K;
+    A acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = A(0);
+    accumulate_entries<TB, TV, VW, LANES>(rp[row], rp[row + 1], ci, vals, vperm, B, ldb, k0, kvalid,
+                                          gbase, lig, acc);
+    if (kvalid) vec_store<A, VW>::run(C + row * ldc + k0, acc);
+}
+
+// Start row of every merge-path share: part[g] = largest i in
+// [max(0, d - nnz), min(d, m)] with row_ptr[i] + i <= d, d = min(g*items, m+nnz).
+// The walk consumes an entry while the current row still has one and a row
+// end otherwise, so after d steps it has finished exactly part[g] rows and
+// consumed d - part[g] entries.
+__global__ void merge_partition_kernel(int64_t m, int64_t nnz, const int32_t *__restrict__ rp,
+                                       int64_t items, int64_t ngroups, int32_t *__restrict__ part) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g > ngroups) return;
+    const int64_t total = m + nnz;
+    const int64_t d = g * items < total ? g * items : total;
+    const int64_t lo = d - nnz > 0 ? d - nnz : 0;
+    const int64_t hi = d < m ? d : m;
+    part[g] = static_cast<int32_t>(last_at_most(lo, hi, d, [&](int64_t i) { return static_cast<int64_t>(rp[i]) + i; }));
+}
+
+template <typename TB, typename TV, int VW, int LANES>
+__global__ __launch_bounds__(kBlock) void spmm_merge_kernel(
+    int64_t m, int64_t nnz, int K, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const TV *__restrict__ vals, const int32_t *__restrict__ vperm, const TB *__restrict__ B, int64_t ldb,
+    typename acc_of<TB>::type *__restrict__ C, int64_t ldc, const int32_t *__restrict__ part, int64_t items,
+    int64_t ngroups, int32_t *__restrict__ carry_row, typename acc_of<TB>::type *__restrict__ carry_val) {
+    using A = typename acc_of<TB>::type;
+    constexpr int GPB = kBlock / LANES;
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = (threadIdx.x & (kWave - 1)) & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t g = blk * GPB + threadIdx.x / LANES;
+    if (g >= ngroups) return;
+    const int k0 = blockIdx.y * (LANES * VW) + lig * VW;
+    const bool kvalid = k0 < K;
+    const int64_t total = m + nnz;
+    const int64_t d0 = g * items;
+    const int64_t d1 = d0 + items < total ? d0 + items : total;
+    const int64_t i0 = part[g], i1 = part[g + 1];
+    const int64_t j1 = d1 - i1;
+    int64_t j = d0 - i0;
+    A acc[VW];
+    for (int64_t r = i0; r < i1; ++r) {  // rows whose end lies in this share
+        const int64_t e = rp[r + 1];
+#pragma unroll
+        for (int q = 0; q < VW; ++q) acc[q] = A(0);
+        accumulate_entries<TB, TV, VW, LANES>(j, e, ci, vals, vperm, B, ldb, k0, kvalid, gbase, lig, acc);
+        if (kvalid) vec_store<A, VW>::run(C + r * ldc + k0, acc);
+        j = e;
+    }
+    // Entries of row i1 inside this share: carried to the fix-up.
+    const bool has_carry = j < j1;
+    if (has_carry) {
+#pragma unroll
+        for (int q = 0; q < VW; ++q) acc[q] = A(0);
+        accumulate_entries<TB, TV, VW, LANES>(j, j1, ci, vals, vperm, B, ldb, k0, kvalid, gbase, lig, acc);
+        if (kvalid) vec_store<A, VW>::run(carry_val + g * K + k0, acc);
+    }
+    if (lig == 0 && blockIdx.y == 0) carry_row[g] = has_carry ? static_cast<int32_t>(i1) : -1;
+}
+
+// One wave per share: the first share of each run of shares carrying the
+// same row adds the run's carries, in share order, to that row of C.
+template <typename A>
+__global__ __launch_bounds__(kBlock) void merge_fixup_kernel(int64_t ngroups, int K, const int32_t *__restrict__ carry_row,
+                                                             const A *__restrict__ carry_val, A *__restrict__ C,
+                                                             int64_t ldc) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    if (g >= ngroups) return;
+    const int32_t r = carry_row[g];
+    if (r < 0 || (g > 0 && carry_row[g - 1] == r)) return;
+    int64_t g_end = g + 1;
+    while (g_end < ngroups && carry_row[g_end] == r) ++g_end;
+    for (int k = threadIdx.x & (kWave - 1); k < K; k += kWave) {
+        A s = A(0);
+        for (int64_t h = g; h < g_end; ++h) s += carry_val[h * K + k];
+        C[static_cast<int64_t>(r) * ldc + k] += s;
+    }
+}
+
+// -------------------------------------------------------------------------
+// Host launchers
+// -------------------------------------------------------------------------
+template <typename TB, typename TV, int VW, int LANES>
+static hipError_t launch_rows(const SpmmArgs &a, hipStream_t s) {
+    constexpr int GPB = kBlock / LANES;
+    const int64_t nb = (a.m + GPB - 1) / GPB;
+    const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
+    if (nb > 0x7FFFFFFF || ktiles > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((spmm_rows_kernel<TB, TV, VW, LANES>), dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)),
+                       dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.rp, a.ci, static_cast<const TV *>(a.vals),
+                       a.vperm, static_cast<const TB *>(a.B), a.ldb,
+                       static_cast<typename acc_of<TB>::type *>(a.C), a.ldc);
+    return hipGetLastError();
+}
+
+template <typename TB, typename TV, int VW, int LANES>
+static hipError_t launch_merge(const SpmmArgs &a, hipStream_t s) {
+    using A = typename acc_of<TB>::type;
+    constexpr int GPB = kBlock / LANES;
+    const MergeLayout L = merge_layout(a.m, a.nnz, a.K, a.chunk, sizeof(A));
+    char *ws = static_cast<char *>(a.ws);
+    int32_t *part = reinterpret_cast<int32_t *>(ws + L.part_off);
+    int32_t *carry_row = reinterpret_cast<int32_t *>(ws + L.row_off);
+    A *carry_val = reinterpret_cast<A *>(ws + L.val_off);
+    const int64_t pthreads = L.ngroups + 1;
+    hipLaunchKernelGGL(merge_partition_kernel, dim3(static_cast<unsigned>((pthreads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       a.m, a.nnz, a.rp, L.items, L.ngroups, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nb = (L.ngroups + GPB - 1) / GPB;
+    const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
+    if (nb > 0x7FFFFFFF || ktiles > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((spmm_merge_kernel<TB, TV, VW, LANES>), dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)),
+                       dim3(kBlock), 0, s, a.m, a.nnz, static_cast<int>(a.K), a.rp, a.ci,
+                       static_cast<const TV *>(a.vals), a.vperm, static_cast<const TB *>(a.B), a.ldb,
+                       static_cast<A *>(a.C), a.ldc, part, L.items, L.ngroups, carry_row, carry_val);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t fb = (L.ngroups + (kBlock / kWave) - 1) / (kBlock / kWave);
+    hipLaunchKernelGGL((merge_fixup_kernel<A>), dim3(static_cast<unsigned>(fb)), dim3(kBlock), 0, s, L.ngroups,
+                       static_cast<int>(a.K), carry_row, carry_val, static_cast<A *>(a.C), a.ldc);
+    return hipGetLastError();
+}
+
+template <typename TB, typename TV, int VW>
+static hipError_t dispatch_lanes(const SpmmArgs &a, hipStream_t s) {
+    const bool merge = a.variant == SPK_VAR_MERGE;
+    switch (a.lanes) {
+#define SPK_CASE(L) \
+    case L: return merge ? launch_merge<TB, TV, VW, L>(a, s) : launch_rows<TB, TV, VW, L>(a, s);
+        SPK_CASE(4)
+        SPK_CASE(8)
+        SPK_CASE(16)
+        SPK_CASE(32)
+        SPK_CASE(64)
+#undef SPK_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t spmm_launch(const SpmmArgs &a, hipStream_t s) {
+    switch (a.b_dtype) {
+    case SPK_F32:
+        return a.vec > 1 ? dispatch_lanes<float, float, 4>(a, s) : dispatch_lanes<float, float, 1>(a, s);
+    case SPK_BF16:
+        if (a.vec == 8) return dispatch_lanes<bf16, float, 8>(a, s);
+        return a.vec > 1 ? dispatch_lanes<bf16, float, 4>(a, s) : dispatch_lanes<bf16, float, 1>(a, s);
+    case SPK_F64:
+        return a.vec > 1 ? dispatch_lanes<double, double, 2>(a, s) : dispatch_lanes<double, double, 1>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Zero-fill of an m x K block with leading dimension ld (nnz = 0 case).
+template <typename A>
+__global__ void fill_zero_kernel(int64_t m, int64_t K, A *__restrict__ C, int64_t ld) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= m * K) return;
+    C[(idx / K) * ld + idx % K] = A(0);
+}
+
+hipError_t zero_fill(void *C, int64_t m, int64_t K, int64_t ld, int32_t dtype, hipStream_t s) {
+    const int64_t total = m * K;
+    if (total == 0) return hipSuccess;
+    const int64_t nb = (total + kBlock - 1) / kBlock;
+    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    if (dtype == SPK_F64)
+        hipLaunchKernelGGL((fill_zero_kernel<double>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, K,
+                           static_cast<double *>(C), ld);
+    else
+        hipLaunchKernelGGL((fill_zero_kernel<float>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, K,
+                           static_cast<float *>(C), ld);
+    return hipGetLastError();
+}
+
+}  // namespace spk

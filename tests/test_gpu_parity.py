@@ -1,0 +1,224 @@
+"""Parity of the HIP kernels with the FP64 oracle (GPU).
+
+Every product is called through the C ABI (via the binding) and compared
+element by element with the oracle on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_27985_amd import synth
+from spk_testutil import TOL_F32, TOL_F64, assert_within, host_csr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SPMM_PLANS = [(v, l) for v in (0, 1) for l in (4, 8, 16, 32, 64)]
+
+
+@pytest.fixture(scope="module")
+def spk():
+    import paper_2604_27985_amd as spk
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return spk
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t if dtype is None else t.to(dtype)
+
+
+def problem(m, n, d, K, seed, kind="uniform"):
+    if kind == "uniform":
+        A = synth.bernoulli(m, n, d, seed)
+    elif kind == "powerlaw":
+        A = synth.powerlaw(n, d, 2.1, seed)
+    elif kind == "banded":
+        A = synth.bernoulli(m, n, d, seed, band=64)
+    else:
+        A = synth.block4(m, n, d, seed)
+    v = synth.normal(A.nnz, seed, synth.S_VALS)
+    B = synth.normal((A.n, K), seed, synth.S_B)
+    U = synth.normal((A.m, K), seed, synth.S_U)
+    return A, v, B, U
+
+
+def run_spmm(spk, A, v, B, plan=None, pattern=False):
+    dA = spk.CSR.from_host(A, None if pattern else v)
+    C = spk.spmm(dA, dev(B), plan=plan)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+# ------------------------------------------------------------------ SpMM
+@pytest.mark.parametrize("variant,lanes", SPMM_PLANS)
+def test_spmm_config1_every_plan(spk, variant, lanes):
+    """1024 x 1024 at 90% sparsity, K = 64, seed 0: every row-split and merge plan."""
+    A, v, B, _ = problem(1024, 1024, 0.1, 64, 0)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    for flags in (0, 1):
+        plan = spk.Plan(variant, lanes, 0 if variant == 0 else 96, flags)
+        C = run_spmm(spk, A, v, B, plan)
+        assert_within(C, C64, M, TOL_F32, f"spmm {plan.name()}")
+
+
+@pytest.mark.parametrize("m,n,d,K", [(1000, 777, 0.02, 1), (333, 1000, 0.05, 3), (517, 517, 0.03, 36),
+                                     (2049, 1500, 0.01, 100), (700, 900, 0.02, 128), (300, 4000, 0.01, 256),
+                                     (257, 513, 0.05, 300), (5, 3, 0.5, 7)])
+def test_spmm_ragged_shapes(spk, m, n, d, K):
+    A, v, B, _ = problem(m, n, d, K, 3)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    for plan in (None, spk.Plan(1, 8, 64), spk.Plan(0, 64)):
+        C = run_spmm(spk, A, v, B, plan)
+        assert_within(C, C64, M, TOL_F32, f"spmm {m}x{n} K={K} {plan}")
+
+
+def test_spmm_pattern_mode_and_empty_rows(spk):
+    # rows 0, 3, 4 and the last are empty
+    A = host_csr(6, 9, [[], [0, 4, 8], [2], [], [], [1, 2, 3, 4, 5, 6, 7]])
+    B = synth.normal((9, 20), 1, synth.S_B)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, None, B)
+    for plan in (None, spk.Plan(1, 4, 3), spk.Plan(1, 8, 1), spk.Plan(0, 4)):
+        C = run_spmm(spk, A, None, B, plan, pattern=True)
+        assert_within(C, C64, M, TOL_F32, "pattern")
+        assert not C[[0, 3, 4]].any()
+
+
+def test_spmm_special_cases_bit_exact(spk):
+    """One product per output is a single rounding: identity, permutation, diagonal."""
+    n, K = 3000, 64
+    B = synth.normal((n, K), 2, synth.S_B)
+    eye = synth.HostCSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32))
+    pi = np.random.default_rng(0).permutation(n).astype(np.int32)
+    perm = synth.HostCSR(n, n, np.arange(n + 1, dtype=np.int32), pi)
+    dvals = synth.normal(n, 2, synth.S_VALS)
+    for plan in (None, spk.Plan(1, 16, 7), spk.Plan(0, 4, 0, 1)):
+        assert np.array_equal(run_spmm(spk, eye, np.ones(n, np.float32), B, plan), B)
+        assert np.array_equal(run_spmm(spk, perm, None, B, plan, pattern=True), B[pi])
+        C = run_spmm(spk, eye, dvals, B, plan)
+        assert np.array_equal(C, (dvals[:, None] * B).astype(np.float32))
+
+
+def test_spmm_nnz_zero_and_noops(spk):
+    A = synth.HostCSR(10, 7, np.zeros(11, np.int32), np.zeros(0, np.int32))
+    dA = spk.CSR.from_host(A, np.zeros(0, np.float32))
+    C = torch.full((10, 5), 7.0, device="cuda")
+    spk.spmm(dA, torch.randn(7, 5, device="cuda"), out=C)
+    assert not C.cpu().numpy().any()
+    # m = 0 and K = 0 are no-ops
+    E = synth.HostCSR(0, 7, np.zeros(1, np.int32), np.zeros(0, np.int32))
+    out = spk.spmm(spk.CSR.from_host(E, np.zeros(0, np.float32)), torch.randn(7, 5, device="cuda"))
+    assert out.shape == (0, 5)
+    A2, v2, _, _ = problem(20, 20, 0.2, 1, 1)
+    out = spk.spmm(spk.CSR.from_host(A2, v2), torch.zeros(20, 0, device="cuda"))
+    assert out.shape == (20, 0)
+
+
+def test_spmm_strided_operands(spk):
+    """Leading dimensions larger than K (views of wider tensors)."""
+    A, v, B, _ = problem(400, 300, 0.05, 40, 4)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    dA = spk.CSR.from_host(A, v)
+    Bw = torch.zeros(300, 52, device="cuda")
+    Bw[:, :40] = dev(B)
+    Cw = torch.full((400, 44), 9.0, device="cuda")
+    spk.spmm(dA, Bw[:, :40], out=Cw[:, :40])
+    torch.cuda.synchronize()
+    out = Cw.cpu().numpy()
+    assert_within(out[:, :40], C64, M, TOL_F32, "strided")
+    assert (out[:, 40:] == 9.0).all()
+
+
+@pytest.mark.parametrize("kind,n,d", [("powerlaw", 20000, 16), ("banded", 5000, 0.2), ("block4", 4096, 0.01)])
+def test_spmm_structured_patterns(spk, kind, n, d):
+    A, v, B, _ = problem(n, n, d, 64, 5, kind)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    for plan in (None, spk.Plan(1, 16), spk.Plan(1, 64, 256), spk.Plan(0, 8)):
+        assert_within(run_spmm(spk, A, v, B, plan), C64, M, TOL_F32, f"{kind} {plan}")
+
+
+def test_spmm_deterministic(spk):
+    A, v, B, _ = problem(3000, 3000, 16, 128, 6, "powerlaw")
+    for plan in (spk.Plan(0, 32), spk.Plan(1, 32, 100)):
+        c1 = run_spmm(spk, A, v, B, plan)
+        c2 = run_spmm(spk, A, v, B, plan)
+        assert np.array_equal(c1.view(np.uint32), c2.view(np.uint32))
+
+
+# ------------------------------------------------------------------ SDDMM
+def run_sddmm(spk, A, v, U, V, plan=None, pattern=False):
+    dA = spk.CSR.from_host(A, v)
+    S = spk.sddmm(dA, dev(U), dev(V), plan=plan, pattern=pattern)
+    torch.cuda.synchronize()
+    return S.cpu().numpy()
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
+def test_sddmm_config1_every_plan(spk, lanes):
+    """1024 x 1024 at 90% sparsity, U, V 1024 x 64, seed 0."""
+    A, v, V, U = problem(1024, 1024, 0.1, 64, 0)
+    S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    for chunk in (0, 5, 1000):
+        for flags in (0, 1):
+            S = run_sddmm(spk, A, v, U, V, spk.Plan(0, lanes, chunk, flags))
+            assert_within(S, S64, M, TOL_F32, f"sddmm lanes={lanes} chunk={chunk} flags={flags}")
+
+
+@pytest.mark.parametrize("m,n,d,K", [(1000, 777, 0.02, 1), (333, 1000, 0.05, 3), (517, 517, 0.03, 36),
+                                     (700, 900, 0.02, 128), (300, 4000, 0.01, 256), (257, 513, 0.05, 300)])
+def test_sddmm_ragged_and_pattern(spk, m, n, d, K):
+    A, v, V, U = problem(m, n, d, K, 7)
+    S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    P64, PM = oracle.sddmm(A.row_ptr, A.col_idx, None, U, V)
+    assert_within(run_sddmm(spk, A, v, U, V), S64, M, TOL_F32, "sddmm")
+    assert_within(run_sddmm(spk, A, v, U, V, pattern=True), P64, PM, TOL_F32, "sddmm pattern")
+
+
+def test_sddmm_powerlaw_and_empty_rows(spk):
+    A, v, V, U = problem(20000, 20000, 16, 64, 8, "powerlaw")
+    S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    for plan in (None, spk.Plan(0, 16, 64), spk.Plan(0, 4, 1024)):
+        assert_within(run_sddmm(spk, A, v, U, V, plan), S64, M, TOL_F32, f"powerlaw {plan}")
+    E = host_csr(7, 5, [[], [], [1, 3], [], [0, 1, 2, 3, 4], [], [4]])
+    Ue = synth.normal((7, 12), 1, synth.S_U)
+    Ve = synth.normal((5, 12), 1, synth.S_V)
+    ve = synth.normal(E.nnz, 1, synth.S_VALS)
+    S64, M = oracle.sddmm(E.row_ptr, E.col_idx, ve, Ue, Ve)
+    for plan in (None, spk.Plan(0, 4, 1), spk.Plan(0, 4, 3)):
+        assert_within(run_sddmm(spk, E, ve, Ue, Ve, plan), S64, M, TOL_F32, "empty rows")
+
+
+def test_sddmm_deterministic(spk):
+    A, v, V, U = problem(3000, 3000, 0.02, 64, 9)
+    s1 = run_sddmm(spk, A, v, U, V)
+    s2 = run_sddmm(spk, A, v, U, V)
+    assert np.array_equal(s1.view(np.uint32), s2.view(np.uint32))
+
+
+# ------------------------------------------------------------------ adjoint
+def test_adjoint_identity_on_gpu(spk):
+    """<SpMM(A, B), G> = <vals, SDDMM(pattern, G, B)> within the summed bounds."""
+    A, v, B, _ = problem(2000, 1800, 0.01, 32, 10)
+    G = synth.normal((2000, 32), 10, synth.S_G)
+    C = run_spmm(spk, A, v, B).astype(np.float64)
+    S = run_sddmm(spk, A, v, G, B, pattern=True).astype(np.float64)
+    lhs, rhs = float((C * G).sum()), float((v * S).sum())
+    _, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    _, PM = oracle.sddmm(A.row_ptr, A.col_idx, None, G, B)
+    scale = float((M * np.abs(G)).sum() + (np.abs(v) * PM).sum())
+    assert abs(lhs - rhs) <= 2 * TOL_F32 * scale
+
+
+# ------------------------------------------------------------------ FP64
+def test_f64_kernels_match_oracle(spk):
+    A, v, B, U = problem(900, 700, 0.03, 24, 11)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    dA = spk.CSR.from_host(A, v, vals_dtype=torch.float64)
+    for plan in (None, spk.Plan(1, 8, 50)):
+        C = spk.spmm(dA, dev(B, torch.float64), plan=plan).cpu().numpy()
+        assert_within(C, C64, M, TOL_F64, "f64 spmm")
+    V = synth.normal((700, 24), 11, synth.S_V)
+    S64, SM = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    S = spk.sddmm(dA, dev(U, torch.float64), dev(V, torch.float64)).cpu().numpy()
+    assert_within(S, S64, SM, TOL_F64, "f64 sddmm")
