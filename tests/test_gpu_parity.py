@@ -161,7 +161,14 @@ def test_sddmm_config1_every_plan(spk, lanes):
     S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
     for chunk in (0, 5, 1000):
         for flags in (0, 1):
-            S = run_sddmm(spk, A, v, U, V, spk.Plan(0, lanes, chunk, flags))
+            plan = spk.Plan(0, lanes, chunk, flags)
+            if -(-64 // (lanes * (1 if flags else 4))) > 8:
+                # more than 8 register slices per lane: the plan is refused before launch
+                with pytest.raises(spk.SpkError) as e:
+                    run_sddmm(spk, A, v, U, V, plan)
+                assert e.value.status == -6
+                continue
+            S = run_sddmm(spk, A, v, U, V, plan)
             assert_within(S, S64, M, TOL_F32, f"sddmm lanes={lanes} chunk={chunk} flags={flags}")
 
 
