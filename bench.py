@@ -1,18 +1,23 @@
 """Throughput of the SpMM / SDDMM hot path on one MI355X.
 
-A step is one SpMM (C = A B, Eq. 1) plus one SDDMM (S = A (.) (U V^T), Eq. 2)
-on the same sparse matrix, with every operand resident in HBM before the
-timed region.  The default workload is the paper's headline shape (random
-N x N at 90% sparsity, largest N = 65536, Section IV-A) with dense width 64:
-uniform column positions, values and dense operands ~ N(0, 1), FP32, seed 0.
+A step is one pass of the hot path over one synthetic matrix with every
+operand resident in HBM before the timed region:
+  uniform        SpMM (C = A B, Eq. 1) + SDDMM (S = A (.) (U V^T), Eq. 2), FP32
+  powerlaw-bf16  the same two products with BF16 dense operands, FP32 accumulation
+  gcn            forward SpMM + backward (dB = A^T G, dvals = SDDMM(pattern, G, B)),
+                 FP32; the transpose is per-pattern preprocessing, timed once
+The default workload is the paper's headline shape (random N x N at 90%
+sparsity, the largest N = 65536, Section IV-A) with dense width 64: uniform
+column positions, values and dense operands ~ N(0, 1), FP32, seed 0.
 
 Prints ONE JSON line on stdout:
-  value      whole-job GFLOP/s (2 nnz K flops per product, both products)
-  roofline   for the dominant kernel: algorithmic bytes or flops per launch
-             divided by its average launch time (HIP events on the launch
-             stream), against the binding MI355X peak
-  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of rows of the
-             same workload on this host's cores (rank 0, one GPU)
+  value         whole-job GFLOP/s (2 nnz K flops per product, all products)
+  roofline      for the dominant kernel: algorithmic bytes or flops per launch
+                over its average launch time (HIP events on the launch stream),
+                against the binding MI355X peak (HBM 8 TB/s, or the FP32 VALU
+                rate of 78.6 TFLOP/s without packed FP32)
+  cpu_baseline  the FP64 CPU oracle timed on the first rows of the same
+                workload (about --cpu-budget seconds) on this host's cores
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--plan plain|tuned|learned]
   python bench.py --sweep OUT.jsonl    # the n x sparsity x K grid, one record per op
@@ -32,7 +37,9 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_VALU_PEAK_TFS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
 
 WORKLOADS = {
-    # name: (n, density, K, kind)
+    # name: (n, density or mean degree, K, kind)
+    "powerlaw-n1048576-mean32-K256-bf16": (1 << 20, 32, 256, "powerlaw-bf16"),
+    "gcn-n262144-mean16-K128": (262144, 16, 128, "gcn"),
     "uniform-n65536-s90-K64": (65536, 0.1, 64, "uniform"),
     "uniform-n65536-s90-K128": (65536, 0.1, 128, "uniform"),
     "uniform-n65536-s99-K64": (65536, 0.01, 64, "uniform"),
@@ -48,11 +55,13 @@ WORKLOADS = {
     "uniform-n1024-s90-K64": (1024, 0.1, 64, "uniform"),
 }
 DEFAULT_WORKLOAD = "uniform-n65536-s90-K64"
+SWEEP = [w for w, v in WORKLOADS.items() if v[3] == "uniform" and v[0] >= 16384]
 
 
-def spmm_bytes(m, n, nnz, K, sv=4, sb=4):
-    """Compulsory HBM bytes of SpMM: row_ptr, (col, val) per entry, B once, C once."""
-    return 4 * (m + 1) + nnz * (4 + sv) + n * K * sb + m * K * 4
+def spmm_bytes(m, n, nnz, K, sv=4, sb=4, perm=False):
+    """Compulsory HBM bytes of SpMM: row_ptr, (col, val) per entry, B once, C once
+    (plus a 4-byte perm entry per stored value for A^T G)."""
+    return 4 * (m + 1) + nnz * (4 + sv + (4 if perm else 0)) + n * K * sb + m * K * 4
 
 
 def sddmm_bytes(m, n, nnz, K, sv=4, su=4):
@@ -79,23 +88,31 @@ def make_problem(name, seed=0):
     n, d, K, kind = WORKLOADS[name]
     if kind == "uniform":
         return synth.uniform_problem(n, d, K, seed)
+    if kind == "powerlaw-bf16":
+        return synth.powerlaw_problem(n, d, K, 2.1, seed)
+    if kind == "gcn":
+        # vals U(0,1) learnable, B and G ~ N(0,1); SDDMM(pattern, G, B) takes U = G, V = B
+        p = synth.powerlaw_problem(n, d, K, 2.1, seed, dense=("B", "G"))
+        p.U, p.V = p.G, p.B
+        return p
     raise ValueError(kind)
 
 
-def to_device(p):
+def to_device(p, kind):
     import torch
 
     import paper_2604_27985_amd as spk
 
     dA = spk.CSR.from_host(p.A, p.vals)
-    B = torch.from_numpy(p.B).cuda()
-    U = torch.from_numpy(p.U).cuda()
-    V = torch.from_numpy(p.V).cuda()
+    dt = torch.bfloat16 if kind == "powerlaw-bf16" else torch.float32
+    B = torch.from_numpy(p.B).cuda().to(dt)
+    U = torch.from_numpy(p.U).cuda().to(dt)
+    V = B if p.V is p.B else torch.from_numpy(p.V).cuda().to(dt)
     return dA, B, U, V
 
 
-def choose_plans(mode, dA, K, B, U, V):
-    """(spmm plan, sddmm plan) for plain (NULL plans), tuned (timed search) or learned."""
+def choose_plans(mode, dA, K, B, U, V, kind):
+    """(spmm plan, sddmm plan): NULL plans (plain), a timed search (tuned), or the selector."""
     import paper_2604_27985_amd as spk
 
     if mode == "plain":
@@ -106,22 +123,55 @@ def choose_plans(mode, dA, K, B, U, V):
         return selector.select(dA, K, spk.OP_SPMM), selector.select(dA, K, spk.OP_SDDMM)
     from paper_2604_27985_amd import autotune
 
-    return autotune.best_plan(dA, K, spk.OP_SPMM, B=B)[0], autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
+    p1 = autotune.best_plan(dA, K, spk.OP_SPMM, B=B)[0]
+    p2 = None if kind == "gcn" else autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
+    return p1, p2
 
 
-def time_steps(dA, B, U, V, p_spmm, p_sddmm, steps, warmup):
-    """Run warmup + timed steps; per-kernel HIP events on the launch stream."""
+class Step:
+    """One pass of the hot path with preallocated outputs and workspaces."""
+
+    def __init__(self, dA, B, U, V, p_spmm, p_sddmm, kind):
+        import torch
+
+        import paper_2604_27985_amd as spk
+
+        self.spk, self.kind = spk, kind
+        self.dA, self.B, self.U, self.V = dA, B, U, V
+        self.p_spmm, self.p_sddmm = p_spmm, p_sddmm
+        K = B.shape[1]
+        self.C = torch.empty((dA.m, K), dtype=torch.float32, device="cuda")
+        self.S = torch.empty(dA.nnz, dtype=torch.float32, device="cuda")
+        nb = spk.workspace_bytes(spk.OP_SPMM, dA, K, p_spmm)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        nb = spk.workspace_bytes(spk.OP_SDDMM, dA, K, p_sddmm)
+        self.ws2 = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        if kind == "gcn":
+            self.G = U
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            dA.transpose()  # per-pattern preprocessing, cached on the matrix
+            ev1.record()
+            torch.cuda.synchronize()
+            self.transpose_ms = ev0.elapsed_time(ev1)
+
+    def first(self):
+        self.spk.spmm(self.dA, self.B, plan=self.p_spmm, out=self.C, workspace=self.ws)
+
+    def second(self):
+        if self.kind == "gcn":
+            self.dB, self.S = self.spk.spmm_backward(self.dA, self.B, self.G, plan=self.p_spmm)
+        else:
+            self.spk.sddmm(self.dA, self.U, self.V, plan=self.p_sddmm, out=self.S, workspace=self.ws2)
+
+
+def time_steps(step, steps, warmup):
+    """Warmup, then `steps` timed steps; per-part HIP events on the launch stream."""
     import torch
 
-    import paper_2604_27985_amd as spk
-
-    C = torch.empty((dA.m, B.shape[1]), dtype=torch.float32, device="cuda")
-    S = torch.empty(dA.nnz, dtype=torch.float32, device="cuda")
-    ws_nb = spk.workspace_bytes(spk.OP_SPMM, dA, B.shape[1], p_spmm)
-    ws = torch.empty(max(ws_nb, 1), dtype=torch.uint8, device="cuda")
     for _ in range(warmup):
-        spk.spmm(dA, B, plan=p_spmm, out=C, workspace=ws if ws_nb else None)
-        spk.sddmm(dA, U, V, plan=p_sddmm, out=S)
+        step.first()
+        step.second()
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t_start = torch.cuda.Event(enable_timing=True)
@@ -131,22 +181,23 @@ def time_steps(dA, B, U, V, p_spmm, p_sddmm, steps, warmup):
     t_start.record()
     for s in range(steps):
         ev[s][0].record()
-        spk.spmm(dA, B, plan=p_spmm, out=C, workspace=ws if ws_nb else None)
+        step.first()
         ev[s][1].record()
-        spk.sddmm(dA, U, V, plan=p_sddmm, out=S)
+        step.second()
         ev[s][2].record()
     t_end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
-    spmm_ms = [e[0].elapsed_time(e[1]) for e in ev]
-    sddmm_ms = [e[1].elapsed_time(e[2]) for e in ev]
-    return total_ms, wall, spmm_ms, sddmm_ms, C, S
+    first_ms = [e[0].elapsed_time(e[1]) for e in ev]
+    second_ms = [e[1].elapsed_time(e[2]) for e in ev]
+    return total_ms, wall, first_ms, second_ms
 
 
-def cpu_baseline(p, C, S, budget_s=12.0):
-    """FP64 oracle on the first rows of the workload, sized to about budget_s of CPU work;
-    also reports the scaled error of the GPU results on those rows."""
+def cpu_baseline(p, kind, C, S, budget_s=12.0):
+    """FP64 oracle (SpMM + SDDMM) on the first rows of the workload, sized to about
+    budget_s of CPU work, timed on this host; also the scaled error of the GPU
+    results on those rows."""
     import numpy as np
 
     import oracle
@@ -154,29 +205,58 @@ def cpu_baseline(p, C, S, budget_s=12.0):
     A = p.A
     K = p.K
     rp = A.row_ptr
-    # calibrate on a small slice, then take as many rows as the budget allows
+    B, U, V = p.B, p.U, p.V
+    if kind == "powerlaw-bf16":  # the GPU consumed the bf16-rounded operands
+        B, U = oracle.round_bf16(B), oracle.round_bf16(U)
+        V = oracle.round_bf16(V)
+    svals = None if kind == "gcn" else p.vals  # the backward's SDDMM is pattern-only
     rows = max(1, min(A.m, 64))
-    t0 = time.perf_counter()
-    oracle.spmm(rp[:rows + 1], A.col_idx, p.vals, p.B)
-    oracle.sddmm(rp[:rows + 1], A.col_idx, p.vals, p.U, p.V)
-    dt = max(time.perf_counter() - t0, 1e-4)
+    while True:  # grow the sample until one pass takes at least 1 s, then scale to the budget
+        t0 = time.perf_counter()
+        oracle.spmm(rp[:rows + 1], A.col_idx, p.vals, B, with_bound=False)
+        oracle.sddmm(rp[:rows + 1], A.col_idx, svals, U, V, with_bound=False)
+        dt = time.perf_counter() - t0
+        if dt >= 1.0 or rows >= A.m:
+            break
+        rows = min(A.m, rows * 4)
     rows = int(min(A.m, max(rows, rows * budget_s / dt)))
     t0 = time.perf_counter()
-    C64, CM = oracle.spmm(rp[:rows + 1], A.col_idx, p.vals, p.B)
-    S64, SM = oracle.sddmm(rp[:rows + 1], A.col_idx, p.vals, p.U, p.V)
+    C64, CM = oracle.spmm(rp[:rows + 1], A.col_idx, p.vals, B)
+    S64, SM = oracle.sddmm(rp[:rows + 1], A.col_idx, svals, U, V)
     dt = time.perf_counter() - t0
     nnz_s = int(rp[rows]) - int(rp[0])
     S64, SM = S64[:nnz_s], SM[:nnz_s]  # entries of the sampled rows (row_ptr starts at 0)
     flops = 2.0 * nnz_s * K * 2
     c = C[:rows].cpu().numpy().astype(np.float64)
-    s = S[: nnz_s].cpu().numpy().astype(np.float64)
+    s = S[:nnz_s].cpu().numpy().astype(np.float64)
     with np.errstate(divide="ignore", invalid="ignore"):
         ec = np.where(CM > 0, np.abs(c - C64) / CM, np.abs(c - C64))
         es = np.where(SM > 0, np.abs(s - S64) / SM, np.abs(s - S64))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {rows} of {A.m} rows ({nnz_s} entries), SpMM + SDDMM in FP64, {dt:.1f} s",
+            "sample": f"first {rows} of {A.m} rows ({nnz_s} entries): SpMM + SDDMM in FP64, {dt:.1f} s",
             "gpu_max_scaled_err": float(max(ec.max(initial=0.0), es.max(initial=0.0)))}
+
+
+def kernel_table(p, kind, K, t1, t2):
+    """Per-part time, GFLOP/s and compulsory-byte HBM fraction."""
+    m, n, nnz = p.A.m, p.A.n, p.A.nnz
+    sb = 2 if kind == "powerlaw-bf16" else 4
+    f = 2.0 * nnz * K
+    if kind == "gcn":
+        # backward = A^T G (with perm) + SDDMM(pattern, G, B)
+        b1 = spmm_bytes(m, n, nnz, K)
+        b2 = spmm_bytes(n, m, nnz, K, perm=True) + sddmm_bytes(m, n, nnz, K, sv=0)
+        names, flops = ("spmm", "backward"), (f, 2 * f)
+    else:
+        b1 = spmm_bytes(m, n, nnz, K, sb=sb)
+        b2 = sddmm_bytes(m, n, nnz, K, su=sb)
+        names, flops = ("spmm", "sddmm"), (f, f)
+    out = {}
+    for name, t, b, fl in zip(names, (t1, t2), (b1, b2), flops):
+        out[name] = {"ms": round(t * 1e3, 4), "gflops": round(fl / t / 1e9, 1), "alg_bytes": int(b),
+                     "hbm_frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4), "_b": b, "_f": fl, "_t": t}
+    return out
 
 
 def run_workload(args):
@@ -188,42 +268,43 @@ def run_workload(args):
     t0 = time.perf_counter()
     p = make_problem(name)
     gen_s = time.perf_counter() - t0
-    dA, B, U, V = to_device(p)
+    dA, B, U, V = to_device(p, kind)
     torch.cuda.synchronize()
-    p_spmm, p_sddmm = choose_plans(args.plan, dA, K, B, U, V)
-    total_ms, wall, spmm_ms, sddmm_ms, C, S = time_steps(dA, B, U, V, p_spmm, p_sddmm, args.steps, args.warmup)
+    p_spmm, p_sddmm = choose_plans(args.plan, dA, K, B, U, V, kind)
+    step = Step(dA, B, U, V, p_spmm, p_sddmm, kind)
+    total_ms, wall, first_ms, second_ms = time_steps(step, args.steps, args.warmup)
     nnz = p.A.nnz
-    flops_step = 2.0 * nnz * K * 2
+    kt = kernel_table(p, kind, K, float(np.mean(first_ms)) * 1e-3, float(np.mean(second_ms)) * 1e-3)
+    flops_step = sum(v["_f"] for v in kt.values())
     ms_step = total_ms / args.steps
     value = flops_step / (ms_step * 1e-3) / 1e9
-    t_spmm = float(np.mean(spmm_ms)) * 1e-3
-    t_sddmm = float(np.mean(sddmm_ms)) * 1e-3
-    b_spmm = spmm_bytes(p.A.m, p.A.n, nnz, K)
-    b_sddmm = sddmm_bytes(p.A.m, p.A.n, nnz, K)
-    f_one = 2.0 * nnz * K
-    dominant = "spmm" if t_spmm >= t_sddmm else "sddmm"
-    roof = roofline(b_spmm if dominant == "spmm" else b_sddmm, f_one, max(t_spmm, t_sddmm))
-    roof["kernel"] = dominant
+    dom = max(kt, key=lambda k: kt[k]["_t"])
+    roof = roofline(kt[dom]["_b"], kt[dom]["_f"], kt[dom]["_t"])
+    roof["kernel"] = dom
     roof["traffic"] = None
+    for v in kt.values():
+        for key in ("_b", "_f", "_t"):
+            v.pop(key)
+    cfg = {"workload": name, "n": n, "nnz": nnz, "K": K, "pattern": "uniform" if kind == "uniform" else "powerlaw",
+           "ops": "spmm+backward" if kind == "gcn" else "spmm+sddmm", "plan": args.plan,
+           "plans": {"spmm": p_spmm.name() if p_spmm else "plain",
+                     "sddmm": p_sddmm.name() if p_sddmm else "plain"}}
+    if kind == "uniform":
+        cfg["sparsity"] = 1 - d
+    else:
+        cfg["mean_degree"] = d
     out = {
         "metric": "SpMM/SDDMM GFLOP/s + % HBM roofline; learned-tuned vs plain at 1e-5 rel err",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": name, "n": n, "sparsity": 1 - d, "nnz": nnz, "K": K, "pattern": kind,
-                   "ops": "spmm+sddmm", "plan": args.plan,
-                   "plans": {"spmm": p_spmm.name() if p_spmm else "plain", "sddmm": p_sddmm.name() if p_sddmm else "plain"}},
-        "roofline": roof,
-        "kernels": {
-            "spmm": {"ms": round(t_spmm * 1e3, 4), "gflops": round(f_one / t_spmm / 1e9, 1),
-                     "hbm_frac": round(b_spmm / t_spmm / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": b_spmm},
-            "sddmm": {"ms": round(t_sddmm * 1e3, 4), "gflops": round(f_one / t_sddmm / 1e9, 1),
-                      "hbm_frac": round(b_sddmm / t_sddmm / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": b_sddmm},
-        },
+        "dtype": "bf16-in/f32-acc" if kind == "powerlaw-bf16" else "f32", "data": "synthetic",
+        "config": cfg, "roofline": roof, "kernels": kt,
         "host_wall_s": round(wall, 3), "gen_s": round(gen_s, 2),
     }
+    if kind == "gcn":
+        out["transpose_ms_once"] = round(step.transpose_ms, 4)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, C, S, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(p, kind, step.C, step.S, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 
@@ -232,28 +313,26 @@ def run_sweep(args):
     import numpy as np
     import torch
 
-    import paper_2604_27985_amd as spk
-
-    names = [w for w in WORKLOADS if w != "uniform-n1024-s90-K64"]
     with open(args.sweep, "w") as f:
-        for name in names:
+        for name in SWEEP:
             n, d, K, kind = WORKLOADS[name]
             p = make_problem(name)
-            dA, B, U, V = to_device(p)
+            dA, B, U, V = to_device(p, kind)
             for mode in args.sweep_modes.split(","):
-                ps, pd = choose_plans(mode, dA, K, B, U, V)
-                total_ms, wall, spmm_ms, sddmm_ms, _, _ = time_steps(dA, B, U, V, ps, pd, args.steps, args.warmup)
-                for op, ms, plan, b in (("spmm", spmm_ms, ps, spmm_bytes(p.A.m, n, p.A.nnz, K)),
-                                        ("sddmm", sddmm_ms, pd, sddmm_bytes(p.A.m, n, p.A.nnz, K))):
-                    t = float(np.median(ms)) * 1e-3
+                ps, pd = choose_plans(mode, dA, K, B, U, V, kind)
+                step = Step(dA, B, U, V, ps, pd, kind)
+                _, _, first_ms, second_ms = time_steps(step, args.steps, args.warmup)
+                kt = kernel_table(p, kind, K, float(np.median(first_ms)) * 1e-3, float(np.median(second_ms)) * 1e-3)
+                for op, plan in (("spmm", ps), ("sddmm", pd)):
+                    v = kt[op]
                     rec = {"workload": name, "op": op, "mode": mode, "plan": plan.name() if plan else "plain",
-                           "n": n, "sparsity": 1 - d, "K": K, "nnz": p.A.nnz, "ms_median": round(t * 1e3, 4),
-                           "gflops": round(2.0 * p.A.nnz * K / t / 1e9, 1), "alg_bytes": b,
-                           "hbm_frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4),
-                           "roofline": roofline(b, 2.0 * p.A.nnz * K, t)}
+                           "n": n, "sparsity": 1 - d, "K": K, "nnz": p.A.nnz, "ms_median": v["ms"],
+                           "gflops": v["gflops"], "alg_bytes": v["alg_bytes"], "hbm_frac": v["hbm_frac"],
+                           "roofline": roofline(v["_b"], v["_f"], v["_t"])}
                     f.write(json.dumps(rec) + "\n")
                     f.flush()
                     print(json.dumps(rec), file=sys.stderr, flush=True)
+                del step
             del dA, B, U, V
             torch.cuda.empty_cache()
 

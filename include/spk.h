@@ -69,7 +69,8 @@ enum spk_op {
     SPK_OP_SPMM = 0,      /* spmm_csr */
     SPK_OP_SDDMM = 1,     /* sddmm_csr */
     SPK_OP_BACKWARD = 2,  /* spmm_csr_backward (the plan applies to A^T G) */
-    SPK_OP_TRANSPOSE = 3  /* csr_transpose (plan ignored) */
+    SPK_OP_TRANSPOSE = 3, /* csr_transpose (plan ignored) */
+    SPK_OP_BSR4 = 4       /* csr_to_bsr4_count (plan and K ignored) */
 };
 
 /* A sparse matrix in CSR form. */
@@ -86,24 +87,32 @@ enum spk_variant {
     SPK_VAR_ROWS = 0,  /* row-split: a group of `lanes` lanes owns one row */
     SPK_VAR_MERGE = 1, /* merge-path: each group owns an equal share of
                           rows + entries; split rows are fixed up in order */
-    SPK_VAR_BSR4 = 2   /* 4x4 block-sparse with matrix cores (SpMM only;
+    SPK_VAR_BSR4 = 2,  /* 4x4 block-sparse with matrix cores (SpMM only;
                           needs the block form from csr_to_bsr4) */
+    SPK_VAR_SLAB = 3   /* row-split over column slabs: one launch per slab
+                          of `chunk` columns, so the slab of the dense operand
+                          being gathered stays in L2 */
 };
 
 /* An execution plan: plain data, owned by the caller.
- * variant  one of spk_variant.
- * lanes    lanes cooperating on one row (SpMM) or one entry (SDDMM):
- *          4, 8, 16, 32 or 64.  Each lane covers `vec` consecutive columns of
- *          the dense operand, so one pass covers lanes * vec columns.
- * chunk    merge-path: rows + entries per group (0: max(256, 4K));
- *          SDDMM: entries per group (0: 256).
+ * variant  one of spk_variant.  SpMM: ROWS, MERGE, SLAB.  SDDMM: ROWS (a
+ *          group per row), MERGE (equal runs of entries per group), SLAB.
+ * lanes    lanes cooperating on one row: 4, 8, 16, 32 or 64.  Each lane
+ *          covers `vec` consecutive columns of the dense operand (4 for F32
+ *          and BF16, 8 for BF16 SpMM when K allows, 2 for F64), so one pass
+ *          covers lanes * vec columns.
+ * chunk    SpMM MERGE: rows + entries per group (0: max(256, 4K)).
+ *          SDDMM MERGE: entries per group (0: 256).
+ *          SLAB: slab width in columns (0: the width whose slab of the dense
+ *          operand takes 2 MiB, at least 256).
  * flags    bit 0: use scalar (one element per lane) loads even when the
  *          operands allow 8/16-byte vector loads; other bits must be 0.
  * Vector loads are used when K and the leading dimensions are multiples of
  * the vector width and the base pointers are aligned to it; otherwise the
  * call falls back to scalar loads by itself.
  * A NULL plan means the plain method: row-split SpMM with the smallest
- * power-of-two `lanes` >= K/4 (at most 64), and SDDMM with lanes = 8. */
+ * power-of-two `lanes` >= K/4 (at most 64), and entry-split (MERGE) SDDMM
+ * with lanes = 8 (widened until K fits in 8 register slices). */
 typedef struct spk_plan {
     int32_t variant;
     int32_t lanes;
@@ -123,7 +132,7 @@ const char *spk_strerror(int32_t status);
  *       A->vals_dtype is SPK_F64), leading dimension ldb >= K.
  * C     device [m x K], F32 (F64 in F64 mode), leading dimension ldc >= K;
  *       fully overwritten.
- * plan  NULL or a plan (variants ROWS and MERGE; BSR4 goes through spmm_bsr4).
+ * plan  NULL or a plan (variants ROWS, MERGE, SLAB; BSR4 goes through spmm_bsr4).
  * ws    workspace of spk_workspace_bytes(SPK_OP_SPMM, ...) bytes. */
 int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K,
                  void *C, int64_t ldc, const spk_plan *plan, void *ws, size_t ws_bytes,
@@ -160,6 +169,35 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
                           int64_t ldg, int32_t dtype, int64_t K, void *dB, int64_t lddb,
                           void *dvals, const spk_plan *plan, void *ws, size_t ws_bytes,
                           void *stream);
+
+/* A 4x4 block-sparse matrix (block CSR): block row I holds rows 4I..4I+3 of
+ * A, block column J columns 4J..4J+3; edge blocks are padded with zeros. */
+typedef struct spk_bsr4 {
+    int64_t m, n;             /* rows and columns of A */
+    int64_t nblocks;          /* stored 4x4 tiles */
+    const int32_t *b_row_ptr; /* device, ceil(m/4)+1 */
+    const int32_t *b_col;     /* device, nblocks, ascending within a block row */
+    const float *b_vals;      /* device, nblocks * 16, row-major 4x4 tiles */
+} spk_bsr4;
+
+/* CSR -> 4x4 block form, first half: b_row_ptr (device, ceil(m/4)+1) of the
+ * blocks holding at least one stored entry, and their number in *nblocks
+ * (host).  ws: spk_workspace_bytes(SPK_OP_BSR4, ...) bytes.  Synchronises
+ * `stream` (the caller allocates the block arrays from *nblocks). */
+int32_t csr_to_bsr4_count(const spk_csr *A, int32_t *b_row_ptr, int64_t *nblocks, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Second half: block columns b_col (device, nblocks) and tiles b_vals (device,
+ * nblocks * 16 floats; zeros where A stores nothing, ones in pattern mode).
+ * A->vals must be F32 or NULL. */
+int32_t csr_to_bsr4_fill(const spk_csr *A, const int32_t *b_row_ptr, int32_t *b_col, float *b_vals,
+                         void *stream);
+
+/* SpMM on the block form with matrix cores: C = A B as in spmm_csr (C F32,
+ * B F32 or BF16).  The block form computes exactly the CSR product: padded
+ * zeros add nothing. */
+int32_t spmm_bsr4(const spk_bsr4 *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C,
+                  int64_t ldc, void *stream);
 
 /* Opt-in O(nnz) structural check of A (canonical CSR as described above).
  * ws    at least 16 bytes.  Synchronises `stream`.  Returns SPK_OK or

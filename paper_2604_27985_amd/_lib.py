@@ -14,9 +14,9 @@ LIB_PATH = os.path.join(_HERE, "libspk.so")
 # enum spk_dtype
 F32, BF16, F64 = 0, 1, 2
 # enum spk_op
-OP_SPMM, OP_SDDMM, OP_BACKWARD, OP_TRANSPOSE = 0, 1, 2, 3
+OP_SPMM, OP_SDDMM, OP_BACKWARD, OP_TRANSPOSE, OP_BSR4 = 0, 1, 2, 3, 4
 # enum spk_variant
-VAR_ROWS, VAR_MERGE, VAR_BSR4 = 0, 1, 2
+VAR_ROWS, VAR_MERGE, VAR_BSR4, VAR_SLAB = 0, 1, 2, 3
 
 STATUS = {
     0: "SPK_OK", -1: "SPK_ERR_NULL", -2: "SPK_ERR_SIZE", -3: "SPK_ERR_DTYPE", -4: "SPK_ERR_LD",
@@ -37,6 +37,11 @@ class spk_plan(ctypes.Structure):
 
     def __repr__(self):
         return f"spk_plan(variant={self.variant}, lanes={self.lanes}, chunk={self.chunk}, flags={self.flags})"
+
+
+class spk_bsr4(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nblocks", ctypes.c_int64),
+                ("b_row_ptr", ctypes.c_void_p), ("b_col", ctypes.c_void_p), ("b_vals", ctypes.c_void_p)]
 
 
 class SpkError(RuntimeError):
@@ -60,6 +65,9 @@ SIGNATURES = {
     "spmm_csr_backward": ([_CSR_P, _P, _P, _P, _P, _I64, _P, _I64, _I32, _I64, _P, _I64, _P, _PLAN_P, _P,
                            _SZ, _P], _I32),
     "spk_csr_validate": ([_CSR_P, _P, _SZ, _P], _I32),
+    "csr_to_bsr4_count": ([_CSR_P, _P, ctypes.POINTER(ctypes.c_int64), _P, _SZ, _P], _I32),
+    "csr_to_bsr4_fill": ([_CSR_P, _P, _P, _P, _P], _I32),
+    "spmm_bsr4": ([ctypes.POINTER(spk_bsr4), _P, _I64, _I32, _I64, _P, _I64, _P], _I32),
 }
 
 _lib = None

@@ -12,7 +12,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _lib
-from ._lib import BF16, F32, F64, OP_BACKWARD, OP_SDDMM, OP_SPMM, OP_TRANSPOSE, VAR_MERGE, VAR_ROWS
+from ._lib import BF16, F32, F64, OP_BACKWARD, OP_SDDMM, OP_SPMM, OP_TRANSPOSE, VAR_MERGE, VAR_ROWS, VAR_SLAB
 
 _DT = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}
 
@@ -30,7 +30,7 @@ class Plan:
         return _lib.spk_plan(self.variant, self.lanes, self.chunk, self.flags)
 
     def name(self) -> str:
-        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4"}[self.variant]
+        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4", VAR_SLAB: "slab"}[self.variant]
         s = f"{v}/l{self.lanes}"
         if self.chunk:
             s += f"/c{self.chunk}"
@@ -150,7 +150,8 @@ def spmm(A: CSR, B: torch.Tensor, plan: Plan | None = None, out: torch.Tensor | 
 
 
 def sddmm(A: CSR, U: torch.Tensor, V: torch.Tensor, plan: Plan | None = None, out: torch.Tensor | None = None,
-          vals: torch.Tensor | None = None, pattern: bool = False) -> torch.Tensor:
+          vals: torch.Tensor | None = None, pattern: bool = False,
+          workspace: torch.Tensor | None = None) -> torch.Tensor:
     """S[p] = a_p <U[row p], V[col p]> (Eq. 2); pattern=True uses a_p = 1."""
     lib = _lib.load()
     _require_device(A.row_ptr, U, V)
@@ -163,8 +164,9 @@ def sddmm(A: CSR, U: torch.Tensor, V: torch.Tensor, plan: Plan | None = None, ou
     S = out if out is not None else torch.empty(A.nnz, dtype=odt, device=U.device)
     ca = A.c(vals, use_vals=not pattern)
     cp = plan.c() if plan is not None else None
+    ws, nb = (workspace, workspace.numel()) if workspace is not None else _workspace(OP_SDDMM, A, K, plan, U.device)
     st = lib.sddmm_csr(ctypes.byref(ca), _ptr(U), U.stride(0), _ptr(V), V.stride(0), _DT[U.dtype], K, _ptr(S),
-                       ctypes.byref(cp) if cp else None, None, 0, _stream())
+                       ctypes.byref(cp) if cp else None, _ptr(ws), nb, _stream())
     _lib.check(st, "sddmm_csr")
     return S
 
@@ -205,6 +207,62 @@ def spmm_backward(A: CSR, B: torch.Tensor, G: torch.Tensor, need_dB: bool = True
                                _ptr(dv), ctypes.byref(cp) if cp else None, _ptr(ws), nb, _stream())
     _lib.check(st, "spmm_csr_backward")
     return dB, dv
+
+
+@dataclass
+class BSR4:
+    """4x4 block-sparse form of a CSR matrix (device arrays)."""
+
+    b_row_ptr: torch.Tensor
+    b_col: torch.Tensor
+    b_vals: torch.Tensor  # [nblocks, 4, 4] float32
+    shape: tuple
+
+    @property
+    def nblocks(self) -> int:
+        return int(self.b_col.numel())
+
+    def c(self) -> _lib.spk_bsr4:
+        return _lib.spk_bsr4(int(self.shape[0]), int(self.shape[1]), self.nblocks, self.b_row_ptr.data_ptr(),
+                             self.b_col.data_ptr() if self.nblocks else None,
+                             self.b_vals.data_ptr() if self.nblocks else None)
+
+
+def csr_to_bsr4(A: CSR, vals: torch.Tensor | None = None) -> BSR4:
+    """Block form of A on the GPU (count pass synchronises to size the arrays)."""
+    lib = _lib.load()
+    _require_device(A.row_ptr)
+    dev = A.row_ptr.device
+    mb = (A.m + 3) // 4
+    brp = torch.empty(mb + 1, dtype=torch.int32, device=dev)
+    ca = A.c(vals)
+    if ca.vals is not None and ca.vals_dtype != F32:
+        raise ValueError("the block form holds float32 values")
+    ws, nb = _workspace(_lib.OP_BSR4, A, 0, None, dev)
+    count = ctypes.c_int64(0)
+    _lib.check(lib.csr_to_bsr4_count(ctypes.byref(ca), _ptr(brp), ctypes.byref(count), _ptr(ws), nb, _stream()),
+               "csr_to_bsr4_count")
+    bcol = torch.empty(count.value, dtype=torch.int32, device=dev)
+    bval = torch.empty((count.value, 4, 4), dtype=torch.float32, device=dev)
+    _lib.check(lib.csr_to_bsr4_fill(ctypes.byref(ca), _ptr(brp), _ptr(bcol), _ptr(bval), _stream()),
+               "csr_to_bsr4_fill")
+    return BSR4(brp, bcol, bval, A.shape)
+
+
+def spmm_bsr4(Ab: BSR4, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A B on matrix cores from the block form."""
+    lib = _lib.load()
+    _require_device(Ab.b_row_ptr, B)
+    _rowmajor(B, "B")
+    if B.shape[0] != Ab.shape[1] or B.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("B must be [n, K] float32 or bfloat16")
+    K = int(B.shape[1])
+    C = out if out is not None else torch.empty((Ab.shape[0], K), dtype=torch.float32, device=B.device)
+    _rowmajor(C, "C")
+    cb = Ab.c()
+    _lib.check(lib.spmm_bsr4(ctypes.byref(cb), _ptr(B), B.stride(0), _DT[B.dtype], K, _ptr(C), C.stride(0),
+                             _stream()), "spmm_bsr4")
+    return C
 
 
 def validate(A: CSR) -> bool:

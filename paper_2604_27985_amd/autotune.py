@@ -10,13 +10,14 @@ from __future__ import annotations
 import torch
 
 from . import api
-from ._lib import OP_SDDMM, OP_SPMM, VAR_MERGE, VAR_ROWS
+from ._lib import OP_SDDMM, OP_SPMM, VAR_MERGE, VAR_ROWS, VAR_SLAB
 
 LANES = (4, 8, 16, 32, 64)
 
 
 def spmm_plans(K: int, dtype: torch.dtype = torch.float32) -> list[api.Plan]:
-    """Row-split and merge-path SpMM plans whose lanes cover at most 2x the padded K."""
+    """Row-split, merge-path and column-slab SpMM plans whose lanes cover at most
+    2x the padded K."""
     vec = 2 if dtype == torch.float64 else 4
     cap = max(16, 1 << (max(K, 1) - 1).bit_length())
     plans = []
@@ -25,6 +26,7 @@ def spmm_plans(K: int, dtype: torch.dtype = torch.float32) -> list[api.Plan]:
             continue
         plans.append(api.Plan(VAR_ROWS, lanes, 0))
         plans.append(api.Plan(VAR_MERGE, lanes, 0))
+        plans.append(api.Plan(VAR_SLAB, lanes, 0))
     return plans
 
 
@@ -38,7 +40,9 @@ def sddmm_plans(K: int, dtype: torch.dtype = torch.float32) -> list[api.Plan]:
         if lanes * vec > 2 * max(K, 4) and lanes != 4:
             continue
         for chunk in (64, 256, 1024):
-            plans.append(api.Plan(VAR_ROWS, lanes, chunk))
+            plans.append(api.Plan(VAR_MERGE, lanes, chunk))
+        plans.append(api.Plan(VAR_ROWS, lanes, 0))
+        plans.append(api.Plan(VAR_SLAB, lanes, 0))
     return plans
 
 
@@ -65,9 +69,11 @@ def time_plan(A: api.CSR, K: int, op: int, plan: api.Plan | None, B=None, U=None
         if V is None:
             V = torch.randn(A.n, K, device=dev)
         S = torch.empty(A.nnz, dtype=torch.float32 if U.dtype != torch.float64 else torch.float64, device=dev)
+        nb = api.workspace_bytes(OP_SDDMM, A, K, plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
 
         def launch():
-            api.sddmm(A, U, V, plan=plan, out=S)
+            api.sddmm(A, U, V, plan=plan, out=S, workspace=ws)
     for _ in range(warmup):
         launch()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]

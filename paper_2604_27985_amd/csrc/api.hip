@@ -51,12 +51,23 @@ int32_t default_spmm_lanes(int64_t K) {
     return l;
 }
 
+// Default slab width: the power of two (>= 256) whose slab of the dense
+// operand takes at most 2 MiB, half of one XCD's L2.
+int64_t default_slab_width(int64_t K, size_t es) {
+    const int64_t row_bytes = (K > 0 ? K : 1) * static_cast<int64_t>(es);
+    int64_t w = 256;
+    while (w * 2 * row_bytes <= (int64_t(2) << 20)) w *= 2;
+    return w;
+}
+
 int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const void *B, int64_t ldb, const void *C,
                      int64_t ldc, Resolved &r) {
     r.variant = plan ? plan->variant : SPK_VAR_ROWS;
     r.lanes = plan ? plan->lanes : default_spmm_lanes(K);
-    r.chunk = plan && plan->chunk > 0 ? plan->chunk : (4 * K > kDefaultChunk ? 4 * K : kDefaultChunk);
-    if (r.variant != SPK_VAR_ROWS && r.variant != SPK_VAR_MERGE) return SPK_ERR_PLAN;
+    if (r.variant != SPK_VAR_ROWS && r.variant != SPK_VAR_MERGE && r.variant != SPK_VAR_SLAB) return SPK_ERR_PLAN;
+    if (plan && plan->chunk > 0) r.chunk = plan->chunk;
+    else if (r.variant == SPK_VAR_SLAB) r.chunk = default_slab_width(K, elem_size(b_dtype));
+    else r.chunk = 4 * K > kDefaultChunk ? 4 * K : kDefaultChunk;
     if (!valid_lanes(r.lanes)) return SPK_ERR_PLAN;
     if (plan && (plan->flags & ~1)) return SPK_ERR_PLAN;
     if (plan && plan->chunk < 0) return SPK_ERR_PLAN;
@@ -80,8 +91,11 @@ int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U
     const bool ok = !force_scalar && K % v == 0 && ldu % v == 0 && ldv % v == 0 && aligned(U, es * v) &&
                     aligned(V, es * v);
     r.vec = ok ? v : 1;
-    r.variant = SPK_VAR_ROWS;
-    r.chunk = plan && plan->chunk > 0 ? plan->chunk : kDefaultChunk;
+    r.variant = plan ? plan->variant : SPK_VAR_MERGE;
+    if (r.variant != SPK_VAR_ROWS && r.variant != SPK_VAR_MERGE && r.variant != SPK_VAR_SLAB) return SPK_ERR_PLAN;
+    if (plan && plan->chunk > 0) r.chunk = plan->chunk;
+    else if (r.variant == SPK_VAR_SLAB) r.chunk = default_slab_width(K, es);
+    else r.chunk = kDefaultChunk;
     if (plan) {
         if (plan->flags & ~1) return SPK_ERR_PLAN;
         if (plan->chunk < 0) return SPK_ERR_PLAN;
@@ -106,9 +120,15 @@ int32_t check_ws(size_t need, const void *ws, size_t ws_bytes) {
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? SPK_OK : SPK_ERR_HIP; }
 
-size_t spmm_ws(int64_t m, int64_t nnz, int64_t K, int32_t dt, const Resolved &r) {
-    if (r.variant != SPK_VAR_MERGE || m == 0 || K == 0) return 0;
-    return merge_layout(m, nnz, K, r.chunk, dt == SPK_F64 ? 8 : 4).total;
+size_t spmm_ws(int64_t m, int64_t n, int64_t nnz, int64_t K, int32_t dt, const Resolved &r) {
+    if (m == 0 || K == 0) return 0;
+    if (r.variant == SPK_VAR_MERGE) return merge_layout(m, nnz, K, r.chunk, dt == SPK_F64 ? 8 : 4).total;
+    if (r.variant == SPK_VAR_SLAB) return slab_layout(m, n, r.chunk).total;
+    return 0;
+}
+
+size_t sddmm_ws(int64_t m, int64_t n, const Resolved &r) {
+    return r.variant == SPK_VAR_SLAB ? slab_layout(m, n, r.chunk).total : 0;
 }
 
 }  // namespace
@@ -134,19 +154,80 @@ const char *spk_strerror(int32_t status) {
 
 size_t spk_workspace_bytes(int32_t op, const spk_csr *A, int64_t K, const spk_plan *plan) {
     if (check_csr(A) != SPK_OK || K < 0) return 0;
+    if (plan && (plan->chunk < 0 || plan->variant < SPK_VAR_ROWS || plan->variant > SPK_VAR_SLAB)) return 0;
+    // The size depends only on the variant, the chunk and the shapes.  Sizes
+    // assume the widest element (8 bytes): the largest carry and, for the
+    // default slab width, the most slabs, so any dtype's call fits.
     Resolved r;
+    r.lanes = 4;
+    r.vec = 1;
+    const bool bwd = op == SPK_OP_BACKWARD;
+    const int64_t m = bwd ? A->n : A->m, n = bwd ? A->m : A->n;
     switch (op) {
     case SPK_OP_SPMM:
-        // Alignment does not change the size: resolve with aligned stand-ins.
-        if (resolve_spmm(plan, K, SPK_F64, nullptr, K, nullptr, K, r) != SPK_OK) return 0;
-        return spmm_ws(A->m, A->nnz, K, SPK_F64, r);
-    case SPK_OP_SDDMM: return 0;
-    case SPK_OP_TRANSPOSE: return transpose_ws_bytes(A->m, A->n, A->nnz);
     case SPK_OP_BACKWARD:
-        if (resolve_spmm(plan, K, SPK_F64, nullptr, K, nullptr, K, r) != SPK_OK) return 0;
-        return spmm_ws(A->n, A->nnz, K, SPK_F64, r);
+        r.variant = plan ? plan->variant : SPK_VAR_ROWS;
+        if (plan && plan->chunk > 0) r.chunk = plan->chunk;
+        else if (r.variant == SPK_VAR_SLAB) r.chunk = default_slab_width(K, 8);
+        else r.chunk = 4 * K > kDefaultChunk ? 4 * K : kDefaultChunk;
+        return spmm_ws(m, n, A->nnz, K, SPK_F64, r);
+    case SPK_OP_SDDMM:
+        r.variant = plan ? plan->variant : SPK_VAR_MERGE;
+        r.chunk = plan && plan->chunk > 0 ? plan->chunk : default_slab_width(K, 8);
+        return sddmm_ws(m, n, r);
+    case SPK_OP_TRANSPOSE: return transpose_ws_bytes(A->m, A->n, A->nnz);
+    case SPK_OP_BSR4: return scan_ws_bytes_i32((A->m + 3) / 4 + 1);
     default: return 0;
     }
+}
+
+int32_t csr_to_bsr4_count(const spk_csr *A, int32_t *b_row_ptr, int64_t *nblocks, void *ws, size_t ws_bytes,
+                          void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (!b_row_ptr || !nblocks) return SPK_ERR_NULL;
+    const int64_t mb = (A->m + 3) / 4;
+    if ((st = check_ws(scan_ws_bytes_i32(mb + 1), ws, ws_bytes))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemsetAsync(b_row_ptr, 0, sizeof(int32_t) * static_cast<size_t>(mb + 1), s) != hipSuccess) return SPK_ERR_HIP;
+    if ((st = hip_status(bsr4_count_launch(A->m, A->row_ptr, A->col_idx, b_row_ptr, s)))) return st;
+    if ((st = hip_status(exclusive_scan_i32(b_row_ptr, mb + 1, ws, s)))) return st;
+    int32_t total = 0;
+    if (hipMemcpyAsync(&total, b_row_ptr + mb, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return SPK_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPK_ERR_HIP;
+    *nblocks = total;
+    return SPK_OK;
+}
+
+int32_t csr_to_bsr4_fill(const spk_csr *A, const int32_t *b_row_ptr, int32_t *b_col, float *b_vals, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (A->vals && A->vals_dtype != SPK_F32) return SPK_ERR_DTYPE;
+    if (!b_row_ptr || (A->nnz > 0 && (!b_col || !b_vals))) return SPK_ERR_NULL;
+    if (A->nnz == 0) return SPK_OK;
+    return hip_status(bsr4_fill_launch(A->m, A->row_ptr, A->col_idx, static_cast<const float *>(A->vals), b_row_ptr,
+                                       b_col, b_vals, static_cast<hipStream_t>(stream)));
+}
+
+int32_t spmm_bsr4(const spk_bsr4 *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C, int64_t ldc,
+                  void *stream) {
+    if (!A) return SPK_ERR_NULL;
+    if (A->m < 0 || A->n < 0 || A->nblocks < 0 || A->m > kMaxIndex || A->n > kMaxIndex) return SPK_ERR_SIZE;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (b_dtype != SPK_F32 && b_dtype != SPK_BF16) return SPK_ERR_DTYPE;
+    if (A->m == 0 || K == 0) return SPK_OK;
+    if (!C || !A->b_row_ptr) return SPK_ERR_NULL;
+    if (ldc < K) return SPK_ERR_LD;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (A->nblocks == 0 || A->n == 0) return hip_status(zero_fill(C, A->m, K, ldc, SPK_F32, s));
+    if (!B || !A->b_col || !A->b_vals) return SPK_ERR_NULL;
+    if (ldb < K) return SPK_ERR_LD;
+    const size_t es = elem_size(b_dtype);
+    const bool v4 = K >= 256 && K % 4 == 0 && ldb % 4 == 0 && ldc % 4 == 0 && aligned(B, es * 4) && aligned(C, 16);
+    Bsr4Args a{A->m, A->n, K, A->b_row_ptr, A->b_col, A->b_vals, B, ldb, b_dtype, v4 ? 4 : 1,
+               static_cast<float *>(C), ldc};
+    return hip_status(bsr4_spmm_launch(a, s));
 }
 
 int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C, int64_t ldc,
@@ -163,7 +244,7 @@ int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, 
     if (A->nnz == 0) return hip_status(zero_fill(C, A->m, K, ldc, out_dt, s));
     Resolved r;
     if ((st = resolve_spmm(plan, K, b_dtype, B, ldb, C, ldc, r))) return st;
-    const size_t need = spmm_ws(A->m, A->nnz, K, b_dtype, r);
+    const size_t need = spmm_ws(A->m, A->n, A->nnz, K, b_dtype, r);
     if ((st = check_ws(need, ws, ws_bytes))) return st;
     SpmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, nullptr, B, ldb, b_dtype, C, ldc,
                r.variant, r.lanes, r.vec, r.chunk, ws};
@@ -172,8 +253,6 @@ int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, 
 
 int32_t sddmm_csr(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv, int32_t uv_dtype,
                   int64_t K, void *S, const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
-    (void)ws;
-    (void)ws_bytes;
     int32_t st = check_csr(A);
     if (st) return st;
     if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
@@ -183,8 +262,9 @@ int32_t sddmm_csr(const spk_csr *A, const void *U, int64_t ldu, const void *V, i
     if (K > 0 && (ldu < K || ldv < K)) return SPK_ERR_LD;
     Resolved r;
     if ((st = resolve_sddmm(plan, K, uv_dtype, U, ldu, V, ldv, r))) return st;
-    SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, U, ldu, V, ldv, uv_dtype, S, r.lanes, r.vec,
-                r.chunk};
+    if ((st = check_ws(sddmm_ws(A->m, A->n, r), ws, ws_bytes))) return st;
+    SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, U, ldu, V, ldv, uv_dtype, S,
+                r.variant, r.lanes, r.vec, r.chunk, ws};
     return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
 }
 
@@ -217,7 +297,7 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
         } else {
             Resolved r;
             if ((st = resolve_spmm(plan, K, dtype, G, ldg, dB, lddb, r))) return st;
-            const size_t need = spmm_ws(A->n, A->nnz, K, dtype, r);
+            const size_t need = spmm_ws(A->n, A->m, A->nnz, K, dtype, r);
             if ((st = check_ws(need, ws, ws_bytes))) return st;
             SpmmArgs a{A->n, A->m, A->nnz, K, at_row_ptr, at_col_idx, A->vals, perm, G, ldg, dtype, dB, lddb,
                        r.variant, r.lanes, r.vec, r.chunk, ws};
@@ -231,8 +311,8 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
         P.vals = nullptr;
         Resolved r;
         if ((st = resolve_sddmm(nullptr, K, dtype, G, ldg, B, ldb, r))) return st;
-        SddmmArgs a{P.m, P.n, P.nnz, K, P.row_ptr, P.col_idx, nullptr, G, ldg, B, ldb, dtype, dvals, r.lanes, r.vec,
-                    r.chunk};
+        SddmmArgs a{P.m, P.n, P.nnz, K, P.row_ptr, P.col_idx, nullptr, G, ldg, B, ldb, dtype, dvals,
+                    r.variant, r.lanes, r.vec, r.chunk, nullptr};
         if ((st = hip_status(sddmm_launch(a, s)))) return st;
     }
     return SPK_OK;

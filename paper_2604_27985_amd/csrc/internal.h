@@ -37,9 +37,25 @@ struct SddmmArgs {
     int64_t ldv;
     int32_t uv_dtype;
     void *S;
-    int32_t lanes, vec;
+    int32_t variant, lanes, vec;
     int64_t chunk;
+    void *ws;
 };
+
+// Column slabs of the SLAB variants: nslabs slabs of `width` columns; the
+// workspace holds the (nslabs - 1) interior boundaries of every row.
+struct SlabLayout {
+    int64_t width, nslabs;
+    size_t total;
+};
+
+inline SlabLayout slab_layout(int64_t m, int64_t n, int64_t width) {
+    SlabLayout L;
+    L.width = width > 0 ? width : 1;
+    L.nslabs = n > 0 ? (n + L.width - 1) / L.width : 1;
+    L.total = L.nslabs > 1 ? align_up(sizeof(int32_t) * static_cast<size_t>(m) * static_cast<size_t>(L.nslabs - 1)) : 0;
+    return L;
+}
 
 // Workspace of the merge-path SpMM: share start rows, carry rows, carry sums.
 struct MergeLayout {
@@ -60,8 +76,31 @@ inline MergeLayout merge_layout(int64_t m, int64_t nnz, int64_t K, int64_t chunk
 }
 
 hipError_t spmm_launch(const SpmmArgs &a, hipStream_t s);
+// Interior column-slab boundaries of every row into bnd[(nslabs-1) * m].
+hipError_t slab_bounds_launch(int64_t m, const int32_t *rp, const int32_t *ci, int64_t width, int64_t nslabs,
+                              int32_t *bnd, hipStream_t s);
 hipError_t sddmm_launch(const SddmmArgs &a, hipStream_t s);
 hipError_t zero_fill(void *C, int64_t m, int64_t K, int64_t ld, int32_t dtype, hipStream_t s);
+
+// 4x4 block-sparse SpMM on matrix cores (bsr.hip).
+struct Bsr4Args {
+    int64_t m, n, K;
+    const int32_t *b_rp, *b_col;
+    const float *b_vals;
+    const void *B;
+    int64_t ldb;
+    int32_t b_dtype, vec;
+    float *C;
+    int64_t ldc;
+};
+hipError_t bsr4_count_launch(int64_t m, const int32_t *rp, const int32_t *ci, int32_t *counts, hipStream_t s);
+hipError_t bsr4_fill_launch(int64_t m, const int32_t *rp, const int32_t *ci, const float *vals, const int32_t *b_rp,
+                            int32_t *b_col, float *b_vals, hipStream_t s);
+hipError_t bsr4_spmm_launch(const Bsr4Args &a, hipStream_t s);
+
+// In-place exclusive scan of int32 values (transpose.hip).
+size_t scan_ws_bytes_i32(int64_t count);
+hipError_t exclusive_scan_i32(int32_t *data, int64_t count, void *ws, hipStream_t s);
 
 // CSR transpose (transpose.hip).
 size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz);

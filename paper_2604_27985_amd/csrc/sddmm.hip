@@ -3,142 +3,254 @@
 // Only stored entries of A are computed (the dense product is never formed):
 // S[p] = a_p * <U[row(p), :], V[col(p), :]>.
 //
-// Work is split by entries, not rows: group g of LANES lanes takes entries
-// [g*chunk, (g+1)*chunk), finds the row of its first entry by binary search in
-// row_ptr and walks forward, so power-law rows cost no imbalance.  Each lane
-// holds an NS x VW slice of the current U row in registers (reloaded only
-// when the row changes), gathers the matching slice of V's row with 8/16-byte
-// loads, and the group's partial dot products are summed with a butterfly
-// over the LANES lanes (ds_bpermute exchanges).  Up to eight entries of one
-// row are processed per step: their column indices are read with one
-// coalesced load and shared across the group, and all their V gathers are
-// issued before any arithmetic.
+// A group of LANES lanes works on one row at a time.  Each lane holds an
+// NS x VW slice of the row of U in registers; per step the group takes up to
+// R entries of the row, reads their column indices with one coalesced load,
+// shares them with ds_bpermute, gathers all R slices of V's rows (no
+// exec-mask branches: surplus entries re-read a valid row), and forms R
+// partial dot products per lane.  The R dot products are then reduced
+// together with a transposing butterfly: at each halving step a lane keeps
+// half of its values and receives the partner's matching half, so R values
+// over R lanes cost R-1 exchanges instead of R log2(R).  Lane q of the group
+// ends holding entry q's total.
+//
+// Three ways to hand rows to groups:
+//   MERGE  (default) groups take equal runs of `chunk` entries regardless of
+//          rows (binary search for the first row), so power-law rows cost no
+//          imbalance;
+//   ROWS   group g takes row g;
+//   SLAB   one launch per slab of W columns, group g takes the entries of row
+//          g in that slab, so the rows of V being gathered stay in L2.
 #include "common.h"
 #include "internal.h"
 
 namespace spk {
 
-template <typename TUV, typename TV, int VW, int LANES, int NS>
-__global__ __launch_bounds__(kBlock) void sddmm_kernel(int64_t m, int64_t nnz, int K, const int32_t *__restrict__ rp,
-                                                       const int32_t *__restrict__ ci,
-                                                       const TV *__restrict__ vals,
-                                                       const TUV *__restrict__ U, int64_t ldu,
-                                                       const TUV *__restrict__ V, int64_t ldv,
-                                                       typename acc_of<TUV>::type *__restrict__ S,
-                                                       int64_t chunk, int64_t ngroups) {
+template <bool OFF32, typename T>
+__device__ __forceinline__ const T *row_elem(const T *base, int32_t row, int64_t ld, int32_t col) {
+    if constexpr (OFF32)
+        return base + (static_cast<uint32_t>(row) * static_cast<uint32_t>(ld) + static_cast<uint32_t>(col));
+    else
+        return base + (static_cast<int64_t>(row) * ld + col);
+}
+
+// On return, lane l of each LANES-lane group holds the group-wide total of
+// x[l mod R] (R and LANES powers of two, R <= LANES).
+template <int R, int LANES, typename T>
+__device__ __forceinline__ T reduce_scatter(T (&x)[R], int lane) {
+#pragma unroll
+    for (int h = R / 2; h >= 1; h /= 2) {
+        const bool upper = (lane & h) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const T send = upper ? x[i] : x[i + h];
+            const T keep = upper ? x[i + h] : x[i];
+            x[i] = keep + lane_read(send, lane ^ h);
+        }
+    }
+    T v = x[0];
+#pragma unroll
+    for (int s = R; s < LANES; s *= 2) v += lane_read(v, lane ^ s);
+    return v;
+}
+
+template <typename TUV, int VW, int LANES, int NS>
+struct URow {
     using A = typename acc_of<TUV>::type;
+    A u[NS][VW];
+    // Slice s of lane lig covers columns s*LANES*VW + lig*VW .. +VW; slices
+    // beyond K are zero (their gathers read column 0 and add nothing).
+    __device__ __forceinline__ void load(const TUV *U, int64_t row, int64_t ldu, int K, int lig) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = s * LANES * VW + lig * VW;
+            if (k < K) vec_load<TUV, VW>::run(U + row * ldu + k, u[s]);
+            else
+#pragma unroll
+                for (int e = 0; e < VW; ++e) u[s][e] = A(0);
+        }
+    }
+};
+
+// Entries pb .. pb+cnt-1 (1 <= cnt <= R) of one row whose U slice is in u.
+template <typename TUV, typename TV, int VW, int LANES, int NS, int R, bool OFF32>
+__device__ __forceinline__ void sddmm_step(int64_t pb, int cnt, const int32_t *__restrict__ ci,
+                                           const TV *__restrict__ vals, const TUV *__restrict__ V, int64_t ldv,
+                                           const URow<TUV, VW, LANES, NS> &ur, int K, int gbase, int lig, int lane,
+                                           typename acc_of<TUV>::type *__restrict__ S) {
+    using A = typename acc_of<TUV>::type;
+    const int mine = lig < cnt ? lig : cnt - 1;
+    const int c_mine = __builtin_nontemporal_load(ci + pb + mine);
+    int cc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) cc[q] = lane_read(c_mine, gbase + q);
+    A vrow[R][NS][VW];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = s * LANES * VW + lig * VW;
+            vec_load<TUV, VW>::run(row_elem<OFF32>(V, cc[q], ldv, k < K ? k : 0), vrow[q][s]);
+        }
+    A part[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        A acc = A(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc = fma(ur.u[s][e], vrow[q][s][e], acc);
+        part[q] = acc;
+    }
+    const A tot = reduce_scatter<R, LANES>(part, lane);
+    if (lig < cnt && lig < R) {
+        const int64_t p = pb + lig;
+        const A a = vals ? static_cast<A>(__builtin_nontemporal_load(vals + p)) : A(1);
+        __builtin_nontemporal_store(a * tot, S + p);
+    }
+}
+
+// MERGE: group g takes entries [g*chunk, (g+1)*chunk).
+template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
+__global__ __launch_bounds__(kBlock) void sddmm_split_kernel(int64_t m, int64_t nnz, int K, const int32_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ ci,
+                                                             const TV *__restrict__ vals,
+                                                             const TUV *__restrict__ U, int64_t ldu,
+                                                             const TUV *__restrict__ V, int64_t ldv,
+                                                             typename acc_of<TUV>::type *__restrict__ S,
+                                                             int64_t chunk, int64_t ngroups) {
     constexpr int GPB = kBlock / LANES;
-    constexpr int KT = LANES * VW;             // columns per slice
-    constexpr int R = LANES < 8 ? LANES : 8;   // entries per step (<= LANES)
+    constexpr int R = LANES < 8 ? LANES : 8;
+    const int lane = threadIdx.x & (kWave - 1);
     const int lig = threadIdx.x & (LANES - 1);
-    const int gbase = (threadIdx.x & (kWave - 1)) & ~(LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t g = blk * GPB + threadIdx.x / LANES;
     if (g >= ngroups) return;
     const int64_t p0 = g * chunk;
     const int64_t p1 = p0 + chunk < nnz ? p0 + chunk : nnz;
-
     // Row holding entry p0: largest r in [0, m-1] with row_ptr[r] <= p0.
     int64_t r = last_at_most(0, m - 1, p0, [&](int64_t i) { return static_cast<int64_t>(rp[i]); });
     int64_t next = rp[r + 1];
     int64_t loaded = -1;
-    A u[NS][VW];
-
+    URow<TUV, VW, LANES, NS> ur;
     for (int64_t pb = p0; pb < p1;) {
         while (pb >= next) {  // group-uniform; also skips empty rows
             ++r;
             next = rp[r + 1];
         }
         if (r != loaded) {
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int k = s * KT + lig * VW;
-                if (k < K) vec_load<TUV, VW>::run(U + r * ldu + k, u[s]);
-                else
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) u[s][e] = A(0);
-            }
+            ur.load(U, r, ldu, K, lig);
             loaded = r;
         }
-        // A step never crosses a row end, so one U row serves all of it.
-        int64_t lim = p1 < next ? p1 : next;
+        const int64_t lim = p1 < next ? p1 : next;  // a step never crosses a row end
         const int cnt = static_cast<int>(lim - pb < R ? lim - pb : R);
-        const int c_mine = lig < cnt ? ci[pb + lig] : 0;
-        A vrow[R][NS][VW];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int64_t c = lane_read(c_mine, gbase + q);
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int k = s * KT + lig * VW;
-                if (q < cnt && k < K) vec_load<TUV, VW>::run(V + c * ldv + k, vrow[q][s]);
-                else
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) vrow[q][s][e] = A(0);
-            }
-        }
-        A part[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            part[q] = A(0);
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-                for (int e = 0; e < VW; ++e) part[q] = fma(u[s][e], vrow[q][s][e], part[q]);
-            part[q] = group_sum<LANES>(part[q]);
-        }
-        if (lig < cnt) {  // lane q of the group writes entry pb + q
-            A mine = part[0];
-#pragma unroll
-            for (int q = 1; q < R; ++q) mine = (lig == q) ? part[q] : mine;
-            const int64_t p = pb + lig;
-            const A a = vals ? static_cast<A>(vals[p]) : A(1);
-            S[p] = a * mine;
-        }
+        sddmm_step<TUV, TV, VW, LANES, NS, R, OFF32>(pb, cnt, ci, vals, V, ldv, ur, K, gbase, lig, lane, S);
         pb += cnt;
     }
 }
 
-template <typename TUV, typename TV, int VW, int LANES, int NS>
-static hipError_t launch_sddmm(const SddmmArgs &a, hipStream_t s) {
+// ROWS / SLAB: group g takes the entries of row g in slab s
+// ([bnd(s, g), bnd(s+1, g)) with bnd(0, .) = row_ptr, bnd(nslabs, .) = row_ptr[+1]).
+template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
+__global__ __launch_bounds__(kBlock) void sddmm_rows_kernel(int64_t m, int K, const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ bnd, int nslabs, int s,
+                                                            const int32_t *__restrict__ ci,
+                                                            const TV *__restrict__ vals,
+                                                            const TUV *__restrict__ U, int64_t ldu,
+                                                            const TUV *__restrict__ V, int64_t ldv,
+                                                            typename acc_of<TUV>::type *__restrict__ S) {
     constexpr int GPB = kBlock / LANES;
-    const int64_t ngroups = (a.nnz + a.chunk - 1) / a.chunk;
-    const int64_t nb = (ngroups + GPB - 1) / GPB;
-    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sddmm_kernel<TUV, TV, VW, LANES, NS>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s,
-                       a.m, a.nnz, static_cast<int>(a.K), a.rp, a.ci, static_cast<const TV *>(a.vals),
-                       static_cast<const TUV *>(a.U), a.ldu, static_cast<const TUV *>(a.V), a.ldv,
-                       static_cast<typename acc_of<TUV>::type *>(a.S), a.chunk, ngroups);
-    return hipGetLastError();
+    constexpr int R = LANES < 8 ? LANES : 8;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row = blk * GPB + threadIdx.x / LANES;
+    if (row >= m) return;
+    const int64_t a = s == 0 ? rp[row] : bnd[(s - 1) * m + row];
+    const int64_t b = s == nslabs - 1 ? rp[row + 1] : bnd[s * m + row];
+    if (a >= b) return;
+    URow<TUV, VW, LANES, NS> ur;
+    ur.load(U, row, ldu, K, lig);
+    for (int64_t pb = a; pb < b; pb += R) {
+        const int cnt = static_cast<int>(b - pb < R ? b - pb : R);
+        sddmm_step<TUV, TV, VW, LANES, NS, R, OFF32>(pb, cnt, ci, vals, V, ldv, ur, K, gbase, lig, lane, S);
+    }
 }
 
-template <typename TUV, typename TV, int VW, int LANES>
+template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
+static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
+    constexpr int GPB = kBlock / LANES;
+    using A = typename acc_of<TUV>::type;
+    if (a.variant == SPK_VAR_MERGE) {
+        const int64_t ngroups = (a.nnz + a.chunk - 1) / a.chunk;
+        const int64_t nb = (ngroups + GPB - 1) / GPB;
+        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((sddmm_split_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
+                           dim3(kBlock), 0, s, a.m, a.nnz, static_cast<int>(a.K), a.rp, a.ci,
+                           static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
+                           static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S), a.chunk, ngroups);
+        return hipGetLastError();
+    }
+    int nslabs = 1;
+    int64_t width = a.n > 0 ? a.n : 1;
+    int32_t *bnd = static_cast<int32_t *>(a.ws);
+    if (a.variant == SPK_VAR_SLAB) {
+        const SlabLayout L = slab_layout(a.m, a.n, a.chunk);
+        nslabs = static_cast<int>(L.nslabs);
+        width = L.width;
+    }
+    if (nslabs > 1) {
+        hipError_t e = slab_bounds_launch(a.m, a.rp, a.ci, width, nslabs, bnd, s);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t nb = (a.m + GPB - 1) / GPB;
+    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    for (int sl = 0; sl < nslabs; ++sl) {
+        hipLaunchKernelGGL((sddmm_rows_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
+                           dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.rp, bnd, nslabs, sl, a.ci,
+                           static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
+                           static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename TUV, typename TV, int VW, int LANES, bool OFF32>
 static hipError_t dispatch_ns(const SddmmArgs &a, hipStream_t s) {
     const int64_t ns = (a.K + LANES * VW - 1) / (LANES * VW);
-    if (ns <= 1) return launch_sddmm<TUV, TV, VW, LANES, 1>(a, s);
-    if (ns <= 2) return launch_sddmm<TUV, TV, VW, LANES, 2>(a, s);
-    if (ns <= 4) return launch_sddmm<TUV, TV, VW, LANES, 4>(a, s);
-    if (ns <= 8) return launch_sddmm<TUV, TV, VW, LANES, 8>(a, s);
+    if (ns <= 1) return launch<TUV, TV, VW, LANES, 1, OFF32>(a, s);
+    if (ns <= 2) return launch<TUV, TV, VW, LANES, 2, OFF32>(a, s);
+    if (ns <= 4) return launch<TUV, TV, VW, LANES, 4, OFF32>(a, s);
+    if (ns <= 8) return launch<TUV, TV, VW, LANES, 8, OFF32>(a, s);
     return hipErrorInvalidValue;
 }
 
-template <typename TUV, typename TV, int VW>
+template <typename TUV, typename TV, int VW, bool OFF32>
 static hipError_t dispatch_lanes(const SddmmArgs &a, hipStream_t s) {
     switch (a.lanes) {
-    case 4: return dispatch_ns<TUV, TV, VW, 4>(a, s);
-    case 8: return dispatch_ns<TUV, TV, VW, 8>(a, s);
-    case 16: return dispatch_ns<TUV, TV, VW, 16>(a, s);
-    case 32: return dispatch_ns<TUV, TV, VW, 32>(a, s);
-    case 64: return dispatch_ns<TUV, TV, VW, 64>(a, s);
+    case 4: return dispatch_ns<TUV, TV, VW, 4, OFF32>(a, s);
+    case 8: return dispatch_ns<TUV, TV, VW, 8, OFF32>(a, s);
+    case 16: return dispatch_ns<TUV, TV, VW, 16, OFF32>(a, s);
+    case 32: return dispatch_ns<TUV, TV, VW, 32, OFF32>(a, s);
+    case 64: return dispatch_ns<TUV, TV, VW, 64, OFF32>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
+template <typename TUV, typename TV, int VW>
+static hipError_t dispatch_off(const SddmmArgs &a, hipStream_t s) {
+    const bool off32 = static_cast<uint64_t>(a.n) * static_cast<uint64_t>(a.ldv) < (1ull << 32);
+    return off32 ? dispatch_lanes<TUV, TV, VW, true>(a, s) : dispatch_lanes<TUV, TV, VW, false>(a, s);
+}
+
 hipError_t sddmm_launch(const SddmmArgs &a, hipStream_t s) {
     switch (a.uv_dtype) {
-    case SPK_F32: return a.vec > 1 ? dispatch_lanes<float, float, 4>(a, s) : dispatch_lanes<float, float, 1>(a, s);
-    case SPK_BF16: return a.vec > 1 ? dispatch_lanes<bf16, float, 4>(a, s) : dispatch_lanes<bf16, float, 1>(a, s);
-    case SPK_F64: return a.vec > 1 ? dispatch_lanes<double, double, 2>(a, s) : dispatch_lanes<double, double, 1>(a, s);
+    case SPK_F32: return a.vec > 1 ? dispatch_off<float, float, 4>(a, s) : dispatch_off<float, float, 1>(a, s);
+    case SPK_BF16: return a.vec > 1 ? dispatch_off<bf16, float, 4>(a, s) : dispatch_off<bf16, float, 1>(a, s);
+    case SPK_F64: return a.vec > 1 ? dispatch_off<double, double, 2>(a, s) : dispatch_off<double, double, 1>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -99,6 +99,12 @@ static hipError_t exclusive_scan(int32_t *data, int64_t count, char *ws, hipStre
     return hipGetLastError();
 }
 
+size_t scan_ws_bytes_i32(int64_t count) { return scan_ws_bytes(count); }
+
+hipError_t exclusive_scan_i32(int32_t *data, int64_t count, void *ws, hipStream_t s) {
+    return exclusive_scan(data, count, static_cast<char *>(ws), s);
+}
+
 // ---------------------------------------------------------------- histogram
 __global__ void column_count_kernel(int64_t nnz, const int32_t *__restrict__ ci, int32_t *__restrict__ cnt) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -13,7 +13,8 @@ from spk_testutil import TOL_F32, TOL_F64, assert_within, host_csr
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-SPMM_PLANS = [(v, l) for v in (0, 1) for l in (4, 8, 16, 32, 64)]
+SPMM_PLANS = [(v, l) for v in (0, 1, 3) for l in (4, 8, 16, 32, 64)]
+CHUNK = {0: 0, 1: 96, 3: 100}  # merge: entries + rows per group; slab: columns per slab
 
 
 @pytest.fixture(scope="module")
@@ -58,9 +59,12 @@ def test_spmm_config1_every_plan(spk, variant, lanes):
     A, v, B, _ = problem(1024, 1024, 0.1, 64, 0)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
     for flags in (0, 1):
-        plan = spk.Plan(variant, lanes, 0 if variant == 0 else 96, flags)
+        plan = spk.Plan(variant, lanes, CHUNK[variant], flags)
         C = run_spmm(spk, A, v, B, plan)
         assert_within(C, C64, M, TOL_F32, f"spmm {plan.name()}")
+    if variant == 3:  # default slab width (one slab here) and a width of 1 column
+        for chunk in (0, 1):
+            assert_within(run_spmm(spk, A, v, B, spk.Plan(3, lanes, chunk)), C64, M, TOL_F32, f"slab c{chunk}")
 
 
 @pytest.mark.parametrize("m,n,d,K", [(1000, 777, 0.02, 1), (333, 1000, 0.05, 3), (517, 517, 0.03, 36),
@@ -69,7 +73,7 @@ def test_spmm_config1_every_plan(spk, variant, lanes):
 def test_spmm_ragged_shapes(spk, m, n, d, K):
     A, v, B, _ = problem(m, n, d, K, 3)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
-    for plan in (None, spk.Plan(1, 8, 64), spk.Plan(0, 64)):
+    for plan in (None, spk.Plan(1, 8, 64), spk.Plan(0, 64), spk.Plan(3, 16, 128)):
         C = run_spmm(spk, A, v, B, plan)
         assert_within(C, C64, M, TOL_F32, f"spmm {m}x{n} K={K} {plan}")
 
@@ -79,7 +83,7 @@ def test_spmm_pattern_mode_and_empty_rows(spk):
     A = host_csr(6, 9, [[], [0, 4, 8], [2], [], [], [1, 2, 3, 4, 5, 6, 7]])
     B = synth.normal((9, 20), 1, synth.S_B)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, None, B)
-    for plan in (None, spk.Plan(1, 4, 3), spk.Plan(1, 8, 1), spk.Plan(0, 4)):
+    for plan in (None, spk.Plan(1, 4, 3), spk.Plan(1, 8, 1), spk.Plan(0, 4), spk.Plan(3, 4, 2)):
         C = run_spmm(spk, A, None, B, plan, pattern=True)
         assert_within(C, C64, M, TOL_F32, "pattern")
         assert not C[[0, 3, 4]].any()
@@ -93,7 +97,7 @@ def test_spmm_special_cases_bit_exact(spk):
     pi = np.random.default_rng(0).permutation(n).astype(np.int32)
     perm = synth.HostCSR(n, n, np.arange(n + 1, dtype=np.int32), pi)
     dvals = synth.normal(n, 2, synth.S_VALS)
-    for plan in (None, spk.Plan(1, 16, 7), spk.Plan(0, 4, 0, 1)):
+    for plan in (None, spk.Plan(1, 16, 7), spk.Plan(0, 4, 0, 1), spk.Plan(3, 16, 256)):
         assert np.array_equal(run_spmm(spk, eye, np.ones(n, np.float32), B, plan), B)
         assert np.array_equal(run_spmm(spk, perm, None, B, plan, pattern=True), B[pi])
         C = run_spmm(spk, eye, dvals, B, plan)
@@ -134,13 +138,13 @@ def test_spmm_strided_operands(spk):
 def test_spmm_structured_patterns(spk, kind, n, d):
     A, v, B, _ = problem(n, n, d, 64, 5, kind)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
-    for plan in (None, spk.Plan(1, 16), spk.Plan(1, 64, 256), spk.Plan(0, 8)):
+    for plan in (None, spk.Plan(1, 16), spk.Plan(1, 64, 256), spk.Plan(0, 8), spk.Plan(3, 16, 1000)):
         assert_within(run_spmm(spk, A, v, B, plan), C64, M, TOL_F32, f"{kind} {plan}")
 
 
 def test_spmm_deterministic(spk):
     A, v, B, _ = problem(3000, 3000, 16, 128, 6, "powerlaw")
-    for plan in (spk.Plan(0, 32), spk.Plan(1, 32, 100)):
+    for plan in (spk.Plan(0, 32), spk.Plan(1, 32, 100), spk.Plan(3, 32, 300)):
         c1 = run_spmm(spk, A, v, B, plan)
         c2 = run_spmm(spk, A, v, B, plan)
         assert np.array_equal(c1.view(np.uint32), c2.view(np.uint32))
@@ -154,14 +158,15 @@ def run_sddmm(spk, A, v, U, V, plan=None, pattern=False):
     return S.cpu().numpy()
 
 
+@pytest.mark.parametrize("variant", [0, 1, 3])
 @pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
-def test_sddmm_config1_every_plan(spk, lanes):
-    """1024 x 1024 at 90% sparsity, U, V 1024 x 64, seed 0."""
+def test_sddmm_config1_every_plan(spk, variant, lanes):
+    """1024 x 1024 at 90% sparsity, U, V 1024 x 64, seed 0: rows, entry-split, slab."""
     A, v, V, U = problem(1024, 1024, 0.1, 64, 0)
     S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
     for chunk in (0, 5, 1000):
         for flags in (0, 1):
-            plan = spk.Plan(0, lanes, chunk, flags)
+            plan = spk.Plan(variant, lanes, chunk, flags)
             if -(-64 // (lanes * (1 if flags else 4))) > 8:
                 # more than 8 register slices per lane: the plan is refused before launch
                 with pytest.raises(spk.SpkError) as e:
@@ -185,14 +190,14 @@ def test_sddmm_ragged_and_pattern(spk, m, n, d, K):
 def test_sddmm_powerlaw_and_empty_rows(spk):
     A, v, V, U = problem(20000, 20000, 16, 64, 8, "powerlaw")
     S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
-    for plan in (None, spk.Plan(0, 16, 64), spk.Plan(0, 4, 1024)):
+    for plan in (None, spk.Plan(1, 16, 64), spk.Plan(1, 4, 1024), spk.Plan(0, 8), spk.Plan(3, 16, 3000)):
         assert_within(run_sddmm(spk, A, v, U, V, plan), S64, M, TOL_F32, f"powerlaw {plan}")
     E = host_csr(7, 5, [[], [], [1, 3], [], [0, 1, 2, 3, 4], [], [4]])
     Ue = synth.normal((7, 12), 1, synth.S_U)
     Ve = synth.normal((5, 12), 1, synth.S_V)
     ve = synth.normal(E.nnz, 1, synth.S_VALS)
     S64, M = oracle.sddmm(E.row_ptr, E.col_idx, ve, Ue, Ve)
-    for plan in (None, spk.Plan(0, 4, 1), spk.Plan(0, 4, 3)):
+    for plan in (None, spk.Plan(1, 4, 1), spk.Plan(1, 4, 3), spk.Plan(0, 4), spk.Plan(3, 4, 2)):
         assert_within(run_sddmm(spk, E, ve, Ue, Ve, plan), S64, M, TOL_F32, "empty rows")
 
 
