@@ -70,7 +70,8 @@ enum spk_op {
     SPK_OP_SDDMM = 1,     /* sddmm_csr */
     SPK_OP_BACKWARD = 2,  /* spmm_csr_backward (the plan applies to A^T G) */
     SPK_OP_TRANSPOSE = 3, /* csr_transpose (plan ignored) */
-    SPK_OP_BSR4 = 4       /* csr_to_bsr4_count (plan and K ignored) */
+    SPK_OP_BSR4 = 4,      /* csr_to_bsr4_count (plan and K ignored) */
+    SPK_OP_SELECT = 5     /* plan_select and csr_features (plan and K ignored) */
 };
 
 /* A sparse matrix in CSR form. */
@@ -198,6 +199,81 @@ int32_t csr_to_bsr4_fill(const spk_csr *A, const int32_t *b_row_ptr, int32_t *b_
  * zeros add nothing. */
 int32_t spmm_bsr4(const spk_bsr4 *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C,
                   int64_t ldc, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned plan selection.  Not in the paper: the paper's kernels expose
+ * compile-time tile parameters (rows buffered per chunk, columns per worker
+ * row, Section III-A and IV-C) chosen by sweeping; here a small network maps
+ * sparsity features to the fastest plan and an exhaustive timed search is
+ * the fallback and the judge.
+ * ------------------------------------------------------------------------ */
+
+/* Number of plans in an op's plan list (SPK_OP_SPMM: 16, SPK_OP_SDDMM: 15),
+ * or 0 for other ops. */
+int32_t plan_count(int32_t op);
+
+/* Plan `index` of an op's plan list: index = 5 v + l picks variant v (ROWS,
+ * MERGE, SLAB) and lanes 4 << l; SpMM index 15 is SPK_VAR_BSR4 (lanes 64).
+ * SDDMM MERGE plans use 256 entries per group.  *valid is 1 when the plan
+ * suits dense width K (lanes not wider than twice K rounded up to a power
+ * of two, at least 16; SDDMM: at most 8 register slices).  Host only. */
+int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid);
+
+/* Integer structural features of A into features (device, 28 int64):
+ *   0 m, 1 n, 2 nnz, 3..22 row-length histogram (bin 0 empty rows, bin b in
+ *   1..18 lengths in [2^(b-1), 2^b), bin 19 lengths >= 2^18), 23 max row
+ *   length, 24 sum of squared row lengths, 25 max |i - j| over entries,
+ *   26 sum of |i - j|, 27 number of aligned 4x4 blocks holding an entry.
+ * ws    spk_workspace_bytes(SPK_OP_SELECT, ...) bytes. */
+int32_t csr_features(const spk_csr *A, int64_t *features, void *ws, size_t ws_bytes, void *stream);
+
+/* The 32 network inputs from features (device, 28) and K, into x (device, 32):
+ *   x0 log2(1+m)/20, x1 log2(1+n)/20, x2 log2(1+nnz)/30, x3..x22 fraction of
+ *   rows per length bin, x23 log2(1+max len)/20, x24 log2(1+mean len)/20,
+ *   x25 log2(1+cv)/4 (cv: std / mean of row lengths), x26 log2(1+max|i-j|)/20,
+ *   x27 mean |i-j| / n, x28 nnz / (16 blocks), x29 log2(K)/8,
+ *   x30 1 + log10(density)/5, x31 1.  Binary32 arithmetic. */
+int32_t selector_inputs(const int64_t *features, int64_t K, float *x, void *stream);
+
+/* Network y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 for `batch` rows of X
+ * (device [batch x F]) into Y (device [batch x P]).  params (device) holds
+ * W1[H][F], b1[H], W2[H][H], b2[H], W3[P][H], b3[P] contiguously.
+ * F <= 64, H <= 128, P <= 32. */
+int32_t mlp_forward(const float *params, int64_t F, int64_t H, int64_t P, const float *X, int64_t batch,
+                    float *Y, void *stream);
+
+/* Scratch bytes of mlp_loss_grad for these sizes. */
+size_t mlp_workspace_bytes(int64_t F, int64_t H, int64_t P, int64_t batch);
+
+/* Masked mean squared error L = sum mask (y - T)^2 / (2 count) (count = number
+ * of nonzero mask entries) and its gradient with respect to params (same
+ * layout) for a batch: X [batch x F], T and mask [batch x P], all device.
+ * loss: device, 1 float.  Gradients are summed over samples in order (the
+ * result does not vary between runs). */
+int32_t mlp_loss_grad(const float *params, int64_t F, int64_t H, int64_t P, const float *X, const float *T,
+                      const float *mask, int64_t batch, float *grads, float *loss, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba, Algorithm 1) on `count` parameters (device):
+ * mom = b1 mom + (1-b1) g, vel = b2 vel + (1-b2) g^2,
+ * params -= lr (mom / (1-b1^step)) / (sqrt(vel / (1-b2^step)) + eps). */
+int32_t adam_update(float *params, const float *grads, float *mom, float *vel, int64_t count, float lr,
+                    float beta1, float beta2, float eps, int64_t step, void *stream);
+
+/* Load a trained selector for op (SPK_OP_SPMM or SPK_OP_SDDMM) on the current
+ * device from host memory: mean[F], scale[F] (inputs are standardised as
+ * (x - mean) / scale), then the F x H x P parameters as for mlp_forward.
+ * F must be 32 and P the op's plan count.  Synchronous; copies into a static
+ * table of the library (no allocation). */
+int32_t selector_load(int32_t op, const float *table, int64_t F, int64_t H, int64_t P);
+
+/* Learned plan for op on A with dense width K: features, inputs, network and
+ * the argmin of its outputs over the plans valid for K, all on the device.
+ * Synchronises `stream` to return the plan in *out.  SPK_ERR_NO_MODEL when
+ * no selector is loaded for op on this device (callers then fall back to a
+ * timed search).  ws: spk_workspace_bytes(SPK_OP_SELECT, ...) bytes. */
+int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void *ws, size_t ws_bytes,
+                    void *stream);
 
 /* Opt-in O(nnz) structural check of A (canonical CSR as described above).
  * ws    at least 16 bytes.  Synchronises `stream`.  Returns SPK_OK or

@@ -65,6 +65,8 @@ def _load():
     lib.oracle_mlp_loss_grad.restype = dbl
     lib.oracle_adam.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i64]
     lib.oracle_adam.restype = None
+    lib.oracle_selector_inputs.argtypes = [vp, i64, vp]
+    lib.oracle_selector_inputs.restype = None
     _lib = lib
     return lib
 
@@ -160,6 +162,18 @@ def features(row_ptr, col_idx, n: int) -> np.ndarray:
     f = np.zeros(NFEAT, np.int64)
     lib.oracle_features(rp.shape[0] - 1, n, _p(rp), _p(ci), _p(f))
     return f
+
+
+NIN = 32
+
+
+def selector_inputs(f, K: int) -> np.ndarray:
+    """The 32 scaled selector inputs of integer features f and width K (see oracle.c)."""
+    lib = _load()
+    f64 = np.ascontiguousarray(f, dtype=np.int64)
+    x = np.empty(NIN, np.float64)
+    lib.oracle_selector_inputs(_p(f64), int(K), _p(x))
+    return x
 
 
 def csr_to_bsr4(row_ptr, col_idx, vals, n: int):

@@ -213,6 +213,43 @@ void oracle_features(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t
 }
 
 /* ---------------------------------------------------------------------- */
+/* Selector inputs: 32 numbers derived from the integer features f and the  */
+/* dense width K, each scaled to roughly [0, 1]:                           */
+/*   x0 log2(1+m)/20, x1 log2(1+n)/20, x2 log2(1+nnz)/30,                  */
+/*   x3..x22 fraction of rows in each row-length bin,                      */
+/*   x23 log2(1+max len)/20, x24 log2(1+mean len)/20 (mean = nnz/m),       */
+/*   x25 log2(1+cv)/4, cv = sqrt(max(0, E[L^2] - mean^2)) / mean,          */
+/*   x26 log2(1+max |i-j|)/20, x27 mean |i-j| / n,                         */
+/*   x28 block fill nnz / (16 * blocks), x29 log2(K)/8,                    */
+/*   x30 1 + log10(nnz / (m n)) / 5, x31 = 1.                              */
+/* Empty denominators count as 1.                                          */
+/* ---------------------------------------------------------------------- */
+#define ORACLE_NIN 32
+int oracle_input_count(void) { return ORACLE_NIN; }
+
+void oracle_selector_inputs(const int64_t *f, int64_t K, double *x) {
+    double m = (double)f[0], n = (double)f[1], nnz = (double)f[2];
+    double md = m > 0 ? m : 1.0, nd = n > 0 ? n : 1.0, zd = nnz > 0 ? nnz : 1.0;
+    x[0] = log2(1.0 + m) / 20.0;
+    x[1] = log2(1.0 + n) / 20.0;
+    x[2] = log2(1.0 + nnz) / 30.0;
+    for (int b = 0; b < 20; ++b) x[3 + b] = (double)f[3 + b] / md;
+    double mean = nnz / md;
+    x[23] = log2(1.0 + (double)f[23]) / 20.0;
+    x[24] = log2(1.0 + mean) / 20.0;
+    double var = (double)f[24] / md - mean * mean;
+    double cv = mean > 0 ? sqrt(var > 0 ? var : 0.0) / mean : 0.0;
+    x[25] = log2(1.0 + cv) / 4.0;
+    x[26] = log2(1.0 + (double)f[25]) / 20.0;
+    x[27] = ((double)f[26] / zd) / nd;
+    x[28] = nnz / (16.0 * (f[27] > 0 ? (double)f[27] : 1.0));
+    x[29] = log2((double)(K > 0 ? K : 1)) / 8.0;
+    double dens = nnz / (md * nd);
+    x[30] = 1.0 + log10(dens > 1e-12 ? dens : 1e-12) / 5.0;
+    x[31] = 1.0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* CSR -> 4x4 block CSR.  Block (I, J) exists when any entry (i, j) has     */
 /* i/4 == I and j/4 == J.  Block values are dense row-major 4x4 tiles with   */
 /* zeros where A has no entry; block columns ascend within a block row.     */

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libspk.so")
 # enum spk_dtype
 F32, BF16, F64 = 0, 1, 2
 # enum spk_op
-OP_SPMM, OP_SDDMM, OP_BACKWARD, OP_TRANSPOSE, OP_BSR4 = 0, 1, 2, 3, 4
+OP_SPMM, OP_SDDMM, OP_BACKWARD, OP_TRANSPOSE, OP_BSR4, OP_SELECT = 0, 1, 2, 3, 4, 5
 # enum spk_variant
 VAR_ROWS, VAR_MERGE, VAR_BSR4, VAR_SLAB = 0, 1, 2, 3
 
@@ -68,6 +68,17 @@ SIGNATURES = {
     "csr_to_bsr4_count": ([_CSR_P, _P, ctypes.POINTER(ctypes.c_int64), _P, _SZ, _P], _I32),
     "csr_to_bsr4_fill": ([_CSR_P, _P, _P, _P, _P], _I32),
     "spmm_bsr4": ([ctypes.POINTER(spk_bsr4), _P, _I64, _I32, _I64, _P, _I64, _P], _I32),
+    "plan_count": ([_I32], _I32),
+    "plan_of_index": ([_I32, _I32, _I64, _PLAN_P, ctypes.POINTER(_I32)], _I32),
+    "csr_features": ([_CSR_P, _P, _P, _SZ, _P], _I32),
+    "selector_inputs": ([_P, _I64, _P, _P], _I32),
+    "mlp_forward": ([_P, _I64, _I64, _I64, _P, _I64, _P, _P], _I32),
+    "mlp_workspace_bytes": ([_I64, _I64, _I64, _I64], _SZ),
+    "mlp_loss_grad": ([_P, _I64, _I64, _I64, _P, _P, _P, _I64, _P, _P, _P, _SZ, _P], _I32),
+    "adam_update": ([_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I64,
+                     _P], _I32),
+    "selector_load": ([_I32, _P, _I64, _I64, _I64], _I32),
+    "plan_select": ([_CSR_P, _I64, _I32, _PLAN_P, _P, _SZ, _P], _I32),
 }
 
 _lib = None

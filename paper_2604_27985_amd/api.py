@@ -113,6 +113,15 @@ class CSR:
             self._transpose = csr_transpose(self)
         return self._transpose
 
+    def block_form(self, vals: torch.Tensor | None = None) -> "BSR4":
+        """4x4 block form for these values, built on the GPU once and cached."""
+        v = self.vals if vals is None else vals
+        key = None if v is None else (v.data_ptr(), v._version)
+        cache = getattr(self, "_bsr4", None)
+        if cache is None or cache[0] != key:
+            self._bsr4 = (key, csr_to_bsr4(self, vals))
+        return self._bsr4[1]
+
 
 def workspace_bytes(op: int, A: CSR, K: int, plan: Plan | None = None) -> int:
     lib = _lib.load()
@@ -140,6 +149,9 @@ def spmm(A: CSR, B: torch.Tensor, plan: Plan | None = None, out: torch.Tensor | 
     odt = torch.float64 if B.dtype == torch.float64 else torch.float32
     C = out if out is not None else torch.empty((A.m, K), dtype=odt, device=B.device)
     _rowmajor(C, "C")
+    if plan is not None and plan.variant == _lib.VAR_BSR4:
+        # the block form is per-pattern (and per-values) preprocessing, cached on A
+        return spmm_bsr4(A.block_form(vals), B, out=C)
     ca = A.c(vals)
     cp = plan.c() if plan is not None else None
     ws, nb = (workspace, workspace.numel()) if workspace is not None else _workspace(OP_SPMM, A, K, plan, B.device)

@@ -47,7 +47,13 @@ def sddmm_plans(K: int, dtype: torch.dtype = torch.float32) -> list[api.Plan]:
 
 
 def plans_for(op: int, K: int, dtype: torch.dtype = torch.float32) -> list[api.Plan]:
-    return spmm_plans(K, dtype) if op == OP_SPMM else sddmm_plans(K, dtype)
+    """The op's plan list (as the selector sees it) restricted to plans valid for K;
+    F64 operands use their own vector width and have no block form."""
+    if dtype == torch.float64:
+        return spmm_plans(K, dtype) if op == OP_SPMM else sddmm_plans(K, dtype)
+    from . import selector
+
+    return [p for p, ok in selector.plan_list(op, K) if ok]
 
 
 def time_plan(A: api.CSR, K: int, op: int, plan: api.Plan | None, B=None, U=None, V=None, reps: int = 5,

@@ -177,6 +177,8 @@ size_t spk_workspace_bytes(int32_t op, const spk_csr *A, int64_t K, const spk_pl
         return sddmm_ws(m, n, r);
     case SPK_OP_TRANSPOSE: return transpose_ws_bytes(A->m, A->n, A->nnz);
     case SPK_OP_BSR4: return scan_ws_bytes_i32((A->m + 3) / 4 + 1);
+    case SPK_OP_SELECT:
+        return align_up(sizeof(int64_t) * 28) + align_up(sizeof(int32_t) * 4) + features_ws_bytes(A->m);
     default: return 0;
     }
 }
@@ -316,6 +318,122 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
         if ((st = hip_status(sddmm_launch(a, s)))) return st;
     }
     return SPK_OK;
+}
+
+// ---------------------------------------------------------------- selector
+static constexpr int kMaxDevices = 64;
+static int32_t g_loaded[kMaxDevices][2];
+static int64_t g_dims[kMaxDevices][2][3];
+
+static int current_device() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kMaxDevices) return -1;
+    return d;
+}
+
+int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 16 : op == SPK_OP_SDDMM ? 15 : 0; }
+
+int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid) {
+    if (!out) return SPK_ERR_NULL;
+    if (op != SPK_OP_SPMM && op != SPK_OP_SDDMM) return SPK_ERR_OP;
+    if (index < 0 || index >= plan_count(op)) return SPK_ERR_PLAN;
+    if (op == SPK_OP_SPMM && index == 15) {
+        *out = spk_plan{SPK_VAR_BSR4, 64, 0, 0};
+    } else {
+        static const int32_t variants[3] = {SPK_VAR_ROWS, SPK_VAR_MERGE, SPK_VAR_SLAB};
+        const int32_t v = variants[index / 5];
+        const int32_t chunk = (op == SPK_OP_SDDMM && v == SPK_VAR_MERGE) ? 256 : 0;
+        *out = spk_plan{v, 4 << (index % 5), chunk, 0};
+    }
+    if (valid) *valid = plan_valid_host(op, index, K) ? 1 : 0;
+    return SPK_OK;
+}
+
+int32_t csr_features(const spk_csr *A, int64_t *features, void *ws, size_t ws_bytes, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (!features) return SPK_ERR_NULL;
+    if ((st = check_ws(features_ws_bytes(A->m), ws, ws_bytes))) return st;
+    return hip_status(features_launch(A->m, A->n, A->nnz, A->row_ptr, A->col_idx, features, ws,
+                                      static_cast<hipStream_t>(stream)));
+}
+
+int32_t selector_inputs(const int64_t *features, int64_t K, float *x, void *stream) {
+    if (!features || !x) return SPK_ERR_NULL;
+    if (K < 0) return SPK_ERR_SIZE;
+    return hip_status(inputs_launch(features, K, x, static_cast<hipStream_t>(stream)));
+}
+
+int32_t mlp_forward(const float *params, int64_t F, int64_t H, int64_t P, const float *X, int64_t batch, float *Y,
+                    void *stream) {
+    if (!mlp_dims_ok(F, H, P) || batch < 0 || batch > kMaxIndex) return SPK_ERR_SIZE;
+    if (batch > 0 && (!params || !X || !Y)) return SPK_ERR_NULL;
+    return hip_status(mlp_forward_launch(params, F, H, P, X, batch, Y, static_cast<hipStream_t>(stream)));
+}
+
+size_t mlp_workspace_bytes(int64_t F, int64_t H, int64_t P, int64_t batch) {
+    if (!mlp_dims_ok(F, H, P) || batch < 0) return 0;
+    return mlp_train_ws_bytes(F, H, P, batch);
+}
+
+int32_t mlp_loss_grad(const float *params, int64_t F, int64_t H, int64_t P, const float *X, const float *T,
+                      const float *mask, int64_t batch, float *grads, float *loss, void *ws, size_t ws_bytes,
+                      void *stream) {
+    if (!mlp_dims_ok(F, H, P) || batch < 0 || batch > kMaxIndex) return SPK_ERR_SIZE;
+    if (!params || !grads || !loss || (batch > 0 && (!X || !T || !mask))) return SPK_ERR_NULL;
+    int32_t st = check_ws(mlp_train_ws_bytes(F, H, P, batch), ws, ws_bytes);
+    if (st) return st;
+    return hip_status(
+        mlp_loss_grad_launch(params, F, H, P, X, T, mask, batch, grads, loss, ws, static_cast<hipStream_t>(stream)));
+}
+
+int32_t adam_update(float *params, const float *grads, float *mom, float *vel, int64_t count, float lr, float beta1,
+                    float beta2, float eps, int64_t step, void *stream) {
+    if (count < 0 || step < 1) return SPK_ERR_SIZE;
+    if (count > 0 && (!params || !grads || !mom || !vel)) return SPK_ERR_NULL;
+    return hip_status(adam_launch(params, grads, mom, vel, count, lr, beta1, beta2, eps, step,
+                                  static_cast<hipStream_t>(stream)));
+}
+
+int32_t selector_load(int32_t op, const float *table, int64_t F, int64_t H, int64_t P) {
+    if (op != SPK_OP_SPMM && op != SPK_OP_SDDMM) return SPK_ERR_OP;
+    if (!table) return SPK_ERR_NULL;
+    if (F != 32 || !mlp_dims_ok(F, H, P) || P != plan_count(op)) return SPK_ERR_SIZE;
+    const int dev = current_device();
+    if (dev < 0) return SPK_ERR_HIP;
+    int32_t st = hip_status(selector_table_load(op, table, F, H, P));
+    if (st) return st;
+    g_loaded[dev][op] = 1;
+    g_dims[dev][op][0] = F;
+    g_dims[dev][op][1] = H;
+    g_dims[dev][op][2] = P;
+    return SPK_OK;
+}
+
+int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void *ws, size_t ws_bytes, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (!out) return SPK_ERR_NULL;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (op != SPK_OP_SPMM && op != SPK_OP_SDDMM) return SPK_ERR_OP;
+    const int dev = current_device();
+    if (dev < 0) return SPK_ERR_HIP;
+    if (!g_loaded[dev][op]) return SPK_ERR_NO_MODEL;
+    const size_t f_bytes = align_up(sizeof(int64_t) * 28), o_bytes = align_up(sizeof(int32_t) * 4);
+    if ((st = check_ws(f_bytes + o_bytes + features_ws_bytes(A->m), ws, ws_bytes))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    int64_t *f = reinterpret_cast<int64_t *>(w);
+    int32_t *idx = reinterpret_cast<int32_t *>(w + f_bytes);
+    if ((st = hip_status(features_launch(A->m, A->n, A->nnz, A->row_ptr, A->col_idx, f, w + f_bytes + o_bytes, s))))
+        return st;
+    const int64_t *d = g_dims[dev][op];
+    if ((st = hip_status(select_launch(op, f, K, d[0], d[1], d[2], idx, s)))) return st;
+    int32_t host = -1;
+    if (hipMemcpyAsync(&host, idx, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return SPK_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPK_ERR_HIP;
+    if (host < 0) return SPK_ERR_PLAN;
+    return plan_of_index(op, host, K, out, nullptr);
 }
 
 int32_t spk_csr_validate(const spk_csr *A, void *ws, size_t ws_bytes, void *stream) {

@@ -1,0 +1,352 @@
+"""Learned plan selection: data, training and inference around the C ABI.
+
+The network, its training step (forward, hand-derived backward, Adam) and
+inference run in the library's HIP kernels; this module only organises the
+data:
+
+  specs      seeded descriptions of synthetic matrices (size, density,
+             pattern family, dense width K)
+  timings    every plan of an op timed on the GPU for each matrix (the
+             exhaustive search), appended to a resumable JSONL file
+  training   inputs standardised with the training split's mean and scale,
+             targets log(t_plan / t_best) on the valid plans, full-batch Adam
+  inference  plan_select (features -> inputs -> network -> masked argmin)
+
+The exhaustive search (autotune) stays the fallback when no model is loaded
+and is the judge of the selector's regret.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import _lib, api, synth
+from ._lib import OP_SDDMM, OP_SELECT, OP_SPMM
+
+F, H = 32, 64
+WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector_weights.json")
+PATTERNS = ("uniform", "banded", "powerlaw", "block4")
+KS = (32, 64, 128, 256)
+NNZ_CAP = 1 << 24
+
+
+# ---------------------------------------------------------------- plan lists
+def plan_count(op: int) -> int:
+    return int(_lib.load().plan_count(op))
+
+
+def plan_list(op: int, K: int) -> list[tuple[api.Plan, bool]]:
+    """[(plan, valid for K)] in the op's plan-list order (include/spk.h)."""
+    lib = _lib.load()
+    out = []
+    for i in range(plan_count(op)):
+        p = _lib.spk_plan()
+        v = ctypes.c_int32(0)
+        _lib.check(lib.plan_of_index(op, i, K, ctypes.byref(p), ctypes.byref(v)), "plan_of_index")
+        out.append((api.Plan(p.variant, p.lanes, p.chunk, p.flags), bool(v.value)))
+    return out
+
+
+# ---------------------------------------------------------------- specs
+def sample_spec(index: int, cap: int = NNZ_CAP) -> dict:
+    """Matrix `index` of the selector set: n log-uniform in [4096, 524288] (multiple
+    of 64), density log-uniform in [1e-4, 0.1] (redrawn while the expected entry
+    count exceeds `cap`), pattern and K uniform."""
+    rng = np.random.default_rng([2604, 27985, index])
+    pattern = PATTERNS[int(rng.integers(len(PATTERNS)))]
+    K = KS[int(rng.integers(len(KS)))]
+    while True:  # redraw (n, density) until the expected entry count fits the cap
+        n = int(round(math.exp(rng.uniform(math.log(4096), math.log(524288))) / 64) * 64)
+        d = math.exp(rng.uniform(math.log(1e-4), math.log(0.1)))
+        if expected_nnz(n, d, pattern) <= cap:
+            break
+    return {"index": index, "n": n, "density": d, "pattern": pattern, "K": K, "seed": index,
+            "split": "test" if index % 5 == 0 else "train"}
+
+
+def expected_nnz(n: int, d: float, pattern: str) -> float:
+    if pattern == "banded":
+        return n * 129 * min(1.0, d * n / 129)
+    if pattern == "powerlaw":
+        return n * max(1.0, d * n)
+    return d * n * n
+
+
+def make_matrix(spec: dict):
+    """Host CSR and values of a spec (banded: in-band probability min(1, d n / 129);
+    power-law: Zipf 2.1 degrees with mean max(1, d n))."""
+    n, d, seed, pat = spec["n"], spec["density"], spec["seed"], spec["pattern"]
+    if pat == "uniform":
+        A = synth.bernoulli(n, n, d, seed)
+    elif pat == "banded":
+        A = synth.bernoulli(n, n, min(1.0, d * n / 129), seed, band=64)
+    elif pat == "powerlaw":
+        A = synth.powerlaw(n, min(float(n), max(1.0, d * n)), 2.1, seed)
+    else:
+        A = synth.block4(n, n, d, seed)
+    return A, synth.normal(A.nnz, seed, synth.S_VALS)
+
+
+# ---------------------------------------------------------------- features
+def features(A: api.CSR) -> torch.Tensor:
+    """Integer features (device int64[28]) from the GPU feature kernels."""
+    lib = _lib.load()
+    dev = A.row_ptr.device
+    f = torch.empty(28, dtype=torch.int64, device=dev)
+    nb = api.workspace_bytes(OP_SELECT, A, 0)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    ca = A.c(use_vals=False)
+    _lib.check(lib.csr_features(ctypes.byref(ca), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb,
+                                api._stream()), "csr_features")
+    return f
+
+
+def inputs(f: torch.Tensor, K: int) -> torch.Tensor:
+    """The 32 network inputs (device float32) of features f and width K."""
+    lib = _lib.load()
+    x = torch.empty(F, dtype=torch.float32, device=f.device)
+    _lib.check(lib.selector_inputs(ctypes.c_void_p(f.data_ptr()), K, ctypes.c_void_p(x.data_ptr()), api._stream()),
+               "selector_inputs")
+    return x
+
+
+# ---------------------------------------------------------------- timings
+def time_plans(A: api.CSR, K: int, op: int, reps: int = 3, warmup: int = 1) -> list[float | None]:
+    """Median ms of every plan of the op's list (None where invalid for K)."""
+    from . import autotune
+
+    dev = A.row_ptr.device
+    B = torch.randn(A.n, K, device=dev)
+    U = torch.randn(A.m, K, device=dev) if op == OP_SDDMM else None
+    out = []
+    for plan, valid in plan_list(op, K):
+        if not valid:
+            out.append(None)
+            continue
+        if plan.variant == _lib.VAR_BSR4:
+            A.block_form()  # conversion is per-pattern preprocessing, not timed
+        out.append(autotune.time_plan(A, K, op, plan, B=B, U=U, V=B, reps=reps, warmup=warmup))
+    return out
+
+
+def build_timings(path: str, count: int = 2000, start: int = 0, ops=(OP_SPMM, OP_SDDMM), log=print,
+                  time_budget_s: float | None = None) -> int:
+    """Append one record per spec index in [start, count) not yet in `path`."""
+    done = set()
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                done.add(json.loads(line)["index"])
+    t0 = time.time()
+    added = 0
+    with open(path, "a") as fh:
+        for i in range(start, count):
+            if i in done:
+                continue
+            if time_budget_s is not None and time.time() - t0 > time_budget_s:
+                break
+            spec = sample_spec(i)
+            tg = time.time()
+            A, v = make_matrix(spec)
+            dA = api.CSR.from_host(A, v)
+            f = features(dA)
+            rec = dict(spec, nnz=A.nnz, features=f.cpu().tolist(), gen_s=round(time.time() - tg, 3))
+            for op in ops:
+                rec["ms_" + ("spmm" if op == OP_SPMM else "sddmm")] = time_plans(dA, spec["K"], op)
+            fh.write(json.dumps(rec) + "\n")
+            fh.flush()
+            added += 1
+            log(f"[{i}] {spec['pattern']} n={spec['n']} nnz={A.nnz} K={spec['K']} "
+                f"best spmm {min(t for t in rec['ms_spmm'] if t is not None):.4f} ms ({time.time() - t0:.0f} s)")
+            del dA
+    return added
+
+
+def load_timings(path: str) -> list[dict]:
+    with open(path) as fh:
+        return [json.loads(line) for line in fh]
+
+
+# ---------------------------------------------------------------- dataset
+def dataset(records: list[dict], op: int):
+    """(X inputs [N, 32], T targets [N, P], mask [N, P], times [N, P]) for an op.
+    Inputs come from the GPU input kernel on the recorded integer features."""
+    key = "ms_spmm" if op == OP_SPMM else "ms_sddmm"
+    P = plan_count(op)
+    dev = torch.device("cuda")
+    feats = torch.tensor([r["features"] for r in records], dtype=torch.int64, device=dev)
+    X = torch.stack([inputs(feats[i].contiguous(), r["K"]) for i, r in enumerate(records)]).cpu().numpy()
+    times = np.full((len(records), P), np.nan)
+    for i, r in enumerate(records):
+        for p, t in enumerate(r[key]):
+            if t is not None and t > 0:
+                times[i, p] = t
+    mask = np.isfinite(times).astype(np.float32)
+    best = np.nanmin(times, axis=1, keepdims=True)
+    T = np.where(mask > 0, np.log(np.where(mask > 0, times, 1.0) / best), 0.0).astype(np.float32)
+    return X.astype(np.float32), T, mask, times
+
+
+# ---------------------------------------------------------------- training
+class Trainer:
+    """Full-batch training of the selector network with the library's kernels."""
+
+    def __init__(self, P: int, hidden: int = H, seed: int = 0):
+        self.P, self.H = P, hidden
+        g = torch.Generator().manual_seed(seed)
+
+        def init(o, i):  # He-uniform
+            lim = math.sqrt(6.0 / i)
+            return (torch.rand(o, i, generator=g) * 2 - 1) * lim
+
+        parts = [init(hidden, F), torch.zeros(hidden), init(hidden, hidden), torch.zeros(hidden),
+                 init(P, hidden) * 0.1, torch.zeros(P)]
+        self.params = torch.cat([t.reshape(-1) for t in parts]).cuda().contiguous()
+        self.mom = torch.zeros_like(self.params)
+        self.vel = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, device="cuda")
+        self.step_no = 0
+
+    def loss_grad(self, X: torch.Tensor, T: torch.Tensor, mask: torch.Tensor) -> float:
+        lib = _lib.load()
+        nb = lib.mlp_workspace_bytes(F, self.H, self.P, X.shape[0])
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        _lib.check(lib.mlp_loss_grad(p(self.params), F, self.H, self.P, p(X), p(T), p(mask), X.shape[0],
+                                     p(self.grads), p(self.loss), p(ws), nb, api._stream()), "mlp_loss_grad")
+        return self.loss
+
+    def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8) -> None:
+        lib = _lib.load()
+        self.step_no += 1
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        _lib.check(lib.adam_update(p(self.params), p(self.grads), p(self.mom), p(self.vel), self.params.numel(), lr,
+                                   b1, b2, eps, self.step_no, api._stream()), "adam_update")
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        lib = _lib.load()
+        Y = torch.empty((X.shape[0], self.P), dtype=torch.float32, device="cuda")
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        _lib.check(lib.mlp_forward(p(self.params), F, self.H, self.P, p(X), X.shape[0], p(Y), api._stream()),
+                   "mlp_forward")
+        return Y
+
+    def fit(self, X, T, mask, steps: int = 4000, lr: float = 3e-3, log=None) -> list[float]:
+        Xd, Td, Md = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (X, T, mask))
+        hist = []
+        for s in range(steps):
+            lr_s = lr * 0.5 * (1 + math.cos(math.pi * s / steps))  # cosine decay
+            self.loss_grad(Xd, Td, Md)
+            self.adam(max(lr_s, lr * 0.01))
+            if s % 200 == 0 or s == steps - 1:
+                hist.append(float(self.loss.item()))
+                if log:
+                    log(f"step {s} loss {hist[-1]:.5f}")
+        return hist
+
+
+def choose(Y: np.ndarray, valid: np.ndarray) -> np.ndarray:
+    """Argmin of predictions over valid plans, per row."""
+    return np.where(valid > 0, Y, np.inf).argmin(axis=1)
+
+
+def regret_stats(times: np.ndarray, pick: np.ndarray, plain_idx: np.ndarray) -> dict:
+    rows = np.arange(times.shape[0])
+    best = np.nanmin(times, axis=1)
+    t_pick = times[rows, pick]
+    t_plain = times[rows, plain_idx]
+    r = t_pick / best
+    return {"count": int(len(r)), "geomean_regret": float(np.exp(np.mean(np.log(r)))),
+            "median_regret": float(np.median(r)), "p90_regret": float(np.quantile(r, 0.9)),
+            "max_regret": float(r.max()), "total_time_ratio": float(t_pick.sum() / best.sum()),
+            "geomean_gain_over_plain": float(np.exp(np.mean(np.log(t_plain / t_pick)))),
+            "geomean_plain_regret": float(np.exp(np.mean(np.log(t_plain / best))))}
+
+
+def plain_index(op: int, K: int) -> int:
+    """Index of the plan a NULL plan runs (row-split SpMM with the smallest lanes
+    >= K/4; entry-split SDDMM with 8 lanes widened to fit K)."""
+    if op == OP_SPMM:
+        lanes = 4
+        while lanes < 64 and lanes * 4 < K:
+            lanes <<= 1
+        return int(math.log2(lanes)) - 2
+    lanes = 8
+    while lanes < 64 and -(-K // (lanes * 4)) > 8:
+        lanes <<= 1
+    return 5 + int(math.log2(lanes)) - 2
+
+
+def train_op(records: list[dict], op: int, steps: int = 4000, lr: float = 3e-3, seed: int = 0, log=None):
+    """Train on the train split, evaluate on the test split; returns (table dict, report)."""
+    X, T, mask, times = dataset(records, op)
+    split = np.array([r["split"] for r in records])
+    tr, te = split == "train", split == "test"
+    mean = X[tr].mean(0)
+    scale = X[tr].std(0)
+    scale = np.where(scale > 1e-6, scale, 1.0).astype(np.float32)
+    Xs = ((X - mean) / scale).astype(np.float32)
+    P = plan_count(op)
+    trainer = Trainer(P, seed=seed)
+    hist = trainer.fit(Xs[tr], T[tr], mask[tr], steps=steps, lr=lr, log=log)
+    Y = trainer.forward(torch.from_numpy(Xs).cuda()).cpu().numpy()
+    pick = choose(Y, mask)
+    plain = np.array([plain_index(op, r["K"]) for r in records])
+    report = {"op": "spmm" if op == OP_SPMM else "sddmm", "loss_history": hist,
+              "train": regret_stats(times[tr], pick[tr], plain[tr]),
+              "test": regret_stats(times[te], pick[te], plain[te])}
+    table = {"op": int(op), "F": F, "H": trainer.H, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
+             "params": trainer.params.cpu().tolist(), "seed": seed, "steps": steps, "lr": lr,
+             "plans": [p.name() for p, _ in plan_list(op, 64)]}
+    return table, report
+
+
+# ---------------------------------------------------------------- inference
+def load_table(table: dict) -> None:
+    lib = _lib.load()
+    host = np.ascontiguousarray(np.concatenate([table["mean"], table["scale"], table["params"]]).astype(np.float32))
+    _lib.check(lib.selector_load(table["op"], ctypes.c_void_p(host.ctypes.data), table["F"], table["H"], table["P"]),
+               "selector_load")
+
+
+_loaded = set()
+
+
+def load_default(path: str = WEIGHTS_PATH) -> bool:
+    """Load the trained tables shipped with the package (once per device)."""
+    dev = torch.cuda.current_device()
+    if dev in _loaded:
+        return True
+    if not os.path.exists(path):
+        return False
+    with open(path) as fh:
+        tables = json.load(fh)["tables"]
+    for t in tables:
+        load_table(t)
+    _loaded.add(dev)
+    return True
+
+
+def select(A: api.CSR, K: int, op: int, fallback: bool = True) -> api.Plan:
+    """Learned plan for (A, K, op) via plan_select; the timed search when no model is available."""
+    lib = _lib.load()
+    load_default()
+    nb = api.workspace_bytes(OP_SELECT, A, K)
+    ws = torch.empty(nb, dtype=torch.uint8, device=A.row_ptr.device)
+    ca = A.c(use_vals=False)
+    out = _lib.spk_plan()
+    st = lib.plan_select(ctypes.byref(ca), K, op, ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), nb,
+                         api._stream())
+    if st == -10 and fallback:
+        from . import autotune
+
+        return autotune.best_plan(A, K, op)[0]
+    _lib.check(st, "plan_select")
+    return api.Plan(out.variant, out.lanes, out.chunk, out.flags)

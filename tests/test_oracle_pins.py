@@ -268,6 +268,25 @@ def test_bsr4_reconstructs_dense():
         assert not D[m:, :].any() and not D[:, n:].any()
 
 
+def test_selector_inputs_closed_forms(golden):
+    """Hand-worked example: m=3, n=4, nnz=5, lengths (2, 0, 3), |i-j| sum 5, one block, K=64."""
+    f = golden["features"]["f"]
+    x = oracle.selector_inputs(f, 64)
+    assert x[0] == np.log2(4) / 20 and x[1] == np.log2(5) / 20 and x[2] == np.log2(6) / 30
+    assert x[3] == 1 / 3 and x[5] == 2 / 3 and x[3:23].sum() == 1.0
+    mean = 5 / 3
+    assert np.isclose(x[24], np.log2(1 + mean) / 20)
+    cv = np.sqrt(13 / 3 - mean ** 2) / mean  # lengths 2, 0, 3: E[L^2] = 13/3
+    assert np.isclose(x[25], np.log2(1 + cv) / 4)
+    assert x[26] == np.log2(4) / 20 and np.isclose(x[27], (5 / 5) / 4)
+    assert np.isclose(x[28], 5 / 16) and x[29] == 6 / 8
+    assert np.isclose(x[30], 1 + np.log10(5 / 12) / 5) and x[31] == 1.0
+    # an empty matrix gives finite inputs
+    e = np.zeros(28, np.int64)
+    e[0], e[1], e[3] = 10, 10, 10
+    assert np.isfinite(oracle.selector_inputs(e, 1)).all()
+
+
 # ---------------------------------------------------------------- mlp
 def _rand_mlp(F, H, P, seed):
     r = np.random.default_rng(seed)

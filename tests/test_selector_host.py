@@ -1,0 +1,78 @@
+"""Host-side logic of the plan selector (CPU only; the C ABI's host-only calls)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2604_27985_amd import _lib
+
+if not os.path.exists(_lib.LIB_PATH):
+    pytest.skip("libspk.so not built", allow_module_level=True)
+
+from paper_2604_27985_amd import selector  # noqa: E402
+
+
+def test_plan_lists():
+    assert selector.plan_count(_lib.OP_SPMM) == 16 and selector.plan_count(_lib.OP_SDDMM) == 15
+    pl = selector.plan_list(_lib.OP_SPMM, 64)
+    assert [p.variant for p, _ in pl[:15]] == [0] * 5 + [1] * 5 + [3] * 5 and pl[15][0].variant == 2
+    assert [p.lanes for p, _ in pl[:5]] == [4, 8, 16, 32, 64]
+    # K = 64: lanes x 4 up to 2 x 64
+    assert [ok for _, ok in pl[:5]] == [True, True, True, True, False]
+    assert all(ok for _, ok in selector.plan_list(_lib.OP_SPMM, 256)[:5])
+    sd = selector.plan_list(_lib.OP_SDDMM, 256)
+    # 4 lanes x 4 wide x 8 slices = 128 < 256
+    assert not sd[0][1] and sd[1][1]
+    assert all(p.chunk == 256 for p, _ in sd[5:10])
+
+
+def test_plain_index_matches_null_plan_rule():
+    for K in (1, 16, 32, 64, 100, 128, 256, 1024):
+        i = selector.plain_index(_lib.OP_SPMM, K)
+        lanes = 4 << (i % 5)
+        assert i < 5 and (lanes == 64 or lanes * 4 >= K) and (lanes == 4 or (lanes // 2) * 4 < K)
+        j = selector.plain_index(_lib.OP_SDDMM, K)
+        assert 5 <= j < 10
+        lanes = 4 << (j % 5)
+        assert lanes >= 8 and (lanes == 64 or -(-K // (lanes * 4)) <= 8)
+
+
+def test_specs_are_seeded_and_capped():
+    a = [selector.sample_spec(i) for i in range(300)]
+    b = [selector.sample_spec(i) for i in range(300)]
+    assert a == b
+    for s in a:
+        assert 4096 <= s["n"] <= 524288 and s["n"] % 64 == 0
+        assert 1e-4 <= s["density"] <= 0.1
+        assert selector.expected_nnz(s["n"], s["density"], s["pattern"]) <= selector.NNZ_CAP
+        assert s["split"] == ("test" if s["index"] % 5 == 0 else "train")
+    assert {s["pattern"] for s in a} == set(selector.PATTERNS)
+    assert {s["K"] for s in a} == set(selector.KS)
+
+
+def test_make_matrix_families():
+    for i in range(12):
+        s = dict(selector.sample_spec(i), n=2048)
+        A, v = selector.make_matrix(s)
+        assert A.m == A.n == 2048 and v.shape == (A.nnz,)
+        L = A.row_lengths()
+        if s["pattern"] == "banded":
+            rows = np.repeat(np.arange(A.m), L)
+            assert np.all(np.abs(rows - A.col_idx) <= 64)
+        if s["pattern"] == "block4":
+            assert np.all(L.reshape(-1, 4) == L.reshape(-1, 4)[:, :1])
+
+
+def test_regret_stats_and_choice():
+    times = np.array([[1.0, 2.0, np.nan], [3.0, 1.5, 1.0], [2.0, 2.0, 4.0]])
+    valid = np.isfinite(times).astype(np.float32)
+    Y = np.array([[0.5, 0.1, -9.0], [0.0, 1.0, 2.0], [1.0, 0.0, 3.0]])
+    pick = selector.choose(Y, valid)
+    assert pick.tolist() == [1, 0, 1]  # the invalid plan never wins
+    st = selector.regret_stats(times, pick, np.array([0, 0, 0]))
+    r = np.array([2.0, 3.0, 1.0])
+    assert math.isclose(st["geomean_regret"], float(np.exp(np.log(r).mean())))
+    assert st["max_regret"] == 3.0 and st["median_regret"] == 2.0
+    # plain = plan 0: times (1, 3, 2) against picks (2, 3, 2)
+    assert math.isclose(st["geomean_gain_over_plain"], float(np.exp(np.log(np.array([0.5, 1.0, 1.0])).mean())))
