@@ -120,12 +120,24 @@ def choose_plans(mode, dA, K, B, U, V, kind):
     if mode == "learned":
         from paper_2604_27985_amd import selector
 
-        return selector.select(dA, K, spk.OP_SPMM), selector.select(dA, K, spk.OP_SDDMM)
+        p1 = selector.select(dA, K, spk.OP_SPMM)
+        if kind == "gcn":
+            # the backward's product runs on A^T: ask for a plan for that matrix
+            trp, tci, _ = dA.transpose()
+            p2 = selector.select(spk.CSR(trp, tci, None, (dA.n, dA.m)), K, spk.OP_SPMM)
+            if p2.variant == spk.VAR_BSR4:  # no block form of A^T in the backward
+                p2 = spk.Plan(spk.VAR_MERGE, p2.lanes)
+            return p1, p2
+        return p1, selector.select(dA, K, spk.OP_SDDMM)
     from paper_2604_27985_amd import autotune
 
     p1 = autotune.best_plan(dA, K, spk.OP_SPMM, B=B)[0]
-    p2 = None if kind == "gcn" else autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
-    return p1, p2
+    if kind == "gcn":
+        trp, tci, perm = dA.transpose()
+        AT = spk.CSR(trp, tci, None, (dA.n, dA.m))
+        plans = [p for p in autotune.plans_for(spk.OP_SPMM, K) if p.variant != spk.VAR_BSR4]
+        return p1, min(autotune.sweep(AT, K, spk.OP_SPMM, B=U, plans=plans), key=lambda r: r[1])[0]
+    return p1, autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
 
 
 class Step:
@@ -160,7 +172,8 @@ class Step:
 
     def second(self):
         if self.kind == "gcn":
-            self.dB, self.S = self.spk.spmm_backward(self.dA, self.B, self.G, plan=self.p_spmm)
+            # p_sddmm carries the plan of the backward's A^T product
+            self.dB, self.S = self.spk.spmm_backward(self.dA, self.B, self.G, plan=self.p_sddmm)
         else:
             self.spk.sddmm(self.dA, self.U, self.V, plan=self.p_sddmm, out=self.S, workspace=self.ws2)
 
@@ -288,7 +301,7 @@ def run_workload(args):
     cfg = {"workload": name, "n": n, "nnz": nnz, "K": K, "pattern": "uniform" if kind == "uniform" else "powerlaw",
            "ops": "spmm+backward" if kind == "gcn" else "spmm+sddmm", "plan": args.plan,
            "plans": {"spmm": p_spmm.name() if p_spmm else "plain",
-                     "sddmm": p_sddmm.name() if p_sddmm else "plain"}}
+                     ("backward" if kind == "gcn" else "sddmm"): p_sddmm.name() if p_sddmm else "plain"}}
     if kind == "uniform":
         cfg["sparsity"] = 1 - d
     else:
@@ -303,6 +316,14 @@ def run_workload(args):
     }
     if kind == "gcn":
         out["transpose_ms_once"] = round(step.transpose_ms, 4)
+    if args.plan != "plain" and not args.no_compare:
+        # the same step with NULL plans (the plain method), for learned-vs-plain
+        plain = Step(dA, B, U, V, None, None, kind)
+        p_total, _, p1, p2 = time_steps(plain, args.steps, args.warmup)
+        p_ms = p_total / args.steps
+        out["plain"] = {"ms_per_step": round(p_ms, 4), "value": round(flops_step / (p_ms * 1e-3) / 1e9, 2),
+                        "ms": [round(float(np.mean(p1)), 4), round(float(np.mean(p2)), 4)]}
+        out["speedup_vs_plain"] = round(p_ms / ms_step, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, kind, step.C, step.S, args.cpu_budget)
     print(json.dumps(out), flush=True)
@@ -343,8 +364,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
-    ap.add_argument("--plan", default="tuned", choices=["plain", "tuned", "learned"])
+    ap.add_argument("--plan", default="learned", choices=["plain", "tuned", "learned"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain-plan comparison")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--sweep", default=None, help="write the grid sweep to this JSONL file")
     ap.add_argument("--sweep-modes", default="plain,tuned")

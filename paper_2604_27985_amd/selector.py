@@ -334,6 +334,20 @@ def load_default(path: str = WEIGHTS_PATH) -> bool:
     return True
 
 
+def offline_choices(table: dict, records: list[dict]) -> np.ndarray:
+    """Plan index the loaded network picks for each recorded matrix (GPU inputs
+    kernel on the recorded features, then the GPU network)."""
+    op = table["op"]
+    X, _, mask, _ = dataset(records, op)
+    mean, scale = np.asarray(table["mean"], np.float32), np.asarray(table["scale"], np.float32)
+    Xs = np.ascontiguousarray(((X - mean) / scale).astype(np.float32))
+    tr = Trainer(table["P"], table["H"])
+    tr.params = torch.tensor(table["params"], dtype=torch.float32, device="cuda")
+    Y = tr.forward(torch.from_numpy(Xs).cuda()).cpu().numpy()
+    valid = np.array([[ok for _, ok in plan_list(op, r["K"])] for r in records], np.float32)
+    return choose(Y, valid)
+
+
 def select(A: api.CSR, K: int, op: int, fallback: bool = True) -> api.Plan:
     """Learned plan for (A, K, op) via plan_select; the timed search when no model is available."""
     lib = _lib.load()
@@ -350,3 +364,46 @@ def select(A: api.CSR, K: int, op: int, fallback: bool = True) -> api.Plan:
         return autotune.best_plan(A, K, op)[0]
     _lib.check(st, "plan_select")
     return api.Plan(out.variant, out.lanes, out.chunk, out.flags)
+
+
+def main(argv=None) -> None:
+    """python -m paper_2604_27985_amd.selector build|train ..."""
+    import argparse
+
+    ap = argparse.ArgumentParser(prog="python -m paper_2604_27985_amd.selector")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    b = sub.add_parser("build", help="time every plan on seeded synthetic matrices (resumable)")
+    b.add_argument("--out", required=True)
+    b.add_argument("--count", type=int, default=2000)
+    b.add_argument("--budget", type=float, default=None, help="stop after this many seconds")
+    t = sub.add_parser("train", help="train the selector networks on a timing set")
+    t.add_argument("--timings", required=True)
+    t.add_argument("--out", default=WEIGHTS_PATH)
+    t.add_argument("--report", default=None)
+    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+    if args.cmd == "build":
+        n = build_timings(args.out, count=args.count, time_budget_s=args.budget, log=lambda s: print(s, flush=True))
+        print(f"added {n} records", flush=True)
+        return
+    records = load_timings(args.timings)
+    tables, reports = [], []
+    for op in (OP_SPMM, OP_SDDMM):
+        table, report = train_op(records, op, steps=args.steps, lr=args.lr, seed=args.seed,
+                                 log=lambda s: print(s, flush=True))
+        tables.append(table)
+        reports.append(report)
+        print(json.dumps({k: v for k, v in report.items() if k != "loss_history"}), flush=True)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as fh:
+        json.dump({"format": 1, "device": torch.cuda.get_device_name(0), "timings": os.path.basename(args.timings),
+                   "records": len(records), "tables": tables}, fh)
+    if args.report:
+        with open(args.report, "w") as fh:
+            json.dump(reports, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

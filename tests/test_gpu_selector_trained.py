@@ -1,0 +1,70 @@
+"""The shipped selector against the exhaustive search (GPU).
+
+The timing set (2000 seeded synthetic matrices, every plan timed on an
+MI355X) ships with the package; the network was trained on its train split
+(index % 5 != 0).  On the held-out split the learned plan must be within 10%
+of the timed best in geometric mean, and the test reports what it gains over
+the plain method (NULL plan).  A few held-out matrices are regenerated and
+run through the full device path (plan_select) to check it picks what the
+offline evaluation picked.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2604_27985_amd", "data")
+
+
+@pytest.fixture(scope="module")
+def sel():
+    from paper_2604_27985_amd import selector
+
+    assert torch.cuda.is_available()
+    return selector
+
+
+@pytest.fixture(scope="module")
+def shipped():
+    with open(os.path.join(DATA, "selector_weights.json")) as fh:
+        tables = json.load(fh)["tables"]
+    from paper_2604_27985_amd import selector
+
+    records = selector.load_timings(os.path.join(DATA, "timings_mi355x.jsonl"))
+    return tables, records
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_held_out_regret_and_gain(sel, shipped, op):
+    tables, records = shipped
+    table = tables[op]
+    test = [r for r in records if r["split"] == "test"]
+    assert len(test) == 400
+    pick = sel.offline_choices(table, test)
+    _, _, _, times = sel.dataset(test, op)
+    plain = np.array([sel.plain_index(op, r["K"]) for r in test])
+    st = sel.regret_stats(times, pick, plain)
+    print(json.dumps(st))
+    assert st["geomean_regret"] <= 1.10
+    assert st["geomean_gain_over_plain"] > 1.0
+
+
+def test_device_path_picks_the_offline_choice(sel, shipped):
+    import paper_2604_27985_amd as spk
+
+    tables, records = shipped
+    sel._loaded.clear()
+    assert sel.load_default()
+    test = [r for r in records if r["split"] == "test" and r["nnz"] < 3_000_000][:12]
+    for op in (0, 1):
+        pick = sel.offline_choices(tables[op], test)
+        for r, p in zip(test, pick):
+            A, v = sel.make_matrix(r)
+            assert A.nnz == r["nnz"]
+            plan = sel.select(spk.CSR.from_host(A, v), r["K"], op, fallback=False)
+            expect = sel.plan_list(op, r["K"])[int(p)][0]
+            assert (plan.variant, plan.lanes, plan.chunk) == (expect.variant, expect.lanes, expect.chunk), r["index"]
