@@ -90,9 +90,15 @@ enum spk_variant {
                           rows + entries; split rows are fixed up in order */
     SPK_VAR_BSR4 = 2,  /* 4x4 block-sparse with matrix cores (SpMM only;
                           needs the block form from csr_to_bsr4) */
-    SPK_VAR_SLAB = 3   /* row-split over column slabs: one launch per slab
+    SPK_VAR_SLAB = 3,  /* row-split over column slabs: one launch per slab
                           of `chunk` columns, so the slab of the dense operand
                           being gathered stays in L2 */
+    SPK_VAR_TILE = 4   /* SpMM: a workgroup owns (256 / lanes) x 4 rows and
+                          stages each slab of `chunk` rows of B in LDS once,
+                          so every staged row serves all of the workgroup's
+                          entries in it.  F32 or BF16 operands with K <=
+                          4 * lanes, K and ldb multiples of 16 bytes, slab
+                          of at most 64 KiB. */
 };
 
 /* An execution plan: plain data, owned by the caller.

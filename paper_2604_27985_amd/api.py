@@ -30,7 +30,7 @@ class Plan:
         return _lib.spk_plan(self.variant, self.lanes, self.chunk, self.flags)
 
     def name(self) -> str:
-        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4", VAR_SLAB: "slab"}[self.variant]
+        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4", VAR_SLAB: "slab", 4: "tile"}[self.variant]
         s = f"{v}/l{self.lanes}"
         if self.chunk:
             s += f"/c{self.chunk}"

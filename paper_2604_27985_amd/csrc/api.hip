@@ -64,11 +64,28 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
                      int64_t ldc, Resolved &r) {
     r.variant = plan ? plan->variant : SPK_VAR_ROWS;
     r.lanes = plan ? plan->lanes : default_spmm_lanes(K);
-    if (r.variant != SPK_VAR_ROWS && r.variant != SPK_VAR_MERGE && r.variant != SPK_VAR_SLAB) return SPK_ERR_PLAN;
+    if (r.variant != SPK_VAR_ROWS && r.variant != SPK_VAR_MERGE && r.variant != SPK_VAR_SLAB &&
+        r.variant != SPK_VAR_TILE)
+        return SPK_ERR_PLAN;
+    if (!valid_lanes(r.lanes)) return SPK_ERR_PLAN;
+    if (r.variant == SPK_VAR_TILE) {
+        // one K-tile of 16-byte (F32) or 8-byte (BF16) lanes; the slab fits kTileLds
+        const size_t es = elem_size(b_dtype);
+        const int64_t sv = 16 / static_cast<int64_t>(es);
+        if (b_dtype == SPK_F64 || (plan && (plan->flags & ~1)) || (plan && plan->chunk < 0)) return SPK_ERR_PLAN;
+        if (K > 4 * r.lanes || K % sv != 0 || ldb % sv != 0 || !aligned(B, 16) || ldc % 4 != 0 || !aligned(C, 16))
+            return SPK_ERR_PLAN;
+        const int64_t wmax = static_cast<int64_t>(kTileLds) / (K * static_cast<int64_t>(es));
+        int64_t w = 16;
+        while (w * 2 <= wmax) w *= 2;
+        r.chunk = plan && plan->chunk > 0 ? plan->chunk : w;
+        if (r.chunk < 1 || r.chunk > wmax) return SPK_ERR_PLAN;
+        r.vec = 4;
+        return SPK_OK;
+    }
     if (plan && plan->chunk > 0) r.chunk = plan->chunk;
     else if (r.variant == SPK_VAR_SLAB) r.chunk = default_slab_width(K, elem_size(b_dtype));
     else r.chunk = 4 * K > kDefaultChunk ? 4 * K : kDefaultChunk;
-    if (!valid_lanes(r.lanes)) return SPK_ERR_PLAN;
     if (plan && (plan->flags & ~1)) return SPK_ERR_PLAN;
     if (plan && plan->chunk < 0) return SPK_ERR_PLAN;
     const bool force_scalar = plan && (plan->flags & 1);
@@ -154,7 +171,7 @@ const char *spk_strerror(int32_t status) {
 
 size_t spk_workspace_bytes(int32_t op, const spk_csr *A, int64_t K, const spk_plan *plan) {
     if (check_csr(A) != SPK_OK || K < 0) return 0;
-    if (plan && (plan->chunk < 0 || plan->variant < SPK_VAR_ROWS || plan->variant > SPK_VAR_SLAB)) return 0;
+    if (plan && (plan->chunk < 0 || plan->variant < SPK_VAR_ROWS || plan->variant > SPK_VAR_TILE)) return 0;
     // The size depends only on the variant, the chunk and the shapes.  Sizes
     // assume the widest element (8 bytes): the largest carry and, for the
     // default slab width, the most slabs, so any dtype's call fits.

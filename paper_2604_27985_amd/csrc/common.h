@@ -12,6 +12,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, own L2 each
 constexpr int kDefaultChunk = 256; // merge-path / SDDMM items per group
+constexpr size_t kTileLds = 65536; // LDS bytes of one staged slab (TILE variants)
 
 // bfloat16 storage type: the upper half of a binary32 pattern.
 struct bf16 {

@@ -106,7 +106,7 @@ __device__ __forceinline__ void sddmm_step(int64_t pb, int cnt, const int32_t *_
     if (lig < cnt && lig < R) {
         const int64_t p = pb + lig;
         const A a = vals ? static_cast<A>(__builtin_nontemporal_load(vals + p)) : A(1);
-        __builtin_nontemporal_store(a * tot, S + p);
+        S[p] = a * tot;  // cached store: a group writes R consecutive outputs per step
     }
 }
 

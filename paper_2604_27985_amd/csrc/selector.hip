@@ -89,17 +89,38 @@ __global__ void features_init_kernel(int64_t m, int64_t n, int64_t nnz, unsigned
            : k == 2 ? static_cast<unsigned long long>(nnz) : 0ull;
 }
 
-// Sum of the per-block-row block counts into f[27].
-__global__ __launch_bounds__(kBlock) void features_blocks_kernel(int64_t mb, const int32_t *__restrict__ counts,
+// Number of nonempty 4x4 blocks into f[27].  Entry (i, j) opens block
+// (i/4, j/4) when it is the first entry of row i in block column j/4 and no
+// earlier row of the same block row holds a column in [4(j/4), 4(j/4)+4)
+// (a binary search in each such row).  One wave per row, lanes over entries.
+__global__ __launch_bounds__(kBlock) void features_blocks_kernel(int64_t m, const int32_t *__restrict__ rp,
+                                                                 const int32_t *__restrict__ ci,
                                                                  unsigned long long *__restrict__ f) {
     __shared__ unsigned long long part[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
     unsigned long long s = 0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < mb;
-         i += static_cast<int64_t>(gridDim.x) * kBlock)
-        s += static_cast<unsigned long long>(counts[i]);
+    if (row < m) {
+        const int64_t a = rp[row], b = rp[row + 1];
+        const int64_t first_row = row & ~int64_t(3);
+        for (int64_t p = a + lane; p < b; p += kWave) {
+            const int32_t J = ci[p] >> 2;
+            if (p > a && (ci[p - 1] >> 2) == J) continue;
+            bool seen = false;
+            for (int64_t r = first_row; r < row && !seen; ++r) {
+                int64_t lo = rp[r], hi = rp[r + 1];  // first column >= 4J in row r
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (ci[mid] < 4 * J) lo = mid + 1; else hi = mid;
+                }
+                seen = lo < rp[r + 1] && ci[lo] < 4 * J + 4;
+            }
+            s += seen ? 0ull : 1ull;
+        }
+    }
 #pragma unroll
     for (int o = kWave / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = s;
+    if (lane == 0) part[threadIdx.x / kWave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
@@ -364,11 +385,8 @@ hipError_t features_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
     const int64_t nb = (m + (kBlock / kWave) - 1) / (kBlock / kWave);
     hipLaunchKernelGGL(features_rows_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, rp, ci, uf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    int32_t *counts = static_cast<int32_t *>(ws);
-    if ((e = bsr4_count_launch(m, rp, ci, counts, s)) != hipSuccess) return e;
-    const int64_t mb = (m + 3) / 4;
-    const int64_t gb = (mb + kBlock - 1) / kBlock < 1024 ? (mb + kBlock - 1) / kBlock : 1024;
-    hipLaunchKernelGGL(features_blocks_kernel, dim3(static_cast<unsigned>(gb)), dim3(kBlock), 0, s, mb, counts, uf);
+    (void)ws;
+    hipLaunchKernelGGL(features_blocks_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, rp, ci, uf);
     return hipGetLastError();
 }
 

@@ -157,6 +157,105 @@ __global__ __launch_bounds__(kBlock) void spmm_slab_kernel(int64_t m, int K, con
     }
 }
 
+// TILE: a workgroup owns GPB*RPG consecutive rows (RPG per group) and walks
+// the columns in slabs of W; each slab of B is staged once in LDS and every
+// group gathers its rows' entries of that slab from LDS.  A staged row of B
+// serves (rows per workgroup) x density entries on average, which cuts the
+// L2 gather traffic by that factor for dense-ish matrices.  Entries within a
+// row are sorted, so the entries of a row inside a slab are a prefix of the
+// ones not yet consumed: a chunk of LANES entries is read, the count below
+// the slab end found with a ballot, and the cursor advanced by it.
+template <typename TB, typename TV, int VW, int LANES, int RPG>
+__global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n, int K, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const TV *__restrict__ vals,
+                                                           const int32_t *__restrict__ vperm,
+                                                           const TB *__restrict__ B, int64_t ldb,
+                                                           typename acc_of<TB>::type *__restrict__ C, int64_t ldc,
+                                                           int W) {
+    using A = typename acc_of<TB>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TB *Bs = reinterpret_cast<TB *>(smem);  // [W][K]
+    constexpr int GPB = kBlock / LANES;
+    constexpr int U = LANES < 8 ? LANES : 8;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
+    const uint64_t gmask = LANES == 64 ? ~0ull : (((1ull << LANES) - 1) << gbase);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = (blk * GPB + threadIdx.x / LANES) * RPG;
+    const int k0 = lig * VW;
+    const bool kvalid = k0 < K;
+    const int koff = kvalid ? k0 : 0;
+    int64_t cur[RPG], end[RPG];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+        const int64_t row = row0 + r;
+        cur[r] = row < m ? rp[row] : 0;
+        end[r] = row < m ? rp[row + 1] : 0;
+    }
+    A acc[RPG][VW];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) zero<A, VW>(acc[r]);
+    constexpr int SV = 16 / sizeof(TB);  // elements per 16-byte staging load
+    for (int64_t c0 = 0; c0 < n; c0 += W) {
+        const int w = static_cast<int>(n - c0 < W ? n - c0 : W);
+        __syncthreads();  // the previous slab is consumed
+        const int per_row = K / SV;  // K is a multiple of SV for this variant
+        for (int idx = threadIdx.x; idx < w * per_row; idx += kBlock) {
+            const int rr = idx / per_row, cc = (idx % per_row) * SV;
+            *reinterpret_cast<uint4 *>(Bs + rr * K + cc) =
+                *reinterpret_cast<const uint4 *>(B + (c0 + rr) * ldb + cc);
+        }
+        __syncthreads();
+        const int32_t c1 = static_cast<int32_t>(c0 + w);
+#pragma unroll
+        for (int r = 0; r < RPG; ++r) {
+            while (cur[r] < end[r]) {  // group-uniform
+                const int64_t p = cur[r] + lig;
+                int c = 0x7FFFFFFF;
+                A v = A(0);
+                if (p < end[r]) {
+                    c = __builtin_nontemporal_load(ci + p);
+                    if (vals) {
+                        const int64_t pv = vperm ? static_cast<int64_t>(__builtin_nontemporal_load(vperm + p)) : p;
+                        v = static_cast<A>(vals[pv]);
+                    } else {
+                        v = A(1);
+                    }
+                }
+                const bool in = c < c1;
+                const int cnt = __popcll(__ballot(in) & gmask);
+                const int crel = in ? c - static_cast<int>(c0) : 0;
+                for (int t = 0; t < cnt; t += U) {
+                    int cc[U];
+                    A vv[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        cc[u] = lane_read(crel, gbase + t + u);
+                        vv[u] = lane_read(in ? v : A(0), gbase + t + u);
+                    }
+                    A bv[U][VW];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) vec_load<TB, VW>::run(Bs + cc[u] * K + koff, bv[u]);
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) acc[r][e] = fma(vv[u], bv[u][e], acc[r][e]);
+                }
+                cur[r] += cnt;
+                if (cnt < LANES) break;  // the rest of the row lies beyond this slab
+            }
+        }
+    }
+    if (!kvalid) return;
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+        const int64_t row = row0 + r;
+        if (row < m) vec_store<A, VW>::run(C + row * ldc + k0, acc[r]);
+    }
+}
+
 // Interior slab boundaries: bnd[(s-1)*m + i] = first entry of row i whose
 // column is >= s*W, for s = 1 .. nslabs-1 (binary search in the sorted row).
 __global__ void slab_bounds_kernel(int64_t m, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -324,6 +423,25 @@ static hipError_t launch_merge(const SpmmArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename TB, typename TV, int VW, int LANES>
+static hipError_t launch_tile(const SpmmArgs &a, hipStream_t s) {
+    if constexpr (VW != 4 || sizeof(TB) > 4) {
+        return hipErrorInvalidValue;  // the API layer admits TILE only for 16-byte F32 / 8-byte BF16 lanes
+    } else {
+        constexpr int RPG = 4;
+        constexpr int GPB = kBlock / LANES;
+        const int64_t rows_per_block = GPB * RPG;
+        const int64_t nb = (a.m + rows_per_block - 1) / rows_per_block;
+        const size_t lds = static_cast<size_t>(a.chunk) * static_cast<size_t>(a.K) * sizeof(TB);
+        if (nb > 0x7FFFFFFF || a.K > LANES * VW || lds > kTileLds) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((spmm_tile_kernel<TB, TV, VW, LANES, RPG>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), lds,
+                           s, a.m, a.n, static_cast<int>(a.K), a.rp, a.ci, static_cast<const TV *>(a.vals), a.vperm,
+                           static_cast<const TB *>(a.B), a.ldb, static_cast<typename acc_of<TB>::type *>(a.C), a.ldc,
+                           static_cast<int>(a.chunk));
+        return hipGetLastError();
+    }
+}
+
 template <typename TB, typename TV, int VW, bool OFF32>
 static hipError_t dispatch_lanes(const SpmmArgs &a, hipStream_t s) {
     switch (a.lanes) {
@@ -331,6 +449,7 @@ static hipError_t dispatch_lanes(const SpmmArgs &a, hipStream_t s) {
     case L:                                                                           \
         if (a.variant == SPK_VAR_MERGE) return launch_merge<TB, TV, VW, L, OFF32>(a, s); \
         if (a.variant == SPK_VAR_SLAB) return launch_slab<TB, TV, VW, L, OFF32>(a, s);   \
+        if (a.variant == SPK_VAR_TILE) return launch_tile<TB, TV, VW, L>(a, s);          \
         return launch_rows<TB, TV, VW, L, OFF32>(a, s);
         SPK_CASE(4)
         SPK_CASE(8)

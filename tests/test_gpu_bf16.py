@@ -44,8 +44,8 @@ def powerlaw_bf16(n, mean, K, seed):
     return A, v, B, U
 
 
-@pytest.mark.parametrize("K,plans", [(256, [None, (1, 64, 0), (0, 32, 0), (3, 32, 0)]),
-                                     (64, [None, (1, 8, 0), (0, 16, 0)]), (36, [None, (1, 8, 0)])])
+@pytest.mark.parametrize("K,plans", [(256, [None, (1, 64, 0), (0, 32, 0), (3, 32, 0), (4, 64, 0), (4, 64, 33)]),
+                                     (64, [None, (1, 8, 0), (0, 16, 0), (4, 16, 0)]), (36, [None, (1, 8, 0)])])
 def test_spmm_bf16(spk, K, plans):
     A, v, B32, _ = powerlaw_bf16(40000, 32, K, 1)
     Bt, Br = bf16_dev(B32)

@@ -78,6 +78,31 @@ def test_spmm_ragged_shapes(spk, m, n, d, K):
         assert_within(C, C64, M, TOL_F32, f"spmm {m}x{n} K={K} {plan}")
 
 
+@pytest.mark.parametrize("K,lanes", [(64, 16), (128, 32), (32, 8), (256, 64), (36, 16), (64, 64), (8, 4)])
+@pytest.mark.parametrize("kind,m,n,d", [("uniform", 3001, 2500, 0.05), ("powerlaw", 6000, 6000, 12),
+                                        ("block4", 1024, 4096, 0.02), ("uniform", 7, 5, 0.5)])
+def test_spmm_tile(spk, K, lanes, kind, m, n, d):
+    """LDS-staged slabs: default, odd and one-column slab widths."""
+    A, v, B, _ = problem(m, n, d, K, 8, kind)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    for chunk in (0, 7, 1, 33):  # widths up to the 64 KiB LDS budget (64 rows at K = 256)
+        C = run_spmm(spk, A, v, B, spk.Plan(4, lanes, chunk))
+        assert_within(C, C64, M, TOL_F32, f"tile K={K} lanes={lanes} chunk={chunk}")
+
+
+def test_spmm_tile_rejects_unfit_plans(spk):
+    A, v, B, _ = problem(100, 100, 0.1, 64, 1)
+    for plan in (spk.Plan(4, 8, 0),      # 8 lanes x 4 < K
+                 spk.Plan(4, 16, 1 << 20),  # slab larger than the LDS budget
+                 spk.Plan(4, 16, 0, 2)):    # unknown flag
+        with pytest.raises(spk.SpkError) as e:
+            run_spmm(spk, A, v, B, plan)
+        assert e.value.status == -6
+    with pytest.raises(spk.SpkError):  # K not a multiple of 4 floats
+        A2, v2, B2, _ = problem(100, 100, 0.1, 30, 1)
+        run_spmm(spk, A2, v2, B2, spk.Plan(4, 16, 0))
+
+
 def test_spmm_pattern_mode_and_empty_rows(spk):
     # rows 0, 3, 4 and the last are empty
     A = host_csr(6, 9, [[], [0, 4, 8], [2], [], [], [1, 2, 3, 4, 5, 6, 7]])
