@@ -43,6 +43,7 @@ int32_t native_vec(int32_t dt) { return dt == SPK_F64 ? 2 : 4; }
 struct Resolved {
     int32_t variant, lanes, vec;
     int64_t chunk;
+    int32_t rows_per_group = 4;
 };
 
 int32_t default_spmm_lanes(int64_t K) {
@@ -72,10 +73,11 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
         // one K-tile of 16-byte (F32) or 8-byte (BF16) lanes; the slab fits kTileLds
         const size_t es = elem_size(b_dtype);
         const int64_t sv = 16 / static_cast<int64_t>(es);
-        if (b_dtype == SPK_F64 || (plan && (plan->flags & ~1)) || (plan && plan->chunk < 0)) return SPK_ERR_PLAN;
+        if (b_dtype == SPK_F64 || (plan && (plan->flags & ~3)) || (plan && plan->chunk < 0)) return SPK_ERR_PLAN;
+        r.rows_per_group = plan && (plan->flags & 2) ? 8 : 4;
         if (K > 4 * r.lanes || K % sv != 0 || ldb % sv != 0 || !aligned(B, 16) || ldc % 4 != 0 || !aligned(C, 16))
             return SPK_ERR_PLAN;
-        const int64_t wmax = static_cast<int64_t>(kTileLds) / (K * static_cast<int64_t>(es));
+        const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * K * static_cast<int64_t>(es));  // two buffers
         int64_t w = 16;
         while (w * 2 <= wmax) w *= 2;
         r.chunk = plan && plan->chunk > 0 ? plan->chunk : w;
@@ -137,8 +139,9 @@ int32_t check_ws(size_t need, const void *ws, size_t ws_bytes) {
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? SPK_OK : SPK_ERR_HIP; }
 
-size_t spmm_ws(int64_t m, int64_t n, int64_t nnz, int64_t K, int32_t dt, const Resolved &r) {
+size_t spmm_ws(int64_t m, int64_t n, int64_t nnz, int64_t K, int32_t dt, const Resolved &r, bool permuted) {
     if (m == 0 || K == 0) return 0;
+    if (r.variant == SPK_VAR_TILE) return permuted ? align_up(sizeof(float) * static_cast<size_t>(nnz)) : 0;
     if (r.variant == SPK_VAR_MERGE) return merge_layout(m, nnz, K, r.chunk, dt == SPK_F64 ? 8 : 4).total;
     if (r.variant == SPK_VAR_SLAB) return slab_layout(m, n, r.chunk).total;
     return 0;
@@ -187,7 +190,7 @@ size_t spk_workspace_bytes(int32_t op, const spk_csr *A, int64_t K, const spk_pl
         if (plan && plan->chunk > 0) r.chunk = plan->chunk;
         else if (r.variant == SPK_VAR_SLAB) r.chunk = default_slab_width(K, 8);
         else r.chunk = 4 * K > kDefaultChunk ? 4 * K : kDefaultChunk;
-        return spmm_ws(m, n, A->nnz, K, SPK_F64, r);
+        return spmm_ws(m, n, A->nnz, K, SPK_F64, r, bwd);
     case SPK_OP_SDDMM:
         r.variant = plan ? plan->variant : SPK_VAR_MERGE;
         r.chunk = plan && plan->chunk > 0 ? plan->chunk : default_slab_width(K, 8);
@@ -263,10 +266,10 @@ int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, 
     if (A->nnz == 0) return hip_status(zero_fill(C, A->m, K, ldc, out_dt, s));
     Resolved r;
     if ((st = resolve_spmm(plan, K, b_dtype, B, ldb, C, ldc, r))) return st;
-    const size_t need = spmm_ws(A->m, A->n, A->nnz, K, b_dtype, r);
+    const size_t need = spmm_ws(A->m, A->n, A->nnz, K, b_dtype, r, false);
     if ((st = check_ws(need, ws, ws_bytes))) return st;
     SpmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, nullptr, B, ldb, b_dtype, C, ldc,
-               r.variant, r.lanes, r.vec, r.chunk, ws};
+               r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group};
     return hip_status(spmm_launch(a, s));
 }
 
@@ -316,10 +319,10 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
         } else {
             Resolved r;
             if ((st = resolve_spmm(plan, K, dtype, G, ldg, dB, lddb, r))) return st;
-            const size_t need = spmm_ws(A->n, A->m, A->nnz, K, dtype, r);
+            const size_t need = spmm_ws(A->n, A->m, A->nnz, K, dtype, r, true);
             if ((st = check_ws(need, ws, ws_bytes))) return st;
             SpmmArgs a{A->n, A->m, A->nnz, K, at_row_ptr, at_col_idx, A->vals, perm, G, ldg, dtype, dB, lddb,
-                       r.variant, r.lanes, r.vec, r.chunk, ws};
+                       r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group};
             if ((st = hip_status(spmm_launch(a, s)))) return st;
         }
     }

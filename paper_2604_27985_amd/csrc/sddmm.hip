@@ -34,24 +34,70 @@ __device__ __forceinline__ const T *row_elem(const T *base, int32_t row, int64_t
         return base + (static_cast<int64_t>(row) * ld + col);
 }
 
+// Lane exchanges as DPP moves (VALU, no LDS crossbar).  dpp_ctrl values:
+// quad_perm [1,0,3,2] = 0xB1 (partner lane ^ 1), quad_perm [2,3,0,1] = 0x4E
+// (lane ^ 2), row_half_mirror = 0x141 (7 - lane within 8), row_mirror =
+// 0x140 (15 - lane within 16), row_ror:8 = 0x128 (lane ^ 8 within 16).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Partner value for a halving step of stride H: any lane whose bit H differs
+// works, because both partners hold the same entries at that point (mirror
+// pairs do for H = 4 and 8).
+template <int H, typename T>
+__device__ __forceinline__ T halving_partner(T v, int lane) {
+    if constexpr (H == 1) return dpp<0xB1>(v);
+    else if constexpr (H == 2) return dpp<0x4E>(v);
+    else if constexpr (H == 4) return dpp<0x141>(v);
+    else if constexpr (H == 8) return dpp<0x140>(v);
+    else return lane_read(v, lane ^ H);
+}
+
+// Partner holding the same entry, exactly lane ^ S.
+template <int S, typename T>
+__device__ __forceinline__ T xor_partner(T v, int lane) {
+    if constexpr (S == 1) return dpp<0xB1>(v);
+    else if constexpr (S == 2) return dpp<0x4E>(v);
+    else if constexpr (S == 8) return dpp<0x128>(v);
+    else return lane_read(v, lane ^ S);
+}
+
+template <int H, int R, typename T>
+__device__ __forceinline__ void halving_steps(T (&x)[R], int lane) {
+    if constexpr (H >= 1) {
+        const bool upper = (lane & H) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const T send = upper ? x[i] : x[i + H];
+            const T keep = upper ? x[i + H] : x[i];
+            x[i] = keep + halving_partner<H>(send, lane);
+        }
+        halving_steps<H / 2, R>(x, lane);
+    }
+}
+
+template <int S, int LANES, typename T>
+__device__ __forceinline__ T across_subgroups(T v, int lane) {
+    if constexpr (S < LANES) return across_subgroups<S * 2, LANES>(v + xor_partner<S>(v, lane), lane);
+    else return v;
+}
+
 // On return, lane l of each LANES-lane group holds the group-wide total of
-// x[l mod R] (R and LANES powers of two, R <= LANES).
+// x[l mod R] (R and LANES powers of two, R <= LANES): halving steps leave
+// lane l with entry l mod R summed over its R-lane subgroup, then the
+// subgroups are added.
 template <int R, int LANES, typename T>
 __device__ __forceinline__ T reduce_scatter(T (&x)[R], int lane) {
-#pragma unroll
-    for (int h = R / 2; h >= 1; h /= 2) {
-        const bool upper = (lane & h) != 0;
-#pragma unroll
-        for (int i = 0; i < h; ++i) {
-            const T send = upper ? x[i] : x[i + h];
-            const T keep = upper ? x[i + h] : x[i];
-            x[i] = keep + lane_read(send, lane ^ h);
-        }
-    }
-    T v = x[0];
-#pragma unroll
-    for (int s = R; s < LANES; s *= 2) v += lane_read(v, lane ^ s);
-    return v;
+    halving_steps<R / 2, R>(x, lane);
+    return across_subgroups<R, LANES>(x[0], lane);
 }
 
 template <typename TUV, int VW, int LANES, int NS>
@@ -72,36 +118,53 @@ struct URow {
     }
 };
 
-// Entries pb .. pb+cnt-1 (1 <= cnt <= R) of one row whose U slice is in u.
-template <typename TUV, typename TV, int VW, int LANES, int NS, int R, bool OFF32>
-__device__ __forceinline__ void sddmm_step(int64_t pb, int cnt, const int32_t *__restrict__ ci,
-                                           const TV *__restrict__ vals, const TUV *__restrict__ V, int64_t ldv,
-                                           const URow<TUV, VW, LANES, NS> &ur, int K, int gbase, int lig, int lane,
-                                           typename acc_of<TUV>::type *__restrict__ S) {
+// One step: entries pb .. pb+cnt-1 (1 <= cnt <= R) of one row.  load()
+// issues the column-index read, the lane exchanges and all R x NS gathers;
+// dots() forms the R partial dot products with the row of U; finish()
+// reduces them across the group and stores.  Callers issue the next step's
+// load() between dots() and finish(), so its gathers are in flight while the
+// current step reduces.
+template <typename TUV, int VW, int LANES, int NS, int R, bool OFF32>
+struct Step {
     using A = typename acc_of<TUV>::type;
-    const int mine = lig < cnt ? lig : cnt - 1;
-    const int c_mine = __builtin_nontemporal_load(ci + pb + mine);
-    int cc[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) cc[q] = lane_read(c_mine, gbase + q);
+    int64_t pb;
+    int cnt;
     A vrow[R][NS][VW];
+
+    __device__ __forceinline__ void load(int64_t pb_, int cnt_, const int32_t *__restrict__ ci,
+                                         const TUV *__restrict__ V, int64_t ldv, int K, int gbase, int lig) {
+        pb = pb_;
+        cnt = cnt_;
+        const int mine = lig < cnt ? lig : cnt - 1;
+        const int c_mine = __builtin_nontemporal_load(ci + pb + mine);
+        int cc[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q)
+        for (int q = 0; q < R; ++q) cc[q] = lane_read(c_mine, gbase + q);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int k = s * LANES * VW + lig * VW;
-            vec_load<TUV, VW>::run(row_elem<OFF32>(V, cc[q], ldv, k < K ? k : 0), vrow[q][s]);
-        }
-    A part[R];
+        for (int q = 0; q < R; ++q)
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        A acc = A(0);
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-#pragma unroll
-            for (int e = 0; e < VW; ++e) acc = fma(ur.u[s][e], vrow[q][s][e], acc);
-        part[q] = acc;
+            for (int s = 0; s < NS; ++s) {
+                const int k = s * LANES * VW + lig * VW;
+                vec_load<TUV, VW>::run(row_elem<OFF32>(V, cc[q], ldv, k < K ? k : 0), vrow[q][s]);
+            }
     }
+
+    __device__ __forceinline__ void dots(const URow<TUV, VW, LANES, NS> &ur, A (&part)[R]) const {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            A acc = A(0);
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int e = 0; e < VW; ++e) acc = fma(ur.u[s][e], vrow[q][s][e], acc);
+            part[q] = acc;
+        }
+    }
+};
+
+template <int R, int LANES, typename A, typename TV>
+__device__ __forceinline__ void finish(int64_t pb, int cnt, A (&part)[R], const TV *__restrict__ vals,
+                                       A *__restrict__ S, int lig, int lane) {
     const A tot = reduce_scatter<R, LANES>(part, lane);
     if (lig < cnt && lig < R) {
         const int64_t p = pb + lig;
@@ -132,21 +195,39 @@ __global__ __launch_bounds__(kBlock) void sddmm_split_kernel(int64_t m, int64_t 
     // Row holding entry p0: largest r in [0, m-1] with row_ptr[r] <= p0.
     int64_t r = last_at_most(0, m - 1, p0, [&](int64_t i) { return static_cast<int64_t>(rp[i]); });
     int64_t next = rp[r + 1];
-    int64_t loaded = -1;
-    URow<TUV, VW, LANES, NS> ur;
-    for (int64_t pb = p0; pb < p1;) {
+    int64_t pb = p0;
+    // the step starting at pb never crosses a row end, so one row of U serves it
+    auto step_len = [&]() {
         while (pb >= next) {  // group-uniform; also skips empty rows
             ++r;
             next = rp[r + 1];
         }
-        if (r != loaded) {
-            ur.load(U, r, ldu, K, lig);
-            loaded = r;
+        const int64_t lim = p1 < next ? p1 : next;
+        return static_cast<int>(lim - pb < R ? lim - pb : R);
+    };
+    URow<TUV, VW, LANES, NS> ur;
+    Step<TUV, VW, LANES, NS, R, OFF32> st;
+    int cnt = step_len();
+    ur.load(U, r, ldu, K, lig);
+    int64_t loaded = r;
+    st.load(pb, cnt, ci, V, ldv, K, gbase, lig);
+    while (true) {
+        typename acc_of<TUV>::type part[R];
+        st.dots(ur, part);
+        const int64_t pb_cur = st.pb;
+        const int cnt_cur = st.cnt;
+        pb = pb_cur + cnt_cur;
+        const bool more = pb < p1;
+        if (more) {  // next step's gathers go out before this step's reduction
+            cnt = step_len();
+            if (r != loaded) {
+                ur.load(U, r, ldu, K, lig);
+                loaded = r;
+            }
+            st.load(pb, cnt, ci, V, ldv, K, gbase, lig);
         }
-        const int64_t lim = p1 < next ? p1 : next;  // a step never crosses a row end
-        const int cnt = static_cast<int>(lim - pb < R ? lim - pb : R);
-        sddmm_step<TUV, TV, VW, LANES, NS, R, OFF32>(pb, cnt, ci, vals, V, ldv, ur, K, gbase, lig, lane, S);
-        pb += cnt;
+        finish<R, LANES>(pb_cur, cnt_cur, part, vals, S, lig, lane);
+        if (!more) break;
     }
 }
 
@@ -173,9 +254,18 @@ __global__ __launch_bounds__(kBlock) void sddmm_rows_kernel(int64_t m, int K, co
     if (a >= b) return;
     URow<TUV, VW, LANES, NS> ur;
     ur.load(U, row, ldu, K, lig);
-    for (int64_t pb = a; pb < b; pb += R) {
-        const int cnt = static_cast<int>(b - pb < R ? b - pb : R);
-        sddmm_step<TUV, TV, VW, LANES, NS, R, OFF32>(pb, cnt, ci, vals, V, ldv, ur, K, gbase, lig, lane, S);
+    Step<TUV, VW, LANES, NS, R, OFF32> st;
+    st.load(a, static_cast<int>(b - a < R ? b - a : R), ci, V, ldv, K, gbase, lig);
+    while (true) {
+        typename acc_of<TUV>::type part[R];
+        st.dots(ur, part);
+        const int64_t pb_cur = st.pb;
+        const int cnt_cur = st.cnt;
+        const int64_t pb = pb_cur + cnt_cur;
+        const bool more = pb < b;
+        if (more) st.load(pb, static_cast<int>(b - pb < R ? b - pb : R), ci, V, ldv, K, gbase, lig);
+        finish<R, LANES>(pb_cur, cnt_cur, part, vals, S, lig, lane);
+        if (!more) break;
     }
 }
 

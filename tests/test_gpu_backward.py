@@ -61,7 +61,7 @@ def gcn_layer(n=262144, mean=16, K=128, seed=0):
     return A, vals, B, G
 
 
-@pytest.mark.parametrize("plan_args", [None, (1, 32, 0), (0, 16, 0), (3, 32, 1000), (4, 32, 0)])
+@pytest.mark.parametrize("plan_args", [None, (1, 32, 0), (0, 16, 0), (3, 32, 1000), (4, 32, 0), (4, 32, 7, 2)])
 def test_backward_matches_oracle(spk, plan_args):
     A, v, B, G = gcn_layer(n=30000, mean=16, K=128, seed=2)
     dB64, dBM, dv64, dvM = oracle.spmm_backward(A.row_ptr, A.col_idx, v, B, G, A.n)

@@ -45,7 +45,7 @@ def powerlaw_bf16(n, mean, K, seed):
 
 
 @pytest.mark.parametrize("K,plans", [(256, [None, (1, 64, 0), (0, 32, 0), (3, 32, 0), (4, 64, 0), (4, 64, 33)]),
-                                     (64, [None, (1, 8, 0), (0, 16, 0), (4, 16, 0)]), (36, [None, (1, 8, 0)])])
+                                     (64, [None, (1, 8, 0), (0, 16, 0), (4, 16, 0), (4, 16, 5, 2)]), (36, [None, (1, 8, 0)])])
 def test_spmm_bf16(spk, K, plans):
     A, v, B32, _ = powerlaw_bf16(40000, 32, K, 1)
     Bt, Br = bf16_dev(B32)

@@ -82,19 +82,20 @@ def test_spmm_ragged_shapes(spk, m, n, d, K):
 @pytest.mark.parametrize("kind,m,n,d", [("uniform", 3001, 2500, 0.05), ("powerlaw", 6000, 6000, 12),
                                         ("block4", 1024, 4096, 0.02), ("uniform", 7, 5, 0.5)])
 def test_spmm_tile(spk, K, lanes, kind, m, n, d):
-    """LDS-staged slabs: default, odd and one-column slab widths."""
+    """LDS-staged slabs: default, odd and one-column slab widths; 4 or 8 rows per lane group."""
     A, v, B, _ = problem(m, n, d, K, 8, kind)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
-    for chunk in (0, 7, 1, 33):  # widths up to the 64 KiB LDS budget (64 rows at K = 256)
-        C = run_spmm(spk, A, v, B, spk.Plan(4, lanes, chunk))
-        assert_within(C, C64, M, TOL_F32, f"tile K={K} lanes={lanes} chunk={chunk}")
+    for chunk in (0, 7, 1, 31):  # widths within the two-buffer LDS budget (32 rows at K = 256)
+        for flags in (0, 2):
+            C = run_spmm(spk, A, v, B, spk.Plan(4, lanes, chunk, flags))
+            assert_within(C, C64, M, TOL_F32, f"tile K={K} lanes={lanes} chunk={chunk} flags={flags}")
 
 
 def test_spmm_tile_rejects_unfit_plans(spk):
     A, v, B, _ = problem(100, 100, 0.1, 64, 1)
     for plan in (spk.Plan(4, 8, 0),      # 8 lanes x 4 < K
                  spk.Plan(4, 16, 1 << 20),  # slab larger than the LDS budget
-                 spk.Plan(4, 16, 0, 2)):    # unknown flag
+                 spk.Plan(4, 16, 0, 4)):    # unknown flag
         with pytest.raises(spk.SpkError) as e:
             run_spmm(spk, A, v, B, plan)
         assert e.value.status == -6
@@ -108,7 +109,8 @@ def test_spmm_pattern_mode_and_empty_rows(spk):
     A = host_csr(6, 9, [[], [0, 4, 8], [2], [], [], [1, 2, 3, 4, 5, 6, 7]])
     B = synth.normal((9, 20), 1, synth.S_B)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, None, B)
-    for plan in (None, spk.Plan(1, 4, 3), spk.Plan(1, 8, 1), spk.Plan(0, 4), spk.Plan(3, 4, 2)):
+    for plan in (None, spk.Plan(1, 4, 3), spk.Plan(1, 8, 1), spk.Plan(0, 4), spk.Plan(3, 4, 2), spk.Plan(4, 8, 3),
+                 spk.Plan(4, 8, 2, 2)):
         C = run_spmm(spk, A, None, B, plan, pattern=True)
         assert_within(C, C64, M, TOL_F32, "pattern")
         assert not C[[0, 3, 4]].any()
@@ -122,7 +124,8 @@ def test_spmm_special_cases_bit_exact(spk):
     pi = np.random.default_rng(0).permutation(n).astype(np.int32)
     perm = synth.HostCSR(n, n, np.arange(n + 1, dtype=np.int32), pi)
     dvals = synth.normal(n, 2, synth.S_VALS)
-    for plan in (None, spk.Plan(1, 16, 7), spk.Plan(0, 4, 0, 1), spk.Plan(3, 16, 256)):
+    for plan in (None, spk.Plan(1, 16, 7), spk.Plan(0, 4, 0, 1), spk.Plan(3, 16, 256), spk.Plan(4, 16, 32),
+                 spk.Plan(4, 16, 0, 2)):
         assert np.array_equal(run_spmm(spk, eye, np.ones(n, np.float32), B, plan), B)
         assert np.array_equal(run_spmm(spk, perm, None, B, plan, pattern=True), B[pi])
         C = run_spmm(spk, eye, dvals, B, plan)
