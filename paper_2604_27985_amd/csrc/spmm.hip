@@ -157,74 +157,85 @@ __global__ __launch_bounds__(kBlock) void spmm_slab_kernel(int64_t m, int K, con
     }
 }
 
-// TILE staging.  A slab of B rows [c0, c0 + w) is copied to LDS as [w][K]
-// with gfx950's direct 16-byte global->LDS loads: each lane fetches one 16-byte
-// piece and the hardware writes the pieces of a wave to 1 KiB of contiguous
-// LDS (lane i at byte 16 i past the wave's base), so piece idx of the slab
-// lands at byte 16 idx -- exactly the row-major [w][K] layout.  No registers
-// hold the data; the loads count against vmcnt and are waited for before the
-// barrier that publishes the slab.
+// ------------------------------------------------------------------ TILE
+// A workgroup owns GPB*RPG consecutive rows (RPG per lane group) and walks
+// the columns in slabs of W; each slab of B is copied once to LDS and every
+// group gathers its rows' entries of that slab from LDS.  A staged row of B
+// serves (rows per workgroup) x density entries on average, which cuts the
+// L2 gather traffic by that factor for dense-ish matrices.
+//
+// Memory waits are left to the compiler, which can count them exactly
+// because every slab issues the same loads: the next slab's copy (NPT
+// 16-byte pieces per thread, read into registers right after the barrier
+// that opens a slab and written to the other LDS buffer at its end) and the
+// column and value loads of every row's next chunk.  The copy's
+// latency hides behind the gathers of the current slab; a chunk fetched in
+// one slab is first used in the next.
 template <typename TB> constexpr int kTileSV = 16 / sizeof(TB);
+constexpr int kTilePiece = kBlock * 16;  // bytes one copy round of a workgroup moves (4 KiB)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-typedef const __attribute__((address_space(1))) void *global_cptr;
-typedef __attribute__((address_space(3))) void *lds_ptr;
-
-template <typename TB>
-__device__ __forceinline__ void tile_stage(const TB *__restrict__ B, int64_t ldb, int64_t c0, int w, int per_row,
-                                           TB *dst) {
+// Slab [c0, c0 + w) of B as [w][K] pieces of 16 bytes: thread t holds pieces
+// t + i * kBlock.  Indices past the slab are clamped to its last piece, so
+// every thread always issues NPT loads; their copies land in the buffer's
+// tail beyond the slab (a buffer holds NPT * 4 KiB).
+template <typename TB, int NPT>
+__device__ __forceinline__ void tile_load(const TB *__restrict__ B, int64_t ldb, int64_t c0, int w, int per_row,
+                                          u32x4 (&stg)[NPT]) {
     const int items = w * per_row;
-    const int lane = threadIdx.x & (kWave - 1);
-    for (int base = threadIdx.x & ~(kWave - 1); base < items; base += kBlock) {  // wave-uniform
-        const int idx = base + lane;
-        if (idx < items) {
-            const int rr = idx / per_row;
-            const int cc = (idx - rr * per_row) * kTileSV<TB>;
-            __builtin_amdgcn_global_load_lds((global_cptr)(B + (c0 + rr) * ldb + cc),
-                                             (lds_ptr)(dst + base * kTileSV<TB>), 16, 0, 0);
-        }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int idx0 = static_cast<int>(threadIdx.x) + i * kBlock;
+        const int idx = idx0 < items ? idx0 : items - 1;
+        const int rr = idx / per_row;
+        const int cc = (idx - rr * per_row) * kTileSV<TB>;
+        stg[i] = *reinterpret_cast<const u32x4 *>(B + (c0 + rr) * ldb + cc);
     }
 }
 
-__device__ __forceinline__ void tile_stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
-// Next chunk of one row: lane lig reads entry p = cursor + lig.  The index is
-// clamped to the last entry of the matrix so the load is unconditional (no
-// divergent branch for the compiler to wait at); whether the entry belongs to
-// the row is decided where it is used, from its position.
-template <typename TV, typename A>
-__device__ __forceinline__ void tile_fetch(int64_t p, int64_t last, const int32_t *__restrict__ ci,
-                                           const TV *__restrict__ vals, int &c, A &v) {
-    const int64_t q = p < last ? p : last;
-    c = ci[q];
-    if (vals) v = static_cast<A>(vals[q]);  // uniform branch on a kernel argument
-    else v = A(1);
+template <typename TB, int NPT>
+__device__ __forceinline__ void tile_store(TB *dst, const u32x4 (&stg)[NPT]) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i)
+        *reinterpret_cast<u32x4 *>(dst + (static_cast<int>(threadIdx.x) + i * kBlock) * kTileSV<TB>) = stg[i];
 }
 
-// One pass over the chunk (c, v) held for a row: the lanes whose entry lies
-// in the slab [c0, c1) form a prefix (entries are sorted); that prefix is
-// gathered from LDS, the cursor advanced past it and the chunk at the new
-// cursor fetched.  Returns the prefix length (0: the chunk is kept).
+// Next chunk of one row: the lane reads entry p (its position in the chunk
+// is fixed by the caller).  The index is clamped to the last entry of the
+// matrix so both loads are always issued; whether the entry belongs to the
+// row, and whether a value array exists (else vsrc aliases the column array
+// and the weight is 1), is decided where the chunk is used.
+template <typename TV>
+__device__ __forceinline__ void tile_fetch(int64_t p, int64_t last, const int32_t *__restrict__ ci,
+                                           const TV *__restrict__ vsrc, int &c, TV &v) {
+    const int64_t q = p < last ? p : last;
+    c = ci[q];
+    v = vsrc[q];
+}
+
+// One pass for groups of fewer than 16 lanes (K <= 32): lane lig holds entry
+// cursor + lig; the in-slab prefix (entries are sorted) is gathered with
+// ds_bpermute broadcasts, the cursor advanced past it and the chunk at the
+// new cursor fetched.  Returns the prefix length.
 template <typename TB, typename TV, int VW, int LANES>
-__device__ __forceinline__ int tile_pass(const TB *buf, int K, int koff, int32_t c0, int32_t c1, int gbase,
-                                         uint64_t gmask, int lig, const int32_t *__restrict__ ci,
-                                         const TV *__restrict__ vals, int64_t last, int64_t &cur, int64_t end,
-                                         int &c, typename acc_of<TB>::type &v, typename acc_of<TB>::type (&acc)[VW]) {
-    using A = typename acc_of<TB>::type;
+__device__ __forceinline__ int tile_pass(const TB *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
+                                         int gbase, uint64_t gmask, int lig, bool has_vals,
+                                         const int32_t *__restrict__ ci, const TV *__restrict__ vsrc, int64_t last,
+                                         int64_t &cur, int64_t end, int &c, TV &v, float (&acc)[VW]) {
     constexpr int U = LANES < 8 ? LANES : 8;
     const bool in = cur + lig < end && c < c1;
     const int cnt = __popcll(__ballot(in) & gmask);
-    if (cnt == 0) return 0;  // group-uniform
     const int crel = in ? c - c0 : 0;
-    const A vin = in ? v : A(0);
+    const float vin = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
     for (int t = 0; t < cnt; t += U) {
         int cc[U];
-        A vv[U];
+        float vv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             cc[u] = lane_read(crel, gbase + t + u);
             vv[u] = lane_read(vin, gbase + t + u);
         }
-        A bv[U][VW];
+        float bv[U][VW];
 #pragma unroll
         for (int u = 0; u < U; ++u) vec_load<TB, VW>::run(buf + cc[u] * K + koff, bv[u]);
 #pragma unroll
@@ -232,8 +243,8 @@ __device__ __forceinline__ int tile_pass(const TB *buf, int K, int koff, int32_t
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[e] = fma(vv[u], bv[u][e], acc[e]);
     }
-    cur += cnt;
-    tile_fetch(cur + lig, last, ci, vals, c, v);
+    cur += cnt;  // a chunk with nothing in the slab is fetched again unchanged
+    tile_fetch(cur + lig, last, ci, vsrc, c, v);
     return cnt;
 }
 
@@ -251,7 +262,7 @@ __device__ __forceinline__ float row_bcast(float v) {
 // Entries N .. N+3 of the chunk: LDS offset and weight broadcast from lanes
 // N .. N+3 of each 16-lane row, four independent gathers, then the FMAs.
 template <typename TB, int VW, int N>
-__device__ __forceinline__ void tile_quad(const TB *buf, int off, float w, float (&acc)[VW]) {
+__device__ __forceinline__ void tile_quad(const TB *__restrict__ buf, int off, float w, float (&acc)[VW]) {
     const int o[4] = {row_bcast<N>(off), row_bcast<N + 1>(off), row_bcast<N + 2>(off), row_bcast<N + 3>(off)};
     const float x[4] = {row_bcast<N>(w), row_bcast<N + 1>(w), row_bcast<N + 2>(w), row_bcast<N + 3>(w)};
     float bv[4][VW];
@@ -263,82 +274,68 @@ __device__ __forceinline__ void tile_quad(const TB *buf, int off, float w, float
         for (int e = 0; e < VW; ++e) acc[e] = fma(x[q], bv[q][e], acc[e]);
 }
 
-// Pass for groups of 16 or more lanes: every 16-lane row of a group holds the
-// same 16-entry chunk (lane r16 = lane mod 16 holds entry cursor + r16).  The
-// in-slab prefix of each group is gathered by broadcasting entry u from lane
-// u of the row; the loop bound is the longest prefix in the wave (a uniform
-// branch), shorter groups add zero-weight terms of a valid LDS row.
+// One pass for groups of 16 or more lanes: every 16-lane row of a group holds
+// the same 16-entry chunk (lane r16 = lane mod 16 holds entry cursor + r16).
+// The in-slab prefix is gathered by broadcasting entry u from lane u of the
+// row, four entries at a time (group-divergent: a group runs only the quads
+// its prefix reaches); the last quad adds zero-weight terms of a valid LDS row.
 template <typename TB, typename TV, int VW>
-__device__ __forceinline__ int tile_pass16(const TB *buf, int K, int koff, int32_t c0, int32_t c1, int r16,
-                                           uint64_t gmask16, const int32_t *__restrict__ ci,
-                                           const TV *__restrict__ vals, int64_t last, int64_t &cur, int64_t end,
-                                           int &c, float &v, float (&acc)[VW]) {
+__device__ __forceinline__ int tile_pass16(const TB *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
+                                           int r16, uint64_t gmask16, bool has_vals, const int32_t *__restrict__ ci,
+                                           const TV *__restrict__ vsrc, int64_t last, int64_t &cur, int64_t end,
+                                           int &c, TV &v, float (&acc)[VW]) {
     const bool in = cur + r16 < end && c < c1;
-    const uint64_t bal = __ballot(in);
-    const int cnt = __popcll(bal & gmask16);
-    const uint32_t any = static_cast<uint32_t>((bal | bal >> 16 | bal >> 32 | bal >> 48) & 0xFFFF);
-    if (any == 0) return 0;  // wave-uniform: nothing of these rows in the slab
-    const int longest = 32 - __clz(any);  // prefixes: the union is the longest one
+    const int cnt = __popcll(__ballot(in) & gmask16);
     // the row offset is broadcast; each lane adds its own K offset via bk
     const int off = in ? (c - c0) * K : 0;
-    const float w = in ? v : 0.f;
+    const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
     const TB *bk = buf + koff;
-    tile_quad<TB, VW, 0>(bk, off, w, acc);
-    if (longest > 4) tile_quad<TB, VW, 4>(bk, off, w, acc);
-    if (longest > 8) tile_quad<TB, VW, 8>(bk, off, w, acc);
-    if (longest > 12) tile_quad<TB, VW, 12>(bk, off, w, acc);
+    if (cnt > 0) tile_quad<TB, VW, 0>(bk, off, w, acc);
+    if (cnt > 4) tile_quad<TB, VW, 4>(bk, off, w, acc);
+    if (cnt > 8) tile_quad<TB, VW, 8>(bk, off, w, acc);
+    if (cnt > 12) tile_quad<TB, VW, 12>(bk, off, w, acc);
     cur += cnt;  // a chunk with nothing in the slab is fetched again unchanged
-    tile_fetch(cur + r16, last, ci, vals, c, v);
+    tile_fetch(cur + r16, last, ci, vsrc, c, v);
     return cnt;
 }
 
-// The entries of one row inside the slab.  The chunk held on entry was
-// fetched during an earlier slab and is complete after the barrier, so the
-// first pass waits for nothing; its fetch is first used in the next slab.
-// Only a chunk wholly inside the slab needs the fresh chunk at once, and only
-// that rarer loop waits for it.
+// The entries of one row inside the slab.  The first pass uses the chunk
+// fetched during the previous slab; only a chunk wholly inside the slab needs
+// the fresh chunk at once, and only that rarer loop waits for it.
 template <typename TB, typename TV, int VW, int LANES>
-__device__ __forceinline__ void tile_row(const TB *buf, int K, int koff, int32_t c0, int32_t c1, int gbase,
-                                         uint64_t gmask, int lig, const int32_t *__restrict__ ci,
-                                         const TV *__restrict__ vals, int64_t last, int64_t &cur, int64_t end,
-                                         int &c, typename acc_of<TB>::type &v, typename acc_of<TB>::type (&acc)[VW]) {
+__device__ __forceinline__ void tile_row(const TB *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
+                                         int gbase, uint64_t gmask, int lig, bool has_vals,
+                                         const int32_t *__restrict__ ci, const TV *__restrict__ vsrc, int64_t last,
+                                         int64_t &cur, int64_t end, int &c, TV &v, float (&acc)[VW]) {
     if constexpr (LANES >= 16) {
         const int r16 = lig & 15;
         const uint64_t gmask16 = 0xFFFFull << gbase;
-        if (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gmask16, ci, vals, last, cur, end, c, v, acc) == 16) {
-            while (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gmask16, ci, vals, last, cur, end, c, v,
-                                           acc) == 16) {
+        if (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gmask16, has_vals, ci, vsrc, last, cur, end, c, v,
+                                    acc) == 16) {
+            while (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gmask16, has_vals, ci, vsrc, last, cur, end, c,
+                                           v, acc) == 16) {
             }
         }
     } else {
-        if (tile_pass<TB, TV, VW, LANES>(buf, K, koff, c0, c1, gbase, gmask, lig, ci, vals, last, cur, end, c, v,
-                                         acc) == LANES) {
-            while (tile_pass<TB, TV, VW, LANES>(buf, K, koff, c0, c1, gbase, gmask, lig, ci, vals, last, cur, end, c,
-                                                v, acc) == LANES) {
+        if (tile_pass<TB, TV, VW, LANES>(buf, K, koff, c0, c1, gbase, gmask, lig, has_vals, ci, vsrc, last, cur, end,
+                                         c, v, acc) == LANES) {
+            while (tile_pass<TB, TV, VW, LANES>(buf, K, koff, c0, c1, gbase, gmask, lig, has_vals, ci, vsrc, last,
+                                                cur, end, c, v, acc) == LANES) {
             }
         }
     }
 }
 
-// TILE: a workgroup owns GPB*RPG consecutive rows (RPG per group) and walks
-// the columns in slabs of W; each slab of B is staged once in LDS and every
-// group gathers its rows' entries of that slab from LDS.  A staged row of B
-// serves (rows per workgroup) x density entries on average, which cuts the
-// L2 gather traffic by that factor for dense-ish matrices.  Per slab a wave
-// waits for global memory once: at the barrier that publishes the slab (the
-// slab's copy and the rows' chunk fetches were issued during the previous
-// slab).  Values are read directly (the launcher gathers permuted values
-// into the workspace first).
-template <typename TB, typename TV, int VW, int LANES, int RPG>
+template <typename TB, typename TV, int VW, int LANES, int RPG, int NPT>
 __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n, int64_t nnz, int K,
                                                            const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
                                                            const TV *__restrict__ vals, const TB *__restrict__ B,
-                                                           int64_t ldb, typename acc_of<TB>::type *__restrict__ C,
-                                                           int64_t ldc, int W) {
-    using A = typename acc_of<TB>::type;
+                                                           int64_t ldb, float *__restrict__ C, int64_t ldc, int W) {
+    static_assert(sizeof(TV) == 4, "values are F32 on this path");
     extern __shared__ __align__(16) unsigned char smem[];
-    TB *Bs = reinterpret_cast<TB *>(smem);  // two buffers of [W][K]
+    TB *Bs = reinterpret_cast<TB *>(smem);  // two buffers of NPT * 4 KiB
+    constexpr int buf_elems = NPT * kTilePiece / static_cast<int>(sizeof(TB));
     constexpr int GPB = kBlock / LANES;
     const int lane = threadIdx.x & (kWave - 1);
     const int lig = threadIdx.x & (LANES - 1);
@@ -350,40 +347,48 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
     const bool kvalid = k0 < K;
     const int koff = kvalid ? k0 : 0;
     const int64_t last = nnz - 1;
+    const bool has_vals = vals != nullptr;
+    const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
+    const int pos = LANES >= 16 ? (lig & 15) : lig;  // the lane's entry within a chunk
+    const int per_row = K / kTileSV<TB>;              // K is a multiple of the 16-byte width
     int64_t cur[RPG], end[RPG];
-    int pc[RPG];
-    A pv[RPG], acc[RPG][VW];
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
         const int64_t row = row0 + r;
         cur[r] = row < m ? rp[row] : 0;
         end[r] = row < m ? rp[row + 1] : 0;
-        zero<A, VW>(acc[r]);
-        tile_fetch(cur[r] + (LANES >= 16 ? (lig & 15) : lig), last, ci, vals, pc[r], pv[r]);
     }
-    const int per_row = K / kTileSV<TB>;  // K is a multiple of the 16-byte width
-    const int buf_elems = W * K;          // buffer b starts at Bs + b * buf_elems
-    tile_stage(B, ldb, 0, static_cast<int>(n < W ? n : W), per_row, Bs);
+    u32x4 stg[NPT];
+    tile_load<TB, NPT>(B, ldb, 0, static_cast<int>(n < W ? n : W), per_row, stg);
+    tile_store<TB, NPT>(Bs, stg);
+    int pc[RPG];
+    TV pv[RPG];
+    float acc[RPG][VW];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+        zero<float, VW>(acc[r]);
+        tile_fetch(cur[r] + pos, last, ci, vsrc, pc[r], pv[r]);
+    }
     int sl = 0;
     for (int32_t c0 = 0; c0 < n; c0 += W, ++sl) {
         const int32_t c1 = static_cast<int32_t>(n - c0 < W ? n : c0 + W);
-        tile_stage_wait();
         __syncthreads();  // slab sl is in LDS; every group is done with the other buffer
+        // The next slab's copy into registers; the last slab reads itself
+        // again so that every slab issues the same loads.
+        const int32_t nx = c1 < n ? c1 : c0;
+        tile_load<TB, NPT>(B, ldb, nx, static_cast<int>(n - nx < W ? n - nx : W), per_row, stg);
         const TB *buf = Bs + (sl & 1) * buf_elems;
-        // unrolled so each row's state stays in registers
 #pragma unroll
         for (int r = 0; r < RPG; ++r)
-            tile_row<TB, TV, VW, LANES>(buf, K, koff, c0, c1, gbase, gmask, lig, ci, vals, last, cur[r], end[r],
-                                        pc[r], pv[r], acc[r]);
-        if (c1 < n)
-            tile_stage(B, ldb, c1, static_cast<int>(n - c1 < W ? n - c1 : W), per_row,
-                       Bs + ((sl + 1) & 1) * buf_elems);
+            tile_row<TB, TV, VW, LANES>(buf, K, koff, c0, c1, gbase, gmask, lig, has_vals, ci, vsrc, last, cur[r],
+                                        end[r], pc[r], pv[r], acc[r]);
+        tile_store<TB, NPT>(Bs + ((sl + 1) & 1) * buf_elems, stg);
     }
     if (!kvalid) return;
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
         const int64_t row = row0 + r;
-        if (row < m) vec_store<A, VW>::run(C + row * ldc + k0, acc[r]);
+        if (row < m) vec_store<float, VW>::run(C + row * ldc + k0, acc[r]);
     }
 }
 
@@ -562,17 +567,29 @@ __global__ void gather_vals_kernel(int64_t nnz, const TV *__restrict__ vals, con
     if (p < nnz) out[p] = vals[vperm[p]];
 }
 
-template <typename TB, typename TV, int VW, int LANES, int RPG>
-static hipError_t launch_tile_rpg(const SpmmArgs &a, const TV *vals, hipStream_t s) {
+template <typename TB, typename TV, int VW, int LANES, int RPG, int NPT>
+static hipError_t launch_tile_npt(const SpmmArgs &a, const TV *vals, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
     const int64_t rows_per_block = GPB * RPG;
     const int64_t nb = (a.m + rows_per_block - 1) / rows_per_block;
-    const size_t lds = 2 * static_cast<size_t>(a.chunk) * static_cast<size_t>(a.K) * sizeof(TB);  // two slabs
-    if (nb > 0x7FFFFFFF || a.K > LANES * VW || lds > kTileLds || a.n > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((spmm_tile_kernel<TB, TV, VW, LANES, RPG>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), lds, s,
-                       a.m, a.n, a.nnz, static_cast<int>(a.K), a.rp, a.ci, vals, static_cast<const TB *>(a.B), a.ldb,
-                       static_cast<typename acc_of<TB>::type *>(a.C), a.ldc, static_cast<int>(a.chunk));
+    const size_t lds = 2 * static_cast<size_t>(NPT) * kTilePiece;  // two slab buffers
+    hipLaunchKernelGGL((spmm_tile_kernel<TB, TV, VW, LANES, RPG, NPT>), dim3(static_cast<unsigned>(nb)), dim3(kBlock),
+                       lds, s, a.m, a.n, a.nnz, static_cast<int>(a.K), a.rp, a.ci, vals, static_cast<const TB *>(a.B),
+                       a.ldb, static_cast<float *>(a.C), a.ldc, static_cast<int>(a.chunk));
     return hipGetLastError();
+}
+
+template <typename TB, typename TV, int VW, int LANES, int RPG>
+static hipError_t launch_tile_rpg(const SpmmArgs &a, const TV *vals, hipStream_t s) {
+    const int64_t rows_per_block = (kBlock / LANES) * RPG;
+    const int64_t nb = (a.m + rows_per_block - 1) / rows_per_block;
+    const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TB));
+    if (nb > 0x7FFFFFFF || a.K > LANES * VW || a.chunk < 1 || 2 * slab_bytes > kTileLds || a.n > 0x7FFFFFFF)
+        return hipErrorInvalidValue;
+    // copy rounds per slab: 2, 4 or 8 (a buffer of 8, 16 or 32 KiB)
+    if (slab_bytes <= 2 * kTilePiece) return launch_tile_npt<TB, TV, VW, LANES, RPG, 2>(a, vals, s);
+    if (slab_bytes <= 4 * kTilePiece) return launch_tile_npt<TB, TV, VW, LANES, RPG, 4>(a, vals, s);
+    return launch_tile_npt<TB, TV, VW, LANES, RPG, 8>(a, vals, s);
 }
 
 template <typename TB, typename TV, int VW, int LANES>
