@@ -82,6 +82,152 @@ def roofline(bytes_, flops, seconds):
             "frac": round(ach / FP32_VALU_PEAK_TFS, 4)}
 
 
+# ------------------------------------------------------------------ profiles
+PROFILES = os.path.join(ROOT, "profiles")
+# kernels of each part of a step (rocprofv3 names), for attributing counter readings
+PART_KERNELS = {"spmm": ("spmm_", "slab_bounds_kernel", "merge_partition_kernel", "merge_fixup_kernel",
+                         "gather_vals_kernel"),
+                "sddmm": ("sddmm_",)}
+
+
+def kernel_source_digest():
+    """sha256 (16 hex digits) of the HIP sources and the C header: counter
+    readings taken from another source state are not reported."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2604_27985_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "include", "spk.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _read_csv(path):
+    import csv
+
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d, suffix):
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def _part_of(kernel):
+    short = kernel.split("(")[0].split("<")[0].replace("void ", "").replace("spk::", "").strip()
+    for part, prefixes in PART_KERNELS.items():
+        if any(short.startswith(p) for p in prefixes):
+            return part, short
+    return None, short
+
+
+def profile_summary(args):
+    """Markdown summary of one rocprofv3 trace pass and two counter passes
+    (FETCH_SIZE, WRITE_SIZE) of the same bench command, written to --out.
+    Counter readings (KiB per dispatch) are scaled by what the same counters
+    read for the run's device copy of --calib-copy GiB (that many GiB read and
+    written), then summed per part of a step and divided by the steps run."""
+    d = args.profile_summary
+    with open(os.path.join(d, "cmd.txt")) as fh:
+        cmds = [ln.rstrip("\n") for ln in fh if ln.strip()]
+    line = None
+    with open(os.path.join(d, "trace.log")) as fh:
+        for ln in fh:
+            if ln.startswith("{") and '"metric"' in ln:
+                line = json.loads(ln)
+    if line is None:
+        raise SystemExit("the trace run printed no bench line")
+    runs = line["steps"] + line["warmup"]
+    stats = _read_csv(_find(os.path.join(d, "trace"), "kernel_stats.csv"))
+    per = {}
+    for tag, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        for r in _read_csv(_find(os.path.join(d, tag), "counter_collection.csv")):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+            per.setdefault(tag, {}).setdefault(key, 0.0)
+            per[tag][key] += float(r["Counter_Value"])
+    calib_bytes = float(args.calib_copy << 30)
+    factor = {}
+    for tag in ("fetch", "write"):
+        copies = [v for (_, k), v in per[tag].items() if "copy" in k.lower()]
+        factor[tag] = calib_bytes / (max(copies) * 1024.0) if copies and max(copies) > 0 else None
+    by_kernel = {}
+    for tag in ("fetch", "write"):
+        for (_, k), v in per[tag].items():
+            e = by_kernel.setdefault(k, {"fetch": [], "write": []})
+            e[tag].append(v)
+    part_bytes = {}
+    rows = []
+    for k, e in sorted(by_kernel.items(), key=lambda kv: -sum(kv[1]["fetch"])):
+        part, short = _part_of(k)
+        nf, nw = len(e["fetch"]), len(e["write"])
+        fkib = sum(e["fetch"]) / max(nf, 1)
+        wkib = sum(e["write"]) / max(nw, 1)
+        scaled = None
+        if factor["fetch"] and factor["write"]:
+            scaled = fkib * 1024 * factor["fetch"] + wkib * 1024 * factor["write"]
+            if part:
+                part_bytes[part] = part_bytes.get(part, 0.0) + scaled * nf / runs
+        rows.append((short, part or "-", nf, fkib, wkib, scaled))
+    digest = kernel_source_digest()
+    out = [f"# rocprofv3: {line['config']['workload']}", "",
+           "Commands (repository root, one MI355X; each counter in a pass of its own):", ""]
+    out += ["    " + c for c in cmds]
+    out += ["", f"Plans: {json.dumps(line['config']['plans'])}; {line['steps']} timed + {line['warmup']} warmup "
+            f"steps; bench line: {line['ms_per_step']} ms per step.", "",
+            f"Kernel sources: sha256 {digest} (paper_2604_27985_amd/csrc/*, include/spk.h).", "",
+            "## Kernel time (--kernel-trace --stats)", "",
+            "| kernel | calls | average us | total ms |", "|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        out.append(f"| {_part_of(r['Name'])[1]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.3f} |")
+    fr = "none found" if factor["fetch"] is None else f"{factor['fetch']:.4f}"
+    wr = "none found" if factor["write"] is None else f"{factor['write']:.4f}"
+    out += ["", "## HBM traffic per dispatch (FETCH_SIZE, WRITE_SIZE)", "",
+            f"Calibration: the device copy of {args.calib_copy} GiB (read and written once); "
+            f"scale factors FETCH {fr}, WRITE {wr}.", "",
+            "| kernel | part | dispatches | FETCH KiB | WRITE KiB | scaled HBM bytes |", "|---|---|---|---|---|---|"]
+    for short, part, n, f, w, sc in rows[:14]:
+        out.append(f"| {short} | {part} | {n} | {f:.0f} | {w:.0f} | {'-' if sc is None else f'{sc:.4g}'} |")
+    if line["config"]["ops"] == "spmm+sddmm":
+        out += ["", "Per step (scaled bytes of a part's kernels over the steps run), read by bench.py while the",
+                "kernel sources keep the digest above:", "", "```"]
+        for part, b in sorted(part_bytes.items()):
+            plan = line["config"]["plans"].get(part, "?")
+            out.append(f"traffic {line['config']['workload']} {part} {plan} {b:.0f} {digest}")
+        out += ["```", ""]
+    else:  # the backward runs SpMM kernels too: kernel names do not separate the parts
+        out += ["", "No per-part traffic: forward and backward share kernel names.", ""]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(out))
+    print("\n".join(out))
+
+
+def recorded_traffic(workload, part, plan):
+    """HBM bytes per launch of a step part from profiles/, or None when no
+    summary matches this workload, part and plan at the current sources."""
+    if not os.path.isdir(PROFILES):
+        return None
+    digest = kernel_source_digest()
+    for f in sorted(os.listdir(PROFILES)):
+        if not f.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, f)) as fh:
+            for ln in fh:
+                t = ln.split()
+                if len(t) == 6 and t[0] == "traffic" and t[1:4] == [workload, part, plan] and t[5] == digest:
+                    return int(float(t[4]))
+    return None
+
+
 def make_problem(name, seed=0):
     from paper_2604_27985_amd import synth
 
@@ -304,7 +450,8 @@ def run_workload(args):
     dom = max(kt, key=lambda k: kt[k]["_t"])
     roof = roofline(kt[dom]["_b"], kt[dom]["_f"], kt[dom]["_t"])
     roof["kernel"] = dom
-    roof["traffic"] = None
+    dom_plan = (p_spmm if dom == "spmm" else p_sddmm)
+    roof["traffic"] = recorded_traffic(name, dom, dom_plan.name() if dom_plan else "plain")
     for v in kt.values():
         for key in ("_b", "_f", "_t"):
             v.pop(key)
@@ -382,7 +529,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--sweep", default=None, help="write the grid sweep to this JSONL file")
     ap.add_argument("--sweep-modes", default="plain,tuned")
+    ap.add_argument("--profile-summary", default=None, metavar="DIR",
+                    help="summarise the rocprofv3 passes under DIR (cmd.txt, trace.log, trace/, fetch/, "
+                         "write/) into --out; no GPU needed")
+    ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(row-sharded designs are described but not built); run with --gpus 1", file=sys.stderr)

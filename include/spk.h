@@ -93,17 +93,23 @@ enum spk_variant {
     SPK_VAR_SLAB = 3,  /* row-split over column slabs: one launch per slab
                           of `chunk` columns, so the slab of the dense operand
                           being gathered stays in L2 */
-    SPK_VAR_TILE = 4   /* SpMM: a workgroup owns (256 / lanes) x 4 rows and
-                          stages each slab of `chunk` rows of B in LDS once,
-                          so every staged row serves all of the workgroup's
-                          entries in it.  F32 or BF16 operands with K <=
-                          4 * lanes, K and ldb multiples of 16 bytes, slab
-                          of at most 64 KiB. */
+    SPK_VAR_TILE = 4   /* SpMM: a workgroup owns (256 / lanes) x 4 (or 8)
+                          rows and stages each slab of `chunk` rows of B in
+                          LDS once, so every staged row serves all of the
+                          workgroup's entries in it.  F32 or BF16 operands
+                          with K <= 4 * lanes, K and ldb multiples of 16
+                          bytes, B and C 16-byte aligned, a slab of at most
+                          32 KiB (two are double-buffered in LDS).
+                          SDDMM: the same scheme with slabs of V and each
+                          group's rows of U in registers; lanes 16, 32 or 64,
+                          K <= 4 * lanes, K and ldv multiples of 16 bytes, V
+                          16-byte aligned, ldu a multiple of 4. */
 };
 
 /* An execution plan: plain data, owned by the caller.
- * variant  one of spk_variant.  SpMM: ROWS, MERGE, SLAB.  SDDMM: ROWS (a
- *          group per row), MERGE (equal runs of entries per group), SLAB.
+ * variant  one of spk_variant.  SpMM: ROWS, MERGE, SLAB, TILE.  SDDMM: ROWS (a
+ *          group per row), MERGE (equal runs of entries per group), SLAB,
+ *          TILE.
  * lanes    lanes cooperating on one row: 4, 8, 16, 32 or 64.  Each lane
  *          covers `vec` consecutive columns of the dense operand (4 for F32
  *          and BF16, 8 for BF16 SpMM when K allows, 2 for F64), so one pass
@@ -112,8 +118,11 @@ enum spk_variant {
  *          SDDMM MERGE: entries per group (0: 256).
  *          SLAB: slab width in columns (0: the width whose slab of the dense
  *          operand takes 2 MiB, at least 256).
+ *          TILE: slab width in rows of B (SDDMM: of V; 0: the largest power
+ *          of two >= 16 whose slab fits 16 KiB).
  * flags    bit 0: use scalar (one element per lane) loads even when the
- *          operands allow 8/16-byte vector loads; other bits must be 0.
+ *          operands allow 8/16-byte vector loads (not TILE).  bit 1 (TILE
+ *          only): 8 rows per lane group instead of 4.  Other bits must be 0.
  * Vector loads are used when K and the leading dimensions are multiples of
  * the vector width and the base pointers are aligned to it; otherwise the
  * call falls back to scalar loads by itself.
@@ -214,15 +223,19 @@ int32_t spmm_bsr4(const spk_bsr4 *A, const void *B, int64_t ldb, int32_t b_dtype
  * the fallback and the judge.
  * ------------------------------------------------------------------------ */
 
-/* Number of plans in an op's plan list (SPK_OP_SPMM: 16, SPK_OP_SDDMM: 15),
+/* Number of plans in an op's plan list (SPK_OP_SPMM: 20, SPK_OP_SDDMM: 19),
  * or 0 for other ops. */
 int32_t plan_count(int32_t op);
 
-/* Plan `index` of an op's plan list: index = 5 v + l picks variant v (ROWS,
- * MERGE, SLAB) and lanes 4 << l; SpMM index 15 is SPK_VAR_BSR4 (lanes 64).
- * SDDMM MERGE plans use 256 entries per group.  *valid is 1 when the plan
- * suits dense width K (lanes not wider than twice K rounded up to a power
- * of two, at least 16; SDDMM: at most 8 register slices).  Host only. */
+/* Plan `index` of an op's plan list: index = 5 v + l (< 15) picks variant v
+ * (ROWS, MERGE, SLAB) and lanes 4 << l; SpMM index 15 is SPK_VAR_BSR4 (lanes
+ * 64); SpMM indices 16..19 are SPK_VAR_TILE with the plain lanes for K and a
+ * slab of 16 KiB (16, 18) or 32 KiB (17, 19) of F32 rows, 8 rows per group
+ * for 18 and 19; SDDMM indices 15..18 are the same four SPK_VAR_TILE plans
+ * (at least 16 lanes).  SDDMM MERGE plans use 256 entries per group.  *valid is 1
+ * when the plan suits dense width K (lanes not wider than twice K rounded up
+ * to a power of two, at least 16; SDDMM: at most 8 register slices; TILE: K
+ * a multiple of 8 in [8, 256]).  Host only. */
 int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid);
 
 /* Integer structural features of A into features (device, 28 int64):

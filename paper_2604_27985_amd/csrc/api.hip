@@ -77,9 +77,10 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
         r.rows_per_group = plan && (plan->flags & 2) ? 8 : 4;
         if (K > 4 * r.lanes || K % sv != 0 || ldb % sv != 0 || !aligned(B, 16) || ldc % 4 != 0 || !aligned(C, 16))
             return SPK_ERR_PLAN;
-        const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * K * static_cast<int64_t>(es));  // two buffers
-        int64_t w = 16;
-        while (w * 2 <= wmax) w *= 2;
+        const int64_t row_bytes = K * static_cast<int64_t>(es);
+        const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * row_bytes);  // two buffers
+        int64_t w = 16;  // default: the largest power of two whose slab fits 16 KiB
+        while (w * 2 * row_bytes <= 16384) w *= 2;
         r.chunk = plan && plan->chunk > 0 ? plan->chunk : w;
         if (r.chunk < 1 || r.chunk > wmax) return SPK_ERR_PLAN;
         r.vec = 4;
@@ -111,6 +112,26 @@ int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U
                     aligned(V, es * v);
     r.vec = ok ? v : 1;
     r.variant = plan ? plan->variant : SPK_VAR_MERGE;
+    if (r.variant == SPK_VAR_TILE) {
+        // groups of 16, 32 or 64 lanes, one 4-wide slice of U and V per lane,
+        // slabs of V rows in 16-byte pieces, two slab buffers in kTileLds
+        const int64_t sv = 16 / static_cast<int64_t>(es);
+        if (dt == SPK_F64 || (plan->flags & ~2) || plan->chunk < 0) return SPK_ERR_PLAN;
+        r.lanes = plan->lanes;
+        r.rows_per_group = (plan->flags & 2) ? 8 : 4;
+        if (r.lanes != 16 && r.lanes != 32 && r.lanes != 64) return SPK_ERR_PLAN;
+        if (K > 4 * r.lanes || K % sv != 0 || ldv % sv != 0 || !aligned(V, 16) || ldu % 4 != 0 ||
+            !aligned(U, 4 * es))
+            return SPK_ERR_PLAN;
+        const int64_t row_bytes = K * static_cast<int64_t>(es);
+        const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * row_bytes);
+        int64_t w = 16;  // default: the largest power of two whose slab fits 16 KiB
+        while (w * 2 * row_bytes <= 16384) w *= 2;
+        r.chunk = plan->chunk > 0 ? plan->chunk : w;
+        if (r.chunk > wmax) return SPK_ERR_PLAN;
+        r.vec = 4;
+        return SPK_OK;
+    }
     if (r.variant != SPK_VAR_ROWS && r.variant != SPK_VAR_MERGE && r.variant != SPK_VAR_SLAB) return SPK_ERR_PLAN;
     if (plan && plan->chunk > 0) r.chunk = plan->chunk;
     else if (r.variant == SPK_VAR_SLAB) r.chunk = default_slab_width(K, es);
@@ -286,7 +307,7 @@ int32_t sddmm_csr(const spk_csr *A, const void *U, int64_t ldu, const void *V, i
     if ((st = resolve_sddmm(plan, K, uv_dtype, U, ldu, V, ldv, r))) return st;
     if ((st = check_ws(sddmm_ws(A->m, A->n, r), ws, ws_bytes))) return st;
     SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, U, ldu, V, ldv, uv_dtype, S,
-                r.variant, r.lanes, r.vec, r.chunk, ws};
+                r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group};
     return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
 }
 
@@ -351,7 +372,7 @@ static int current_device() {
     return d;
 }
 
-int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 16 : op == SPK_OP_SDDMM ? 15 : 0; }
+int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 20 : op == SPK_OP_SDDMM ? 19 : 0; }
 
 int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid) {
     if (!out) return SPK_ERR_NULL;
@@ -359,6 +380,15 @@ int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32
     if (index < 0 || index >= plan_count(op)) return SPK_ERR_PLAN;
     if (op == SPK_OP_SPMM && index == 15) {
         *out = spk_plan{SPK_VAR_BSR4, 64, 0, 0};
+    } else if ((op == SPK_OP_SPMM && index >= 16) || (op == SPK_OP_SDDMM && index >= 15)) {
+        // LDS slabs of 16 or 32 KiB of F32 rows (half that for BF16), 4 or 8 rows per lane group
+        const int t = index - (op == SPK_OP_SPMM ? 16 : 15);
+        const int64_t bytes = t % 2 == 0 ? 16384 : 32768;
+        const int64_t k = K > 0 ? K : 1;
+        const int64_t w = bytes / (4 * k);
+        int32_t lanes = default_spmm_lanes(K);
+        if (op == SPK_OP_SDDMM && lanes < 16) lanes = 16;  // SDDMM TILE reduces over 16-lane rows
+        *out = spk_plan{SPK_VAR_TILE, lanes, static_cast<int32_t>(w > 0 ? w : 1), t >= 2 ? 2 : 0};
     } else {
         static const int32_t variants[3] = {SPK_VAR_ROWS, SPK_VAR_MERGE, SPK_VAR_SLAB};
         const int32_t v = variants[index / 5];

@@ -41,6 +41,7 @@ struct SddmmArgs {
     int32_t variant, lanes, vec;
     int64_t chunk;
     void *ws;
+    int32_t rows_per_group = 4;  // TILE: rows each lane group owns (4 or 8)
 };
 
 // Column slabs of the SLAB variants: nslabs slabs of `width` columns; the

@@ -20,9 +20,12 @@
 //          imbalance;
 //   ROWS   group g takes row g;
 //   SLAB   one launch per slab of W columns, group g takes the entries of row
-//          g in that slab, so the rows of V being gathered stay in L2.
+//          g in that slab, so the rows of V being gathered stay in L2;
+//   TILE   a workgroup owns a block of rows and walks the columns in slabs
+//          of V staged in LDS (the SpMM TILE scheme, tile.h).
 #include "common.h"
 #include "internal.h"
+#include "tile.h"
 
 namespace spk {
 
@@ -269,6 +272,178 @@ __global__ __launch_bounds__(kBlock) void sddmm_rows_kernel(int64_t m, int K, co
     }
 }
 
+// ------------------------------------------------------------------ TILE
+// A workgroup owns GPB*RPG consecutive rows (RPG per group of LANES >= 16
+// lanes) and walks the columns in slabs of W rows of V, each copied once to
+// LDS (double-buffered, the copy of the next slab in flight during the
+// current one).  A group keeps its rows' slices of U in registers and reads
+// each row's entries in chunks of 16 (every 16-lane row of the group holds
+// the same chunk); the in-slab prefix of a chunk is processed four entries at
+// a time: the four rows of V come from LDS, each lane forms four partial dot
+// products, and one transposing reduction over the group sums all four.
+
+// Sum over a 16-lane row of four partial dot products: on return lane l holds
+// entry (l mod 4)'s total.  Two halving steps (partners lane ^ 2, lane ^ 1)
+// leave each lane with one entry summed over its 4-lane subgroup; the four
+// subgroups then hold the same entries in the same lane order and are added
+// with rotations of the row by 4 and 8 lanes (row_ror:4 = 0x124, row_ror:8 =
+// 0x128).
+__device__ __forceinline__ float reduce4_row(float (&x)[4], int lane) {
+    halving_steps<2, 4>(x, lane);
+    float t = x[0];
+    t += dpp<0x124>(t);
+    t += dpp<0x128>(t);
+    return t;
+}
+
+// Entries N .. N+3 of the chunk (valid while N < cnt): S[cur + N + j] for
+// j = 0..3, written by lane j of the group.
+template <typename TUV, int VW, int LANES, int N>
+__device__ __forceinline__ void sddmm_quad(const TUV *__restrict__ bk, int off, float w, const float (&u)[VW],
+                                           int64_t cur, int cnt, float *__restrict__ S, int lig, int lane) {
+    const int o[4] = {row_bcast<N>(off), row_bcast<N + 1>(off), row_bcast<N + 2>(off), row_bcast<N + 3>(off)};
+    const float x[4] = {row_bcast<N>(w), row_bcast<N + 1>(w), row_bcast<N + 2>(w), row_bcast<N + 3>(w)};
+    float vv[4][VW];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vec_load<TUV, VW>::run(bk + o[q], vv[q]);
+    float part[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float acc = 0.f;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc = fma(u[e], vv[q][e], acc);
+        part[q] = acc;
+    }
+    float tot = reduce4_row(part, lane);
+    if constexpr (LANES >= 32) tot += lane_read(tot, lane ^ 16);
+    if constexpr (LANES >= 64) tot += lane_read(tot, lane ^ 32);
+    const int j = lig & 3;
+    const float a = j == 0 ? x[0] : j == 1 ? x[1] : j == 2 ? x[2] : x[3];
+    if (lig < 4 && N + lig < cnt) S[cur + N + lig] = a * tot;
+}
+
+template <typename TUV, typename TV, int VW, int LANES>
+__device__ __forceinline__ int sddmm_tile_pass(const TUV *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
+                                               int lig, int lane, uint64_t gmask16, bool has_vals,
+                                               const int32_t *__restrict__ ci, const TV *__restrict__ vsrc,
+                                               int64_t last, int64_t &cur, int64_t end, int &c, TV &v,
+                                               const float (&u)[VW], float *__restrict__ S) {
+    const int r16 = lig & 15;
+    const bool in = cur + r16 < end && c < c1;
+    const int cnt = __popcll(__ballot(in) & gmask16);
+    const int off = in ? (c - c0) * K : 0;  // row offset in the slab, broadcast; lanes add their own K offset
+    const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
+    const TUV *bk = buf + koff;
+    if (cnt > 0) sddmm_quad<TUV, VW, LANES, 0>(bk, off, w, u, cur, cnt, S, lig, lane);
+    if (cnt > 4) sddmm_quad<TUV, VW, LANES, 4>(bk, off, w, u, cur, cnt, S, lig, lane);
+    if (cnt > 8) sddmm_quad<TUV, VW, LANES, 8>(bk, off, w, u, cur, cnt, S, lig, lane);
+    if (cnt > 12) sddmm_quad<TUV, VW, LANES, 12>(bk, off, w, u, cur, cnt, S, lig, lane);
+    cur += cnt;  // a chunk with nothing in the slab is fetched again unchanged
+    tile_fetch(cur + r16, last, ci, vsrc, c, v);
+    return cnt;
+}
+
+template <typename TUV, typename TV, int VW, int LANES, int RPG, int NPT>
+__global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n, int64_t nnz, int K,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const TV *__restrict__ vals,
+                                                            const TUV *__restrict__ U, int64_t ldu,
+                                                            const TUV *__restrict__ V, int64_t ldv,
+                                                            float *__restrict__ S, int W) {
+    static_assert(LANES >= 16 && sizeof(TV) == 4, "16-lane rows, F32 values");
+    extern __shared__ __align__(16) unsigned char smem[];
+    TUV *Vs = reinterpret_cast<TUV *>(smem);  // two buffers of NPT * 4 KiB
+    constexpr int buf_elems = NPT * kTilePiece / static_cast<int>(sizeof(TUV));
+    constexpr int GPB = kBlock / LANES;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
+    const uint64_t gmask16 = 0xFFFFull << gbase;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = (blk * GPB + threadIdx.x / LANES) * RPG;
+    const int k0 = lig * VW;
+    const bool kvalid = k0 < K;
+    const int koff = kvalid ? k0 : 0;
+    const int64_t last = nnz - 1;
+    const bool has_vals = vals != nullptr;
+    const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
+    const int per_row = K / kTileSV<TUV>;  // K is a multiple of the 16-byte width
+    int64_t cur[RPG], end[RPG];
+    float u[RPG][VW];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+        const int64_t row = row0 + r;
+        cur[r] = row < m ? rp[row] : 0;
+        end[r] = row < m ? rp[row + 1] : 0;
+        if (row < m && kvalid) vec_load<TUV, VW>::run(U + row * ldu + k0, u[r]);
+        else
+#pragma unroll
+            for (int e = 0; e < VW; ++e) u[r][e] = 0.f;  // lanes past K add nothing
+    }
+    u32x4 stg[NPT];
+    tile_load<TUV, NPT>(V, ldv, 0, static_cast<int>(n < W ? n : W), per_row, stg);
+    tile_store<TUV, NPT>(Vs, stg);
+    int pc[RPG];
+    TV pv[RPG];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) tile_fetch(cur[r] + (lig & 15), last, ci, vsrc, pc[r], pv[r]);
+    int sl = 0;
+    for (int32_t c0 = 0; c0 < n; c0 += W, ++sl) {
+        const int32_t c1 = static_cast<int32_t>(n - c0 < W ? n : c0 + W);
+        __syncthreads();  // slab sl is in LDS; every group is done with the other buffer
+        const int32_t nx = c1 < n ? c1 : c0;  // the last slab reads itself again: same loads every slab
+        tile_load<TUV, NPT>(V, ldv, nx, static_cast<int>(n - nx < W ? n - nx : W), per_row, stg);
+        const TUV *buf = Vs + (sl & 1) * buf_elems;
+#pragma unroll
+        for (int r = 0; r < RPG; ++r) {
+            // only a chunk wholly inside the slab needs the fresh chunk at once
+            if (sddmm_tile_pass<TUV, TV, VW, LANES>(buf, K, koff, c0, c1, lig, lane, gmask16, has_vals, ci, vsrc, last,
+                                                    cur[r], end[r], pc[r], pv[r], u[r], S) == 16) {
+                while (sddmm_tile_pass<TUV, TV, VW, LANES>(buf, K, koff, c0, c1, lig, lane, gmask16, has_vals, ci,
+                                                           vsrc, last, cur[r], end[r], pc[r], pv[r], u[r], S) == 16) {
+                }
+            }
+        }
+        tile_store<TUV, NPT>(Vs + ((sl + 1) & 1) * buf_elems, stg);
+    }
+}
+
+template <typename TUV, typename TV, int LANES, int RPG, int NPT>
+static hipError_t launch_tile_npt(const SddmmArgs &a, hipStream_t s) {
+    constexpr int GPB = kBlock / LANES;
+    const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
+    const size_t lds = 2 * static_cast<size_t>(NPT) * kTilePiece;  // two slab buffers
+    hipLaunchKernelGGL((sddmm_tile_kernel<TUV, TV, 4, LANES, RPG, NPT>), dim3(static_cast<unsigned>(nb)), dim3(kBlock),
+                       lds, s, a.m, a.n, a.nnz, static_cast<int>(a.K), a.rp, a.ci, static_cast<const TV *>(a.vals),
+                       static_cast<const TUV *>(a.U), a.ldu, static_cast<const TUV *>(a.V), a.ldv,
+                       static_cast<float *>(a.S), static_cast<int>(a.chunk));
+    return hipGetLastError();
+}
+
+template <typename TUV, typename TV, int LANES, int RPG>
+static hipError_t launch_tile_rpg(const SddmmArgs &a, hipStream_t s) {
+    constexpr int GPB = kBlock / LANES;
+    const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
+    const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TUV));
+    if (nb > 0x7FFFFFFF || a.K > LANES * 4 || a.chunk < 1 || 2 * slab_bytes > kTileLds || a.n > 0x7FFFFFFF)
+        return hipErrorInvalidValue;
+    if (slab_bytes <= 2 * kTilePiece) return launch_tile_npt<TUV, TV, LANES, RPG, 2>(a, s);
+    if (slab_bytes <= 4 * kTilePiece) return launch_tile_npt<TUV, TV, LANES, RPG, 4>(a, s);
+    return launch_tile_npt<TUV, TV, LANES, RPG, 8>(a, s);
+}
+
+template <typename TUV, typename TV>
+static hipError_t launch_tile(const SddmmArgs &a, hipStream_t s) {
+    const bool r8 = a.rows_per_group == 8;
+    switch (a.lanes) {
+    case 16: return r8 ? launch_tile_rpg<TUV, TV, 16, 8>(a, s) : launch_tile_rpg<TUV, TV, 16, 4>(a, s);
+    case 32: return r8 ? launch_tile_rpg<TUV, TV, 32, 8>(a, s) : launch_tile_rpg<TUV, TV, 32, 4>(a, s);
+    case 64: return r8 ? launch_tile_rpg<TUV, TV, 64, 8>(a, s) : launch_tile_rpg<TUV, TV, 64, 4>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
 static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
@@ -337,6 +512,11 @@ static hipError_t dispatch_off(const SddmmArgs &a, hipStream_t s) {
 }
 
 hipError_t sddmm_launch(const SddmmArgs &a, hipStream_t s) {
+    if (a.variant == SPK_VAR_TILE) {
+        if (a.uv_dtype == SPK_F32) return launch_tile<float, float>(a, s);
+        if (a.uv_dtype == SPK_BF16) return launch_tile<bf16, float>(a, s);
+        return hipErrorInvalidValue;
+    }
     switch (a.uv_dtype) {
     case SPK_F32: return a.vec > 1 ? dispatch_off<float, float, 4>(a, s) : dispatch_off<float, float, 1>(a, s);
     case SPK_BF16: return a.vec > 1 ? dispatch_off<bf16, float, 4>(a, s) : dispatch_off<bf16, float, 1>(a, s);

@@ -191,11 +191,13 @@ __device__ void mlp_eval(const float *__restrict__ p, Dims d, const float *x, fl
 __device__ __host__ inline bool plan_valid(int32_t op, int idx, int64_t K) {
     if (op == SPK_OP_SPMM) {
         if (idx == 15) return true;  // 4x4 blocks on matrix cores
+        if (idx >= 16) return K >= 8 && K <= 256 && K % 8 == 0;  // LDS slabs: 16-byte pieces of F32 and BF16 rows
         const int lanes = 4 << (idx % 5);
         int64_t cap = 16;
         while (cap < K) cap <<= 1;
         return lanes == 4 || lanes * 4 <= 2 * cap;
     }
+    if (idx >= 15) return K >= 8 && K <= 256 && K % 8 == 0;  // LDS slabs of V
     const int lanes = 4 << (idx % 5);
     const int64_t ns = (K + lanes * 4 - 1) / (lanes * 4);
     return ns <= 8 && (lanes == 4 || lanes * 4 <= 2 * (K > 4 ? K : 4));

@@ -29,6 +29,7 @@
 // with each value read through perm (vals[perm[q]]).
 #include "common.h"
 #include "internal.h"
+#include "tile.h"
 
 namespace spk {
 
@@ -171,48 +172,6 @@ __global__ __launch_bounds__(kBlock) void spmm_slab_kernel(int64_t m, int K, con
 // column and value loads of every row's next chunk.  The copy's
 // latency hides behind the gathers of the current slab; a chunk fetched in
 // one slab is first used in the next.
-template <typename TB> constexpr int kTileSV = 16 / sizeof(TB);
-constexpr int kTilePiece = kBlock * 16;  // bytes one copy round of a workgroup moves (4 KiB)
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// Slab [c0, c0 + w) of B as [w][K] pieces of 16 bytes: thread t holds pieces
-// t + i * kBlock.  Indices past the slab are clamped to its last piece, so
-// every thread always issues NPT loads; their copies land in the buffer's
-// tail beyond the slab (a buffer holds NPT * 4 KiB).
-template <typename TB, int NPT>
-__device__ __forceinline__ void tile_load(const TB *__restrict__ B, int64_t ldb, int64_t c0, int w, int per_row,
-                                          u32x4 (&stg)[NPT]) {
-    const int items = w * per_row;
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int idx0 = static_cast<int>(threadIdx.x) + i * kBlock;
-        const int idx = idx0 < items ? idx0 : items - 1;
-        const int rr = idx / per_row;
-        const int cc = (idx - rr * per_row) * kTileSV<TB>;
-        stg[i] = *reinterpret_cast<const u32x4 *>(B + (c0 + rr) * ldb + cc);
-    }
-}
-
-template <typename TB, int NPT>
-__device__ __forceinline__ void tile_store(TB *dst, const u32x4 (&stg)[NPT]) {
-#pragma unroll
-    for (int i = 0; i < NPT; ++i)
-        *reinterpret_cast<u32x4 *>(dst + (static_cast<int>(threadIdx.x) + i * kBlock) * kTileSV<TB>) = stg[i];
-}
-
-// Next chunk of one row: the lane reads entry p (its position in the chunk
-// is fixed by the caller).  The index is clamped to the last entry of the
-// matrix so both loads are always issued; whether the entry belongs to the
-// row, and whether a value array exists (else vsrc aliases the column array
-// and the weight is 1), is decided where the chunk is used.
-template <typename TV>
-__device__ __forceinline__ void tile_fetch(int64_t p, int64_t last, const int32_t *__restrict__ ci,
-                                           const TV *__restrict__ vsrc, int &c, TV &v) {
-    const int64_t q = p < last ? p : last;
-    c = ci[q];
-    v = vsrc[q];
-}
-
 // One pass for groups of fewer than 16 lanes (K <= 32): lane lig holds entry
 // cursor + lig; the in-slab prefix (entries are sorted) is gathered with
 // ds_bpermute broadcasts, the cursor advanced past it and the chunk at the
@@ -246,17 +205,6 @@ __device__ __forceinline__ int tile_pass(const TB *__restrict__ buf, int K, int 
     cur += cnt;  // a chunk with nothing in the slab is fetched again unchanged
     tile_fetch(cur + lig, last, ci, vsrc, c, v);
     return cnt;
-}
-
-// row_newbcast:N (DPP control 0x150 + N): every lane of a 16-lane row reads
-// lane N of the same row.  A VALU move; no LDS crossbar traffic.
-template <int N>
-__device__ __forceinline__ int row_bcast(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
-}
-template <int N>
-__device__ __forceinline__ float row_bcast(float v) {
-    return __int_as_float(row_bcast<N>(__float_as_int(v)));
 }
 
 // Entries N .. N+3 of the chunk: LDS offset and weight broadcast from lanes

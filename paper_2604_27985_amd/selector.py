@@ -117,15 +117,18 @@ def inputs(f: torch.Tensor, K: int) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------- timings
-def time_plans(A: api.CSR, K: int, op: int, reps: int = 3, warmup: int = 1) -> list[float | None]:
-    """Median ms of every plan of the op's list (None where invalid for K)."""
+def time_plans(A: api.CSR, K: int, op: int, reps: int = 3, warmup: int = 1,
+               indices: list[int] | None = None) -> list[float | None]:
+    """Median ms of every plan of the op's list, or of the plans `indices`
+    only (None where invalid for K)."""
     from . import autotune
 
     dev = A.row_ptr.device
     B = torch.randn(A.n, K, device=dev)
     U = torch.randn(A.m, K, device=dev) if op == OP_SDDMM else None
     out = []
-    for plan, valid in plan_list(op, K):
+    plans = plan_list(op, K)
+    for plan, valid in (plans if indices is None else [plans[i] for i in indices]):
         if not valid:
             out.append(None)
             continue
@@ -171,6 +174,67 @@ def build_timings(path: str, count: int = 2000, start: int = 0, ops=(OP_SPMM, OP
 def load_timings(path: str) -> list[dict]:
     with open(path) as fh:
         return [json.loads(line) for line in fh]
+
+
+def extend_timings(path: str, out_path: str, op: int, indices: list[int], log=print,
+                   time_budget_s: float | None = None) -> int:
+    """Time plans added to an op's list after `path` was built: every matrix of
+    `path` is generated again from its spec (seeded) and only plans `indices`
+    are timed.  Appends {"index", "op", "plans", "ms"} records to `out_path`
+    (resumable); merge_timings folds them into the timing set."""
+    done = set()
+    if os.path.exists(out_path):
+        with open(out_path) as fh:
+            for line in fh:
+                done.add(json.loads(line)["index"])
+    t0 = time.time()
+    added = 0
+    key = "spmm" if op == OP_SPMM else "sddmm"
+    with open(out_path, "a") as fh:
+        for rec in load_timings(path):
+            i = rec["index"]
+            if i in done:
+                continue
+            if time_budget_s is not None and time.time() - t0 > time_budget_s:
+                break
+            spec = {k: rec[k] for k in ("index", "n", "density", "pattern", "K", "seed", "split")}
+            A, v = make_matrix(spec)
+            assert A.nnz == rec["nnz"], f"matrix {i} does not regenerate"
+            dA = api.CSR.from_host(A, v)
+            ms = time_plans(dA, spec["K"], op, indices=indices)
+            fh.write(json.dumps({"index": i, "op": key, "plans": indices, "ms": ms}) + "\n")
+            fh.flush()
+            added += 1
+            if added % 50 == 0:
+                log(f"[{i}] {added} matrices extended ({time.time() - t0:.0f} s)")
+            del dA
+    return added
+
+
+def merge_timings(path: str, ext_path: str, out_path: str) -> int:
+    """Fold extend_timings records into the timing set: the op's time list of
+    each record is widened to the op's plan count with the new plans' times."""
+    ext = {}
+    with open(ext_path) as fh:
+        for line in fh:
+            e = json.loads(line)
+            ext[(e["index"], e["op"])] = e
+    merged = 0
+    with open(out_path + ".tmp", "w") as fh:
+        for rec in load_timings(path):
+            for op in (OP_SPMM, OP_SDDMM):
+                key = "spmm" if op == OP_SPMM else "sddmm"
+                times = list(rec.get("ms_" + key, []))
+                times += [None] * (plan_count(op) - len(times))
+                e = ext.get((rec["index"], key))
+                if e is not None:
+                    for p, t in zip(e["plans"], e["ms"]):
+                        times[p] = t
+                    merged += 1
+                rec["ms_" + key] = times
+            fh.write(json.dumps(rec) + "\n")
+    os.replace(out_path + ".tmp", out_path)
+    return merged
 
 
 # ---------------------------------------------------------------- dataset
@@ -376,6 +440,16 @@ def main(argv=None) -> None:
     b.add_argument("--out", required=True)
     b.add_argument("--count", type=int, default=2000)
     b.add_argument("--budget", type=float, default=None, help="stop after this many seconds")
+    e = sub.add_parser("extend", help="time plans added to an op's list on an existing timing set (resumable)")
+    e.add_argument("--timings", required=True)
+    e.add_argument("--out", required=True)
+    e.add_argument("--op", choices=("spmm", "sddmm"), required=True)
+    e.add_argument("--plans", required=True, help="first-last plan indices, e.g. 16-19")
+    e.add_argument("--budget", type=float, default=None, help="stop after this many seconds")
+    g = sub.add_parser("merge", help="fold extend records into a timing set")
+    g.add_argument("--timings", required=True)
+    g.add_argument("--ext", required=True)
+    g.add_argument("--out", required=True)
     t = sub.add_parser("train", help="train the selector networks on a timing set")
     t.add_argument("--timings", required=True)
     t.add_argument("--out", default=WEIGHTS_PATH)
@@ -383,16 +457,36 @@ def main(argv=None) -> None:
     t.add_argument("--steps", type=int, default=4000)
     t.add_argument("--lr", type=float, default=3e-3)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--ops", default="spmm,sddmm",
+                   help="ops to train; the other ops' tables are kept from --out")
     args = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)  # noqa: E731
     if args.cmd == "build":
-        n = build_timings(args.out, count=args.count, time_budget_s=args.budget, log=lambda s: print(s, flush=True))
+        n = build_timings(args.out, count=args.count, time_budget_s=args.budget, log=log)
         print(f"added {n} records", flush=True)
         return
+    if args.cmd == "extend":
+        lo, hi = (int(x) for x in args.plans.split("-"))
+        op = OP_SPMM if args.op == "spmm" else OP_SDDMM
+        n = extend_timings(args.timings, args.out, op, list(range(lo, hi + 1)), log=log, time_budget_s=args.budget)
+        print(f"extended {n} records", flush=True)
+        return
+    if args.cmd == "merge":
+        print(f"merged {merge_timings(args.timings, args.ext, args.out)} extensions", flush=True)
+        return
     records = load_timings(args.timings)
+    ops = [OP_SPMM if o == "spmm" else OP_SDDMM for o in args.ops.split(",")]
+    kept = {}
+    if set(ops) != {OP_SPMM, OP_SDDMM} and os.path.exists(args.out):
+        with open(args.out) as fh:
+            kept = {t["op"]: t for t in json.load(fh)["tables"]}
     tables, reports = [], []
     for op in (OP_SPMM, OP_SDDMM):
-        table, report = train_op(records, op, steps=args.steps, lr=args.lr, seed=args.seed,
-                                 log=lambda s: print(s, flush=True))
+        if op not in ops:
+            if op in kept:
+                tables.append(kept[op])
+            continue
+        table, report = train_op(records, op, steps=args.steps, lr=args.lr, seed=args.seed, log=log)
         tables.append(table)
         reports.append(report)
         print(json.dumps({k: v for k, v in report.items() if k != "loss_history"}), flush=True)
@@ -401,6 +495,10 @@ def main(argv=None) -> None:
         json.dump({"format": 1, "device": torch.cuda.get_device_name(0), "timings": os.path.basename(args.timings),
                    "records": len(records), "tables": tables}, fh)
     if args.report:
+        if kept and os.path.exists(args.report):  # keep the reports of ops not retrained
+            with open(args.report) as fh:
+                fresh = {r["op"] for r in reports}
+                reports = [r for r in json.load(fh) if r["op"] not in fresh] + reports
         with open(args.report, "w") as fh:
             json.dump(reports, fh, indent=1)
 

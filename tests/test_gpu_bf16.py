@@ -69,7 +69,9 @@ def test_sddmm_bf16(spk, K):
     S_r, M_r = oracle.sddmm(A.row_ptr, A.col_idx, v, Ur, Vr)
     S_s, M_s = oracle.sddmm(A.row_ptr, A.col_idx, v, U32, V32)
     dA = spk.CSR.from_host(A, v)
-    for plan in (None, spk.Plan(1, 16, 256), spk.Plan(0, 32), spk.Plan(3, 16, 0)):
+    tl = K // 4  # TILE plans: default and odd slab widths, 4 or 8 rows per group
+    for plan in (None, spk.Plan(1, 16, 256), spk.Plan(0, 32), spk.Plan(3, 16, 0), spk.Plan(4, tl, 0),
+                 spk.Plan(4, tl, 9, 2)):
         S = spk.sddmm(dA, Ut, Vt, plan=plan).cpu().numpy()
         assert_within(S, S_r, M_r, TOL_F32, f"bf16 sddmm rounded {plan}")
         assert_within(S, S_s, M_s, TOL_BF16_SRC, f"bf16 sddmm vs fp32 sources {plan}")

@@ -229,6 +229,46 @@ def test_sddmm_powerlaw_and_empty_rows(spk):
         assert_within(run_sddmm(spk, E, ve, Ue, Ve, plan), S64, M, TOL_F32, "empty rows")
 
 
+@pytest.mark.parametrize("K,lanes", [(64, 16), (128, 32), (32, 16), (256, 64), (48, 16), (64, 64), (8, 16)])
+@pytest.mark.parametrize("kind,m,n,d", [("uniform", 3001, 2500, 0.05), ("powerlaw", 6000, 6000, 12),
+                                        ("block4", 1024, 4096, 0.02), ("uniform", 7, 5, 0.5)])
+def test_sddmm_tile(spk, K, lanes, kind, m, n, d):
+    """LDS-staged slabs of V: default, odd and one-row slab widths; 4 or 8 rows per group; pattern mode."""
+    A, v, V, U = problem(m, n, d, K, 11, kind)
+    S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    P64, PM = oracle.sddmm(A.row_ptr, A.col_idx, None, U, V)
+    for chunk in (0, 7, 1, 31):  # within the two-buffer LDS budget (32 rows of V at K = 256)
+        for flags in (0, 2):
+            plan = spk.Plan(4, lanes, chunk, flags)
+            assert_within(run_sddmm(spk, A, v, U, V, plan), S64, M, TOL_F32, f"tile sddmm K={K} {plan.name()}")
+    assert_within(run_sddmm(spk, A, v, U, V, spk.Plan(4, lanes, 5), pattern=True), P64, PM, TOL_F32,
+                  "tile sddmm pattern")
+
+
+def test_sddmm_tile_rejects_unfit_plans(spk):
+    A, v, V, U = problem(100, 100, 0.1, 64, 1)
+    for plan in (spk.Plan(4, 8, 0),      # groups narrower than a 16-lane row
+                 spk.Plan(4, 16, 1 << 20),  # slab beyond the LDS budget
+                 spk.Plan(4, 16, 0, 1),     # scalar loads are not a TILE option
+                 spk.Plan(4, 32, 0, 4)):    # unknown flag
+        with pytest.raises(spk.SpkError) as e:
+            run_sddmm(spk, A, v, U, V, plan)
+        assert e.value.status == -6
+    with pytest.raises(spk.SpkError):  # K above 4 x lanes
+        A2, v2, V2, U2 = problem(100, 100, 0.1, 96, 1)
+        run_sddmm(spk, A2, v2, U2, V2, spk.Plan(4, 16, 0))
+
+
+def test_sddmm_tile_empty_rows_and_single_entries(spk):
+    E = host_csr(7, 5, [[], [], [1, 3], [], [0, 1, 2, 3, 4], [], [4]])
+    Ue = synth.normal((7, 16), 1, synth.S_U)
+    Ve = synth.normal((5, 16), 1, synth.S_V)
+    ve = synth.normal(E.nnz, 1, synth.S_VALS)
+    S64, M = oracle.sddmm(E.row_ptr, E.col_idx, ve, Ue, Ve)
+    for plan in (spk.Plan(4, 16, 1), spk.Plan(4, 16, 3), spk.Plan(4, 16, 0, 2), spk.Plan(4, 64, 2)):
+        assert_within(run_sddmm(spk, E, ve, Ue, Ve, plan), S64, M, TOL_F32, f"empty rows {plan.name()}")
+
+
 def test_sddmm_deterministic(spk):
     A, v, V, U = problem(3000, 3000, 0.02, 64, 9)
     s1 = run_sddmm(spk, A, v, U, V)

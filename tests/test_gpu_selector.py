@@ -101,7 +101,7 @@ def test_mlp_forward_grad_adam_match_oracle(spk, sel):
 def test_plan_select_matches_oracle_argmin(spk, sel):
     """plan_select's plan is the argmin, over valid plans, of the FP64 oracle network on
     the same features (near-ties excluded)."""
-    P = 16
+    P = sel.plan_count(0)
     parts = rand_params(P, seed=3)
     mean = np.linspace(0, 0.5, 32).astype(np.float32)
     scale = np.linspace(0.5, 1.5, 32).astype(np.float32)
@@ -123,7 +123,8 @@ def test_plan_select_matches_oracle_argmin(spk, sel):
         if y[order[1]] - y[order[0]] < 1e-3:
             continue
         expect = sel.plan_list(0, K)[order[0]][0]
-        assert (plan.variant, plan.lanes, plan.chunk) == (expect.variant, expect.lanes, expect.chunk)
+        assert (plan.variant, plan.lanes, plan.chunk, plan.flags) == (expect.variant, expect.lanes, expect.chunk,
+                                                                      expect.flags)
         checked += 1
     assert checked >= 4
     sel._loaded.clear()

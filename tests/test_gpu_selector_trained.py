@@ -67,4 +67,5 @@ def test_device_path_picks_the_offline_choice(sel, shipped):
             assert A.nnz == r["nnz"]
             plan = sel.select(spk.CSR.from_host(A, v), r["K"], op, fallback=False)
             expect = sel.plan_list(op, r["K"])[int(p)][0]
-            assert (plan.variant, plan.lanes, plan.chunk) == (expect.variant, expect.lanes, expect.chunk), r["index"]
+            assert (plan.variant, plan.lanes, plan.chunk, plan.flags) == (
+                expect.variant, expect.lanes, expect.chunk, expect.flags), r["index"]

@@ -1,4 +1,5 @@
 """Host-side logic of the plan selector (CPU only; the C ABI's host-only calls)."""
+import json
 import math
 import os
 
@@ -14,9 +15,16 @@ from paper_2604_27985_amd import selector  # noqa: E402
 
 
 def test_plan_lists():
-    assert selector.plan_count(_lib.OP_SPMM) == 16 and selector.plan_count(_lib.OP_SDDMM) == 15
+    assert selector.plan_count(_lib.OP_SPMM) == 20 and selector.plan_count(_lib.OP_SDDMM) == 19
     pl = selector.plan_list(_lib.OP_SPMM, 64)
     assert [p.variant for p, _ in pl[:15]] == [0] * 5 + [1] * 5 + [3] * 5 and pl[15][0].variant == 2
+    # LDS slabs of 16 / 32 KiB of F32 rows (K = 64: 256-byte rows), 4 or 8 rows per group
+    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in pl[16:]] == [
+        (4, 16, 64, 0), (4, 16, 128, 0), (4, 16, 64, 2), (4, 16, 128, 2)]
+    assert all(ok for _, ok in pl[16:])
+    for K, ok in ((8, True), (36, False), (256, True), (512, False)):
+        assert all(v == ok for _, v in selector.plan_list(_lib.OP_SPMM, K)[16:]), K
+    assert [p.chunk for p, _ in selector.plan_list(_lib.OP_SPMM, 256)[16:18]] == [16, 32]
     assert [p.lanes for p, _ in pl[:5]] == [4, 8, 16, 32, 64]
     # K = 64: lanes x 4 up to 2 x 64
     assert [ok for _, ok in pl[:5]] == [True, True, True, True, False]
@@ -25,6 +33,10 @@ def test_plan_lists():
     # 4 lanes x 4 wide x 8 slices = 128 < 256
     assert not sd[0][1] and sd[1][1]
     assert all(p.chunk == 256 for p, _ in sd[5:10])
+    # SDDMM TILE plans: at least 16 lanes (reductions over 16-lane rows)
+    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in selector.plan_list(_lib.OP_SDDMM, 32)[15:]] == [
+        (4, 16, 128, 0), (4, 16, 256, 0), (4, 16, 128, 2), (4, 16, 256, 2)]
+    assert [p.lanes for p, _ in sd[15:]] == [64] * 4 and all(ok for _, ok in sd[15:])
 
 
 def test_plain_index_matches_null_plan_rule():
@@ -76,3 +88,19 @@ def test_regret_stats_and_choice():
     assert st["max_regret"] == 3.0 and st["median_regret"] == 2.0
     # plain = plan 0: times (1, 3, 2) against picks (2, 3, 2)
     assert math.isclose(st["geomean_gain_over_plain"], float(np.exp(np.log(np.array([0.5, 1.0, 1.0])).mean())))
+
+
+def test_extended_timings_merge(tmp_path):
+    """Times of plans added later are folded in at their plan indices."""
+    base = tmp_path / "t.jsonl"
+    ext = tmp_path / "e.jsonl"
+    out = tmp_path / "m.jsonl"
+    recs = [{"index": 0, "ms_spmm": [1.0] * 16, "ms_sddmm": [2.0] * 15},
+            {"index": 1, "ms_spmm": [3.0] * 16, "ms_sddmm": [4.0] * 15}]
+    base.write_text("".join(json.dumps(r) + "\n" for r in recs))
+    ext.write_text(json.dumps({"index": 1, "op": "spmm", "plans": [16, 17, 18, 19], "ms": [0.5, None, 0.7, 0.8]}) + "\n")
+    assert selector.merge_timings(str(base), str(ext), str(out)) == 1
+    m = selector.load_timings(str(out))
+    assert m[0]["ms_spmm"] == [1.0] * 16 + [None] * 4
+    assert m[1]["ms_spmm"] == [3.0] * 16 + [0.5, None, 0.7, 0.8]
+    assert m[1]["ms_sddmm"] == [4.0] * 15 + [None] * 4  # widened to the SDDMM plan count
