@@ -333,13 +333,16 @@ __device__ __forceinline__ int sddmm_tile_pass(const TUV *__restrict__ buf, int 
     const int cnt = __popcll(__ballot(in) & gmask16);
     const int off = in ? (c - c0) * K : 0;  // row offset in the slab, broadcast; lanes add their own K offset
     const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
-    const TUV *bk = buf + koff;
-    if (cnt > 0) sddmm_quad<TUV, VW, LANES, 0>(bk, off, w, u, cur, cnt, S, lig, lane);
-    if (cnt > 4) sddmm_quad<TUV, VW, LANES, 4>(bk, off, w, u, cur, cnt, S, lig, lane);
-    if (cnt > 8) sddmm_quad<TUV, VW, LANES, 8>(bk, off, w, u, cur, cnt, S, lig, lane);
-    if (cnt > 12) sddmm_quad<TUV, VW, LANES, 12>(bk, off, w, u, cur, cnt, S, lig, lane);
-    cur += cnt;  // a chunk with nothing in the slab is fetched again unchanged
+    // the next chunk's fetch goes out before the gathers (off and w hold what
+    // they need of this one); a chunk with nothing in the slab is fetched again
+    const int64_t p0 = cur;
+    cur += cnt;
     tile_fetch(cur + r16, last, ci, vsrc, c, v);
+    const TUV *bk = buf + koff;
+    if (cnt > 0) sddmm_quad<TUV, VW, LANES, 0>(bk, off, w, u, p0, cnt, S, lig, lane);
+    if (cnt > 4) sddmm_quad<TUV, VW, LANES, 4>(bk, off, w, u, p0, cnt, S, lig, lane);
+    if (cnt > 8) sddmm_quad<TUV, VW, LANES, 8>(bk, off, w, u, p0, cnt, S, lig, lane);
+    if (cnt > 12) sddmm_quad<TUV, VW, LANES, 12>(bk, off, w, u, p0, cnt, S, lig, lane);
     return cnt;
 }
 

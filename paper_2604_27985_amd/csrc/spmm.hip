@@ -186,6 +186,8 @@ __device__ __forceinline__ int tile_pass(const TB *__restrict__ buf, int K, int 
     const int cnt = __popcll(__ballot(in) & gmask);
     const int crel = in ? c - c0 : 0;
     const float vin = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
+    cur += cnt;  // the next chunk's fetch goes out before the gathers
+    tile_fetch(cur + lig, last, ci, vsrc, c, v);
     for (int t = 0; t < cnt; t += U) {
         int cc[U];
         float vv[U];
@@ -202,8 +204,6 @@ __device__ __forceinline__ int tile_pass(const TB *__restrict__ buf, int K, int 
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[e] = fma(vv[u], bv[u][e], acc[e]);
     }
-    cur += cnt;  // a chunk with nothing in the slab is fetched again unchanged
-    tile_fetch(cur + lig, last, ci, vsrc, c, v);
     return cnt;
 }
 
@@ -237,13 +237,15 @@ __device__ __forceinline__ int tile_pass16(const TB *__restrict__ buf, int K, in
     // the row offset is broadcast; each lane adds its own K offset via bk
     const int off = in ? (c - c0) * K : 0;
     const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
+    // the next chunk's fetch goes out before the gathers (off and w hold what
+    // they need of this one); a chunk with nothing in the slab is fetched again
+    cur += cnt;
+    tile_fetch(cur + r16, last, ci, vsrc, c, v);
     const TB *bk = buf + koff;
     if (cnt > 0) tile_quad<TB, VW, 0>(bk, off, w, acc);
     if (cnt > 4) tile_quad<TB, VW, 4>(bk, off, w, acc);
     if (cnt > 8) tile_quad<TB, VW, 8>(bk, off, w, acc);
     if (cnt > 12) tile_quad<TB, VW, 12>(bk, off, w, acc);
-    cur += cnt;  // a chunk with nothing in the slab is fetched again unchanged
-    tile_fetch(cur + r16, last, ci, vsrc, c, v);
     return cnt;
 }
 

@@ -55,9 +55,15 @@ def plan_list(op: int, K: int) -> list[tuple[api.Plan, bool]]:
 
 # ---------------------------------------------------------------- specs
 def sample_spec(index: int, cap: int = NNZ_CAP) -> dict:
-    """Matrix `index` of the selector set: n log-uniform in [4096, 524288] (multiple
-    of 64), density log-uniform in [1e-4, 0.1] (redrawn while the expected entry
-    count exceeds `cap`), pattern and K uniform."""
+    """Matrix `index` of the selector set.  Indices below LARGE_FIRST: n
+    log-uniform in [4096, 524288] (multiple of 64), density log-uniform in
+    [1e-4, 0.1] (redrawn while the expected entry count exceeds `cap`),
+    pattern and K uniform.  From LARGE_FIRST on, the regime of the paper's
+    workloads (N x N up to N = 65536 at 90-99.9% sparsity, and denser): n
+    log-uniform in [8192, 131072], density log-uniform in [1e-3, 0.3] (at most
+    LARGE_CAP expected entries), half of them uniform."""
+    if index >= LARGE_FIRST:
+        return _large_spec(index)
     rng = np.random.default_rng([2604, 27985, index])
     pattern = PATTERNS[int(rng.integers(len(PATTERNS)))]
     K = KS[int(rng.integers(len(KS)))]
@@ -65,6 +71,23 @@ def sample_spec(index: int, cap: int = NNZ_CAP) -> dict:
         n = int(round(math.exp(rng.uniform(math.log(4096), math.log(524288))) / 64) * 64)
         d = math.exp(rng.uniform(math.log(1e-4), math.log(0.1)))
         if expected_nnz(n, d, pattern) <= cap:
+            break
+    return {"index": index, "n": n, "density": d, "pattern": pattern, "K": K, "seed": index,
+            "split": "test" if index % 5 == 0 else "train"}
+
+
+LARGE_FIRST = 2000
+LARGE_CAP = 6e8
+
+
+def _large_spec(index: int) -> dict:
+    rng = np.random.default_rng([2604, 27985, 1, index])
+    pattern = "uniform" if rng.uniform() < 0.5 else PATTERNS[1 + int(rng.integers(len(PATTERNS) - 1))]
+    K = KS[int(rng.integers(len(KS)))]
+    while True:
+        n = int(round(math.exp(rng.uniform(math.log(8192), math.log(131072))) / 64) * 64)
+        d = math.exp(rng.uniform(math.log(1e-3), math.log(0.3)))
+        if expected_nnz(n, d, pattern) <= LARGE_CAP:
             break
     return {"index": index, "n": n, "density": d, "pattern": pattern, "K": K, "seed": index,
             "split": "test" if index % 5 == 0 else "train"}
@@ -439,6 +462,7 @@ def main(argv=None) -> None:
     b = sub.add_parser("build", help="time every plan on seeded synthetic matrices (resumable)")
     b.add_argument("--out", required=True)
     b.add_argument("--count", type=int, default=2000)
+    b.add_argument("--start", type=int, default=0)
     b.add_argument("--budget", type=float, default=None, help="stop after this many seconds")
     e = sub.add_parser("extend", help="time plans added to an op's list on an existing timing set (resumable)")
     e.add_argument("--timings", required=True)
@@ -462,7 +486,7 @@ def main(argv=None) -> None:
     args = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     if args.cmd == "build":
-        n = build_timings(args.out, count=args.count, time_budget_s=args.budget, log=log)
+        n = build_timings(args.out, count=args.count, start=args.start, time_budget_s=args.budget, log=log)
         print(f"added {n} records", flush=True)
         return
     if args.cmd == "extend":

@@ -1,8 +1,9 @@
 """The shipped selector against the exhaustive search (GPU).
 
-The timing set (2000 seeded synthetic matrices, every plan timed on an
-MI355X) ships with the package; the network was trained on its train split
-(index % 5 != 0).  On the held-out split the learned plan must be within 10%
+The timing set (2250 seeded synthetic matrices: 2000 of up to 2^24 entries
+and 250 large ones in the regime of the paper's workloads, every plan timed
+on an MI355X) ships with the package; the network was trained on its train
+split (index % 5 != 0).  On the held-out split the learned plan must be within 10%
 of the timed best in geometric mean, and the test reports what it gains over
 the plain method (NULL plan).  A few held-out matrices are regenerated and
 run through the full device path (plan_select) to check it picks what the
@@ -43,7 +44,7 @@ def test_held_out_regret_and_gain(sel, shipped, op):
     tables, records = shipped
     table = tables[op]
     test = [r for r in records if r["split"] == "test"]
-    assert len(test) == 400
+    assert len(test) == sum(1 for r in records if r["index"] % 5 == 0) >= 400
     pick = sel.offline_choices(table, test)
     _, _, _, times = sel.dataset(test, op)
     plain = np.array([sel.plain_index(op, r["K"]) for r in test])
