@@ -300,7 +300,7 @@ __device__ __forceinline__ float reduce4_row(float (&x)[4], int lane) {
 // j = 0..3, written by lane j of the group.
 template <typename TUV, int VW, int LANES, int N>
 __device__ __forceinline__ void sddmm_quad(const TUV *__restrict__ bk, int off, float w, const float (&u)[VW],
-                                           int64_t cur, int cnt, float *__restrict__ S, int lig, int lane) {
+                                           int32_t cur, int cnt, float *__restrict__ S, int lig, int lane) {
     const int o[4] = {row_bcast<N>(off), row_bcast<N + 1>(off), row_bcast<N + 2>(off), row_bcast<N + 3>(off)};
     const float x[4] = {row_bcast<N>(w), row_bcast<N + 1>(w), row_bcast<N + 2>(w), row_bcast<N + 3>(w)};
     float vv[4][VW];
@@ -319,14 +319,14 @@ __device__ __forceinline__ void sddmm_quad(const TUV *__restrict__ bk, int off, 
     if constexpr (LANES >= 64) tot += lane_read(tot, lane ^ 32);
     const int j = lig & 3;
     const float a = j == 0 ? x[0] : j == 1 ? x[1] : j == 2 ? x[2] : x[3];
-    if (lig < 4 && N + lig < cnt) S[cur + N + lig] = a * tot;
+    if (lig < 4 && N + lig < cnt) S[static_cast<uint32_t>(cur + N + lig)] = a * tot;
 }
 
 template <typename TUV, typename TV, int VW, int LANES>
 __device__ __forceinline__ int sddmm_tile_pass(const TUV *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
                                                int lig, int lane, uint64_t gmask16, bool has_vals,
                                                const int32_t *__restrict__ ci, const TV *__restrict__ vsrc,
-                                               int64_t last, int64_t &cur, int64_t end, int &c, TV &v,
+                                               int32_t last, int32_t &cur, int32_t end, int &c, TV &v,
                                                const float (&u)[VW], float *__restrict__ S) {
     const int r16 = lig & 15;
     const bool in = cur + r16 < end && c < c1;
@@ -335,7 +335,7 @@ __device__ __forceinline__ int sddmm_tile_pass(const TUV *__restrict__ buf, int 
     const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
     // the next chunk's fetch goes out before the gathers (off and w hold what
     // they need of this one); a chunk with nothing in the slab is fetched again
-    const int64_t p0 = cur;
+    const int32_t p0 = cur;
     cur += cnt;
     tile_fetch(cur + r16, last, ci, vsrc, c, v);
     const TUV *bk = buf + koff;
@@ -368,11 +368,11 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
     const int k0 = lig * VW;
     const bool kvalid = k0 < K;
     const int koff = kvalid ? k0 : 0;
-    const int64_t last = nnz - 1;
+    const int32_t last = static_cast<int32_t>(nnz - 1);  // row_ptr is int32: positions fit
     const bool has_vals = vals != nullptr;
     const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
     const int per_row = K / kTileSV<TUV>;  // K is a multiple of the 16-byte width
-    int64_t cur[RPG], end[RPG];
+    int32_t cur[RPG], end[RPG];
     float u[RPG][VW];
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
@@ -385,7 +385,9 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
             for (int e = 0; e < VW; ++e) u[r][e] = 0.f;  // lanes past K add nothing
     }
     u32x4 stg[NPT];
-    tile_load<TUV, NPT>(V, ldv, 0, static_cast<int>(n < W ? n : W), per_row, stg);
+    TileCopy<TUV, NPT> copy;
+    copy.layout(static_cast<int>(n < W ? n : W), per_row);
+    copy.load(V, ldv, 0, stg);
     tile_store<TUV, NPT>(Vs, stg);
     int pc[RPG];
     TV pv[RPG];
@@ -396,7 +398,8 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
         const int32_t c1 = static_cast<int32_t>(n - c0 < W ? n : c0 + W);
         __syncthreads();  // slab sl is in LDS; every group is done with the other buffer
         const int32_t nx = c1 < n ? c1 : c0;  // the last slab reads itself again: same loads every slab
-        tile_load<TUV, NPT>(V, ldv, nx, static_cast<int>(n - nx < W ? n - nx : W), per_row, stg);
+        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row);  // a narrower last slab
+        copy.load(V, ldv, nx, stg);
         const TUV *buf = Vs + (sl & 1) * buf_elems;
 #pragma unroll
         for (int r = 0; r < RPG; ++r) {

@@ -179,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void spmm_slab_kernel(int64_t m, int K, con
 template <typename TB, typename TV, int VW, int LANES>
 __device__ __forceinline__ int tile_pass(const TB *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
                                          int gbase, uint64_t gmask, int lig, bool has_vals,
-                                         const int32_t *__restrict__ ci, const TV *__restrict__ vsrc, int64_t last,
-                                         int64_t &cur, int64_t end, int &c, TV &v, float (&acc)[VW]) {
+                                         const int32_t *__restrict__ ci, const TV *__restrict__ vsrc, int32_t last,
+                                         int32_t &cur, int32_t end, int &c, TV &v, float (&acc)[VW]) {
     constexpr int U = LANES < 8 ? LANES : 8;
     const bool in = cur + lig < end && c < c1;
     const int cnt = __popcll(__ballot(in) & gmask);
@@ -230,7 +230,7 @@ __device__ __forceinline__ void tile_quad(const TB *__restrict__ buf, int off, f
 template <typename TB, typename TV, int VW>
 __device__ __forceinline__ int tile_pass16(const TB *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
                                            int r16, uint64_t gmask16, bool has_vals, const int32_t *__restrict__ ci,
-                                           const TV *__restrict__ vsrc, int64_t last, int64_t &cur, int64_t end,
+                                           const TV *__restrict__ vsrc, int32_t last, int32_t &cur, int32_t end,
                                            int &c, TV &v, float (&acc)[VW]) {
     const bool in = cur + r16 < end && c < c1;
     const int cnt = __popcll(__ballot(in) & gmask16);
@@ -255,8 +255,8 @@ __device__ __forceinline__ int tile_pass16(const TB *__restrict__ buf, int K, in
 template <typename TB, typename TV, int VW, int LANES>
 __device__ __forceinline__ void tile_row(const TB *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
                                          int gbase, uint64_t gmask, int lig, bool has_vals,
-                                         const int32_t *__restrict__ ci, const TV *__restrict__ vsrc, int64_t last,
-                                         int64_t &cur, int64_t end, int &c, TV &v, float (&acc)[VW]) {
+                                         const int32_t *__restrict__ ci, const TV *__restrict__ vsrc, int32_t last,
+                                         int32_t &cur, int32_t end, int &c, TV &v, float (&acc)[VW]) {
     if constexpr (LANES >= 16) {
         const int r16 = lig & 15;
         const uint64_t gmask16 = 0xFFFFull << gbase;
@@ -296,12 +296,12 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
     const int k0 = lig * VW;
     const bool kvalid = k0 < K;
     const int koff = kvalid ? k0 : 0;
-    const int64_t last = nnz - 1;
+    const int32_t last = static_cast<int32_t>(nnz - 1);  // row_ptr is int32: positions fit
     const bool has_vals = vals != nullptr;
     const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
     const int pos = LANES >= 16 ? (lig & 15) : lig;  // the lane's entry within a chunk
     const int per_row = K / kTileSV<TB>;              // K is a multiple of the 16-byte width
-    int64_t cur[RPG], end[RPG];
+    int32_t cur[RPG], end[RPG];
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
         const int64_t row = row0 + r;
@@ -309,7 +309,9 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
         end[r] = row < m ? rp[row + 1] : 0;
     }
     u32x4 stg[NPT];
-    tile_load<TB, NPT>(B, ldb, 0, static_cast<int>(n < W ? n : W), per_row, stg);
+    TileCopy<TB, NPT> copy;
+    copy.layout(static_cast<int>(n < W ? n : W), per_row);
+    copy.load(B, ldb, 0, stg);
     tile_store<TB, NPT>(Bs, stg);
     int pc[RPG];
     TV pv[RPG];
@@ -326,7 +328,8 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
         // The next slab's copy into registers; the last slab reads itself
         // again so that every slab issues the same loads.
         const int32_t nx = c1 < n ? c1 : c0;
-        tile_load<TB, NPT>(B, ldb, nx, static_cast<int>(n - nx < W ? n - nx : W), per_row, stg);
+        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row);  // a narrower last slab
+        copy.load(B, ldb, nx, stg);
         const TB *buf = Bs + (sl & 1) * buf_elems;
 #pragma unroll
         for (int r = 0; r < RPG; ++r)

@@ -10,23 +10,37 @@ template <typename TB> constexpr int kTileSV = 16 / sizeof(TB);
 constexpr int kTilePiece = kBlock * 16;  // bytes one copy round of a workgroup moves (4 KiB)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Slab [c0, c0 + w) of B as [w][K] pieces of 16 bytes: thread t holds pieces
-// t + i * kBlock.  Indices past the slab are clamped to its last piece, so
-// every thread always issues NPT loads; their copies land in the buffer's
-// tail beyond the slab (a buffer holds NPT * 4 KiB).
+// Copy of a slab [c0, c0 + w) of B as [w][K] pieces of 16 bytes: thread t
+// moves pieces t + i * kBlock.  Indices past the slab are clamped to its last
+// piece, so every thread always issues NPT loads; their copies land in the
+// buffer's tail beyond the slab (a buffer holds NPT * 4 KiB).  The pieces'
+// (row, column) positions depend only on the slab width, so they are
+// computed once per width (packed as row << 16 | column: rows of a slab and
+// the columns of a piece are below 2^16) instead of dividing every slab.
 template <typename TB, int NPT>
-__device__ __forceinline__ void tile_load(const TB *__restrict__ B, int64_t ldb, int64_t c0, int w, int per_row,
-                                          u32x4 (&stg)[NPT]) {
-    const int items = w * per_row;
+struct TileCopy {
+    int pos[NPT];
+
+    __device__ __forceinline__ void layout(int w, int per_row) {
+        const int items = w * per_row;
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int idx0 = static_cast<int>(threadIdx.x) + i * kBlock;
-        const int idx = idx0 < items ? idx0 : items - 1;
-        const int rr = idx / per_row;
-        const int cc = (idx - rr * per_row) * kTileSV<TB>;
-        stg[i] = *reinterpret_cast<const u32x4 *>(B + (c0 + rr) * ldb + cc);
+        for (int i = 0; i < NPT; ++i) {
+            const int idx0 = static_cast<int>(threadIdx.x) + i * kBlock;
+            const int idx = idx0 < items ? idx0 : items - 1;
+            const int rr = idx / per_row;
+            pos[i] = (rr << 16) | ((idx - rr * per_row) * kTileSV<TB>);
+        }
     }
-}
+
+    __device__ __forceinline__ void load(const TB *__restrict__ B, int64_t ldb, int64_t c0,
+                                         u32x4 (&stg)[NPT]) const {
+        const TB *base = B + c0 * ldb;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            stg[i] = *reinterpret_cast<const u32x4 *>(base + (static_cast<int64_t>(pos[i] >> 16) * ldb +
+                                                              (pos[i] & 0xFFFF)));
+    }
+};
 
 template <typename TB, int NPT>
 __device__ __forceinline__ void tile_store(TB *dst, const u32x4 (&stg)[NPT]) {
@@ -36,14 +50,15 @@ __device__ __forceinline__ void tile_store(TB *dst, const u32x4 (&stg)[NPT]) {
 }
 
 // Next chunk of one row: the lane reads entry p (its position in the chunk
-// is fixed by the caller).  The index is clamped to the last entry of the
-// matrix so both loads are always issued; whether the entry belongs to the
-// row, and whether a value array exists (else vsrc aliases the column array
-// and the weight is 1), is decided where the chunk is used.
+// is fixed by the caller).  Positions are 32-bit (row_ptr is int32).  The
+// index is clamped to the last entry of the matrix so both loads are always
+// issued; whether the entry belongs to the row, and whether a value array
+// exists (else vsrc aliases the column array and the weight is 1), is decided
+// where the chunk is used.
 template <typename TV>
-__device__ __forceinline__ void tile_fetch(int64_t p, int64_t last, const int32_t *__restrict__ ci,
+__device__ __forceinline__ void tile_fetch(int32_t p, int32_t last, const int32_t *__restrict__ ci,
                                            const TV *__restrict__ vsrc, int &c, TV &v) {
-    const int64_t q = p < last ? p : last;
+    const uint32_t q = static_cast<uint32_t>(p < last ? p : last);
     c = ci[q];
     v = vsrc[q];
 }
