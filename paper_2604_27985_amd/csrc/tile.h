@@ -64,10 +64,13 @@ __device__ __forceinline__ void tile_fetch(int32_t p, int32_t last, const int32_
 }
 
 // row_newbcast:N (DPP control 0x150 + N): every lane of a 16-lane row reads
-// lane N of the same row.  A VALU move; no LDS crossbar traffic.
+// lane N of the same row.  A VALU move; no LDS crossbar traffic.  Every lane
+// has a valid source and all rows and banks are written, so the move needs no
+// prior value (mov_dpp, unlike update_dpp with an old value, adds no
+// zeroing move).
 template <int N>
 __device__ __forceinline__ int row_bcast(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, false);
 }
 template <int N>
 __device__ __forceinline__ float row_bcast(float v) {
