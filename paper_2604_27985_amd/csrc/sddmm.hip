@@ -299,12 +299,12 @@ __device__ __forceinline__ float reduce4_row(float (&x)[4], int lane) {
 }
 
 // Entries N .. N+3 of the chunk (valid while N < cnt): S[cur + N + j] for
-// j = 0..3, written by lane j of the group.
+// j = 0..3, written by lane j of the group (the reduction leaves entry j's
+// total on lane j).
 template <typename TUV, int VW, int LANES, int N>
 __device__ __forceinline__ void sddmm_quad(const TUV *__restrict__ bk, int off, float w, const float (&u)[VW],
                                            int32_t cur, int cnt, float *__restrict__ S, int lig, int lane) {
     const int o[4] = {row_bcast<N>(off), row_bcast<N + 1>(off), row_bcast<N + 2>(off), row_bcast<N + 3>(off)};
-    const float x[4] = {row_bcast<N>(w), row_bcast<N + 1>(w), row_bcast<N + 2>(w), row_bcast<N + 3>(w)};
     float vv[4][VW];
 #pragma unroll
     for (int q = 0; q < 4; ++q) vec_load<TUV, VW>::run(bk + o[q], vv[q]);
@@ -319,8 +319,10 @@ __device__ __forceinline__ void sddmm_quad(const TUV *__restrict__ bk, int off, 
     float tot = reduce4_row(part, lane);
     if constexpr (LANES >= 32) tot += lane_read(tot, lane ^ 16);
     if constexpr (LANES >= 64) tot += lane_read(tot, lane ^ 32);
-    const int j = lig & 3;
-    const float a = j == 0 ? x[0] : j == 1 ? x[1] : j == 2 ? x[2] : x[3];
+    // lane j < 4 stores entry N + j, whose weight sits on lane N + j of the
+    // row: row_shl:N (DPP 0x100 + N) moves it to lane j
+    float a = w;
+    if constexpr (N > 0) a = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(w), 0x100 + N, 0xF, 0xF, true));
     if (lig < 4 && N + lig < cnt) S[static_cast<uint32_t>(cur + N + lig)] = a * tot;
 }
 
