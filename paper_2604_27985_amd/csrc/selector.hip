@@ -129,6 +129,43 @@ __global__ __launch_bounds__(kBlock) void features_blocks_kernel(int64_t m, cons
     }
 }
 
+// The same count with a bitmap of block columns in LDS: one workgroup per
+// block row sets bit j/4 for every entry (i, j) of its four rows, then counts
+// the set bits.  Used while the bitmap of n/4 bits fits kBitmapLds.
+constexpr int64_t kBitmapLds = 65536;
+
+__global__ __launch_bounds__(kBlock) void features_blocks_lds_kernel(int64_t m, int64_t n,
+                                                                     const int32_t *__restrict__ rp,
+                                                                     const int32_t *__restrict__ ci,
+                                                                     unsigned long long *__restrict__ f) {
+    extern __shared__ unsigned int bm[];
+    __shared__ unsigned long long part[kBlock / kWave];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 4;
+    const int64_t r1 = r0 + 4 < m ? r0 + 4 : m;
+    const int64_t a = rp[r0], b = rp[r1];
+    if (a == b) return;  // workgroup-uniform: an empty block row has no blocks
+    const int64_t nwords = (n + 127) / 128;
+    for (int64_t w = threadIdx.x; w < nwords; w += kBlock) bm[w] = 0u;
+    __syncthreads();
+    for (int64_t p = a + threadIdx.x; p < b; p += kBlock) {
+        const uint32_t J = static_cast<uint32_t>(ci[p]) >> 2;
+        atomicOr(&bm[J >> 5], 1u << (J & 31));
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int64_t w = threadIdx.x; w < nwords; w += kBlock) s += __popc(bm[w]);
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if (lane == 0) part[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+        atomicAdd(&f[27], t);
+    }
+}
+
 // ---------------------------------------------------------------- inputs
 __device__ void inputs_of(const long long *f, int64_t K, float *x) {
     const float m = static_cast<float>(f[0]), n = static_cast<float>(f[1]), nnz = static_cast<float>(f[2]);
@@ -388,7 +425,13 @@ hipError_t features_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
     hipLaunchKernelGGL(features_rows_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, rp, ci, uf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     (void)ws;
-    hipLaunchKernelGGL(features_blocks_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, rp, ci, uf);
+    const int64_t bm_bytes = (n + 127) / 128 * 4;
+    const int64_t nbr = (m + 3) / 4;
+    if (bm_bytes <= kBitmapLds && nbr <= 0x7FFFFFFF)
+        hipLaunchKernelGGL(features_blocks_lds_kernel, dim3(static_cast<unsigned>(nbr)), dim3(kBlock),
+                           static_cast<size_t>(bm_bytes), s, m, n, rp, ci, uf);
+    else
+        hipLaunchKernelGGL(features_blocks_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, rp, ci, uf);
     return hipGetLastError();
 }
 

@@ -30,9 +30,14 @@ def sel():
 
 
 @pytest.mark.parametrize("kind,n,d", [("uniform", 3000, 0.01), ("banded", 5000, 0.3), ("powerlaw", 20000, 16),
-                                      ("block4", 4096, 0.01), ("uniform", 33, 0.0), ("uniform", 1 << 18, 2e-5)])
+                                      ("block4", 4096, 0.01), ("uniform", 33, 0.0), ("uniform", 1 << 18, 2e-5),
+                                      ("block4", 1030, 0.05), ("wide", 3_000_000, 1e-4)])
 def test_features_bit_exact(spk, sel, kind, n, d):
-    if kind == "powerlaw":
+    """Feature counts equal the oracle's; the 4x4-block count runs as an LDS
+    bitmap per block row up to 2^21 columns and as binary searches beyond."""
+    if kind == "wide":  # 257 rows (a ragged last block row) x 3e6 columns: the search path
+        A = synth.bernoulli(257, n, d, 1)
+    elif kind == "powerlaw":
         A = synth.powerlaw(n, d, 2.1, 1)
     elif kind == "banded":
         A = synth.bernoulli(n, n, d, 1, band=64)
