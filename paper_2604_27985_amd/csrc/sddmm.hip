@@ -302,12 +302,14 @@ __device__ __forceinline__ float reduce4_row(float (&x)[4], int lane) {
 // j = 0..3, written by lane j of the group (the reduction leaves entry j's
 // total on lane j).
 template <typename TUV, int VW, int LANES, int N>
-__device__ __forceinline__ void sddmm_quad(const TUV *__restrict__ bk, int off, float w, const float (&u)[VW],
-                                           int32_t cur, int cnt, float *__restrict__ S, int lig, int lane) {
-    const int o[4] = {row_bcast<N>(off), row_bcast<N + 1>(off), row_bcast<N + 2>(off), row_bcast<N + 3>(off)};
+__device__ __forceinline__ void sddmm_quad(const unsigned char *__restrict__ smem, uint32_t base, int offb, float w,
+                                           const float (&u)[VW], int32_t cur, int cnt, float *__restrict__ S,
+                                           int lig, int lane) {
+    const uint32_t ad[4] = {row_bcast_add<N>(offb, base), row_bcast_add<N + 1>(offb, base),
+                            row_bcast_add<N + 2>(offb, base), row_bcast_add<N + 3>(offb, base)};
     float vv[4][VW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) vec_load<TUV, VW>::run(bk + o[q], vv[q]);
+    for (int q = 0; q < 4; ++q) vec_load<TUV, VW>::run(reinterpret_cast<const TUV *>(smem + ad[q]), vv[q]);
     float part[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -335,18 +337,21 @@ __device__ __forceinline__ int sddmm_tile_pass(const TUV *__restrict__ buf, int 
     const int r16 = lig & 15;
     const bool in = cur + r16 < end && c < c1;
     const int cnt = __popcll(__ballot(in) & gmask16);
-    const int off = in ? (c - c0) * K : 0;  // row offset in the slab, broadcast; lanes add their own K offset
+    const int offb = in ? (c - c0) * K * static_cast<int>(sizeof(TUV)) : 0;  // row offset in the slab, bytes
     const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
     // the next chunk's fetch goes out before the gathers (off and w hold what
     // they need of this one); a chunk with nothing in the slab is fetched again
     const int32_t p0 = cur;
     cur += cnt;
     tile_fetch(cur + r16, last, ci, vsrc, c, v);
-    const TUV *bk = buf + koff;
-    if (cnt > 0) sddmm_quad<TUV, VW, LANES, 0>(bk, off, w, u, p0, cnt, S, lig, lane);
-    if (cnt > 4) sddmm_quad<TUV, VW, LANES, 4>(bk, off, w, u, p0, cnt, S, lig, lane);
-    if (cnt > 8) sddmm_quad<TUV, VW, LANES, 8>(bk, off, w, u, p0, cnt, S, lig, lane);
-    if (cnt > 12) sddmm_quad<TUV, VW, LANES, 12>(bk, off, w, u, p0, cnt, S, lig, lane);
+    // LDS byte address of a gather: the buffer plus this lane's K offset plus
+    // the broadcast row offset
+    const unsigned char *smem = reinterpret_cast<const unsigned char *>(buf);
+    const uint32_t base = static_cast<uint32_t>(koff * sizeof(TUV));
+    if (cnt > 0) sddmm_quad<TUV, VW, LANES, 0>(smem, base, offb, w, u, p0, cnt, S, lig, lane);
+    if (cnt > 4) sddmm_quad<TUV, VW, LANES, 4>(smem, base, offb, w, u, p0, cnt, S, lig, lane);
+    if (cnt > 8) sddmm_quad<TUV, VW, LANES, 8>(smem, base, offb, w, u, p0, cnt, S, lig, lane);
+    if (cnt > 12) sddmm_quad<TUV, VW, LANES, 12>(smem, base, offb, w, u, p0, cnt, S, lig, lane);
     return cnt;
 }
 

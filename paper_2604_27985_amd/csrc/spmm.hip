@@ -207,15 +207,18 @@ __device__ __forceinline__ int tile_pass(const TB *__restrict__ buf, int K, int 
     return cnt;
 }
 
-// Entries N .. N+3 of the chunk: LDS offset and weight broadcast from lanes
-// N .. N+3 of each 16-lane row, four independent gathers, then the FMAs.
+// Entries N .. N+3 of the chunk: LDS row offset and weight broadcast from
+// lanes N .. N+3 of each 16-lane row, four independent gathers, then the
+// FMAs.
 template <typename TB, int VW, int N>
-__device__ __forceinline__ void tile_quad(const TB *__restrict__ buf, int off, float w, float (&acc)[VW]) {
-    const int o[4] = {row_bcast<N>(off), row_bcast<N + 1>(off), row_bcast<N + 2>(off), row_bcast<N + 3>(off)};
+__device__ __forceinline__ void tile_quad(const unsigned char *__restrict__ smem, uint32_t base, int offb, float w,
+                                          float (&acc)[VW]) {
+    const uint32_t a[4] = {row_bcast_add<N>(offb, base), row_bcast_add<N + 1>(offb, base),
+                           row_bcast_add<N + 2>(offb, base), row_bcast_add<N + 3>(offb, base)};
     const float x[4] = {row_bcast<N>(w), row_bcast<N + 1>(w), row_bcast<N + 2>(w), row_bcast<N + 3>(w)};
     float bv[4][VW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) vec_load<TB, VW>::run(buf + o[q], bv[q]);
+    for (int q = 0; q < 4; ++q) vec_load<TB, VW>::run(reinterpret_cast<const TB *>(smem + a[q]), bv[q]);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -234,18 +237,20 @@ __device__ __forceinline__ int tile_pass16(const TB *__restrict__ buf, int K, in
                                            int &c, TV &v, float (&acc)[VW]) {
     const bool in = cur + r16 < end && c < c1;
     const int cnt = __popcll(__ballot(in) & gmask16);
-    // the row offset is broadcast; each lane adds its own K offset via bk
-    const int off = in ? (c - c0) * K : 0;
+    const int offb = in ? (c - c0) * K * static_cast<int>(sizeof(TB)) : 0;  // row offset in the slab, bytes
     const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
     // the next chunk's fetch goes out before the gathers (off and w hold what
     // they need of this one); a chunk with nothing in the slab is fetched again
     cur += cnt;
     tile_fetch(cur + r16, last, ci, vsrc, c, v);
-    const TB *bk = buf + koff;
-    if (cnt > 0) tile_quad<TB, VW, 0>(bk, off, w, acc);
-    if (cnt > 4) tile_quad<TB, VW, 4>(bk, off, w, acc);
-    if (cnt > 8) tile_quad<TB, VW, 8>(bk, off, w, acc);
-    if (cnt > 12) tile_quad<TB, VW, 12>(bk, off, w, acc);
+    // LDS byte address of a gather: the buffer plus this lane's K offset plus
+    // the broadcast row offset
+    const unsigned char *smem = reinterpret_cast<const unsigned char *>(buf);
+    const uint32_t base = static_cast<uint32_t>(koff * sizeof(TB));
+    if (cnt > 0) tile_quad<TB, VW, 0>(smem, base, offb, w, acc);
+    if (cnt > 4) tile_quad<TB, VW, 4>(smem, base, offb, w, acc);
+    if (cnt > 8) tile_quad<TB, VW, 8>(smem, base, offb, w, acc);
+    if (cnt > 12) tile_quad<TB, VW, 12>(smem, base, offb, w, acc);
     return cnt;
 }
 

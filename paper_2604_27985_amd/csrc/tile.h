@@ -77,4 +77,13 @@ __device__ __forceinline__ float row_bcast(float v) {
     return __int_as_float(row_bcast<N>(__float_as_int(v)));
 }
 
+// An LDS byte address: lane N's row offset (bytes) plus this lane's own base.
+// Written as broadcast-then-add, the compiler folds the broadcast into the
+// add (v_add_u32_dpp): one instruction per entry.  bound_ctrl (all sources
+// are valid here anyway) lets the move go without a prior value.
+template <int N>
+__device__ __forceinline__ uint32_t row_bcast_add(int offb, uint32_t base) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, offb, 0x150 + N, 0xF, 0xF, true)) + base;
+}
+
 }  // namespace spk
