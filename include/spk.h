@@ -99,11 +99,13 @@ enum spk_variant {
                           workgroup's entries in it.  F32 or BF16 operands
                           with K <= 4 * lanes, K and ldb multiples of 16
                           bytes, B and C 16-byte aligned, a slab of at most
-                          32 KiB (two are double-buffered in LDS).
+                          32 KiB (two are double-buffered in LDS) spanning
+                          less than 4 GiB of B (chunk * ldb * element size).
                           SDDMM: the same scheme with slabs of V and each
                           group's rows of U in registers; lanes 16, 32 or 64,
                           K <= 4 * lanes, K and ldv multiples of 16 bytes, V
-                          16-byte aligned, ldu a multiple of 4. */
+                          16-byte aligned, ldu a multiple of 4, chunk * ldv *
+                          element size below 4 GiB. */
 };
 
 /* An execution plan: plain data, owned by the caller.

@@ -83,6 +83,7 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
         while (w * 2 * row_bytes <= 16384) w *= 2;
         r.chunk = plan && plan->chunk > 0 ? plan->chunk : w;
         if (r.chunk < 1 || r.chunk > wmax) return SPK_ERR_PLAN;
+        if (r.chunk * ldb * static_cast<int64_t>(es) >= (int64_t(1) << 32)) return SPK_ERR_PLAN;  // 32-bit slab offsets
         r.vec = 4;
         return SPK_OK;
     }
@@ -129,6 +130,7 @@ int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U
         while (w * 2 * row_bytes <= 16384) w *= 2;
         r.chunk = plan->chunk > 0 ? plan->chunk : w;
         if (r.chunk > wmax) return SPK_ERR_PLAN;
+        if (r.chunk * ldv * static_cast<int64_t>(es) >= (int64_t(1) << 32)) return SPK_ERR_PLAN;  // 32-bit slab offsets
         r.vec = 4;
         return SPK_OK;
     }

@@ -330,13 +330,13 @@ __device__ __forceinline__ void sddmm_quad(const unsigned char *__restrict__ sme
 
 template <typename TUV, typename TV, int VW, int LANES>
 __device__ __forceinline__ int sddmm_tile_pass(const TUV *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
-                                               int lig, int lane, uint64_t gmask16, bool has_vals,
+                                               int lig, int lane, int gbase16, bool has_vals,
                                                const int32_t *__restrict__ ci, const TV *__restrict__ vsrc,
                                                int32_t last, int32_t &cur, int32_t end, int &c, TV &v,
                                                const float (&u)[VW], float *__restrict__ S) {
     const int r16 = lig & 15;
     const bool in = cur + r16 < end && c < c1;
-    const int cnt = __popcll(__ballot(in) & gmask16);
+    const int cnt = count16(__ballot(in), gbase16);
     const int offb = in ? (c - c0) * K * static_cast<int>(sizeof(TUV)) : 0;  // row offset in the slab, bytes
     const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
     // the next chunk's fetch goes out before the gathers (off and w hold what
@@ -371,7 +371,6 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
     const int lane = threadIdx.x & (kWave - 1);
     const int lig = threadIdx.x & (LANES - 1);
     const int gbase = lane & ~(LANES - 1);
-    const uint64_t gmask16 = 0xFFFFull << gbase;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t row0 = (blk * GPB + threadIdx.x / LANES) * RPG;
     const int k0 = lig * VW;
@@ -395,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
     }
     u32x4 stg[NPT];
     TileCopy<TUV, NPT> copy;
-    copy.layout(static_cast<int>(n < W ? n : W), per_row);
+    copy.layout(static_cast<int>(n < W ? n : W), per_row, ldv);
     copy.load(V, ldv, 0, stg);
     tile_store<TUV, NPT>(Vs, stg);
     int pc[RPG];
@@ -407,15 +406,15 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
         const int32_t c1 = static_cast<int32_t>(n - c0 < W ? n : c0 + W);
         __syncthreads();  // slab sl is in LDS; every group is done with the other buffer
         const int32_t nx = c1 < n ? c1 : c0;  // the last slab reads itself again: same loads every slab
-        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row);  // a narrower last slab
+        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row, ldv);  // a narrower last slab
         copy.load(V, ldv, nx, stg);
         const TUV *buf = Vs + (sl & 1) * buf_elems;
 #pragma unroll
         for (int r = 0; r < RPG; ++r) {
             // only a chunk wholly inside the slab needs the fresh chunk at once
-            if (sddmm_tile_pass<TUV, TV, VW, LANES>(buf, K, koff, c0, c1, lig, lane, gmask16, has_vals, ci, vsrc, last,
+            if (sddmm_tile_pass<TUV, TV, VW, LANES>(buf, K, koff, c0, c1, lig, lane, gbase, has_vals, ci, vsrc, last,
                                                     cur[r], end[r], pc[r], pv[r], u[r], S) == 16) {
-                while (sddmm_tile_pass<TUV, TV, VW, LANES>(buf, K, koff, c0, c1, lig, lane, gmask16, has_vals, ci,
+                while (sddmm_tile_pass<TUV, TV, VW, LANES>(buf, K, koff, c0, c1, lig, lane, gbase, has_vals, ci,
                                                            vsrc, last, cur[r], end[r], pc[r], pv[r], u[r], S) == 16) {
                 }
             }

@@ -232,11 +232,11 @@ __device__ __forceinline__ void tile_quad(const unsigned char *__restrict__ smem
 // its prefix reaches); the last quad adds zero-weight terms of a valid LDS row.
 template <typename TB, typename TV, int VW>
 __device__ __forceinline__ int tile_pass16(const TB *__restrict__ buf, int K, int koff, int32_t c0, int32_t c1,
-                                           int r16, uint64_t gmask16, bool has_vals, const int32_t *__restrict__ ci,
+                                           int r16, int gbase16, bool has_vals, const int32_t *__restrict__ ci,
                                            const TV *__restrict__ vsrc, int32_t last, int32_t &cur, int32_t end,
                                            int &c, TV &v, float (&acc)[VW]) {
     const bool in = cur + r16 < end && c < c1;
-    const int cnt = __popcll(__ballot(in) & gmask16);
+    const int cnt = count16(__ballot(in), gbase16);
     const int offb = in ? (c - c0) * K * static_cast<int>(sizeof(TB)) : 0;  // row offset in the slab, bytes
     const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
     // the next chunk's fetch goes out before the gathers (off and w hold what
@@ -264,10 +264,9 @@ __device__ __forceinline__ void tile_row(const TB *__restrict__ buf, int K, int 
                                          int32_t &cur, int32_t end, int &c, TV &v, float (&acc)[VW]) {
     if constexpr (LANES >= 16) {
         const int r16 = lig & 15;
-        const uint64_t gmask16 = 0xFFFFull << gbase;
-        if (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gmask16, has_vals, ci, vsrc, last, cur, end, c, v,
+        if (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gbase, has_vals, ci, vsrc, last, cur, end, c, v,
                                     acc) == 16) {
-            while (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gmask16, has_vals, ci, vsrc, last, cur, end, c,
+            while (tile_pass16<TB, TV, VW>(buf, K, koff, c0, c1, r16, gbase, has_vals, ci, vsrc, last, cur, end, c,
                                            v, acc) == 16) {
             }
         }
@@ -315,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
     }
     u32x4 stg[NPT];
     TileCopy<TB, NPT> copy;
-    copy.layout(static_cast<int>(n < W ? n : W), per_row);
+    copy.layout(static_cast<int>(n < W ? n : W), per_row, ldb);
     copy.load(B, ldb, 0, stg);
     tile_store<TB, NPT>(Bs, stg);
     int pc[RPG];
@@ -333,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
         // The next slab's copy into registers; the last slab reads itself
         // again so that every slab issues the same loads.
         const int32_t nx = c1 < n ? c1 : c0;
-        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row);  // a narrower last slab
+        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row, ldb);  // a narrower last slab
         copy.load(B, ldb, nx, stg);
         const TB *buf = Bs + (sl & 1) * buf_elems;
 #pragma unroll

@@ -14,31 +14,30 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // moves pieces t + i * kBlock.  Indices past the slab are clamped to its last
 // piece, so every thread always issues NPT loads; their copies land in the
 // buffer's tail beyond the slab (a buffer holds NPT * 4 KiB).  The pieces'
-// (row, column) positions depend only on the slab width, so they are
-// computed once per width (packed as row << 16 | column: rows of a slab and
-// the columns of a piece are below 2^16) instead of dividing every slab.
+// byte offsets from the slab's first row depend only on the slab width, so
+// they are computed once per width; they fit 32 bits (the API admits TILE
+// plans only when a slab spans less than 4 GiB of B), so every slab's loads
+// are the uniform slab base plus a 32-bit offset, with no address arithmetic.
 template <typename TB, int NPT>
 struct TileCopy {
-    int pos[NPT];
+    uint32_t off[NPT];
 
-    __device__ __forceinline__ void layout(int w, int per_row) {
+    __device__ __forceinline__ void layout(int w, int per_row, int64_t ldb) {
         const int items = w * per_row;
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int idx0 = static_cast<int>(threadIdx.x) + i * kBlock;
             const int idx = idx0 < items ? idx0 : items - 1;
             const int rr = idx / per_row;
-            pos[i] = (rr << 16) | ((idx - rr * per_row) * kTileSV<TB>);
+            off[i] = static_cast<uint32_t>((rr * ldb + (idx - rr * per_row) * kTileSV<TB>) * sizeof(TB));
         }
     }
 
     __device__ __forceinline__ void load(const TB *__restrict__ B, int64_t ldb, int64_t c0,
                                          u32x4 (&stg)[NPT]) const {
-        const TB *base = B + c0 * ldb;
+        const unsigned char *base = reinterpret_cast<const unsigned char *>(B + c0 * ldb);
 #pragma unroll
-        for (int i = 0; i < NPT; ++i)
-            stg[i] = *reinterpret_cast<const u32x4 *>(base + (static_cast<int64_t>(pos[i] >> 16) * ldb +
-                                                              (pos[i] & 0xFFFF)));
+        for (int i = 0; i < NPT; ++i) stg[i] = *reinterpret_cast<const u32x4 *>(base + off[i]);
     }
 };
 
@@ -75,6 +74,13 @@ __device__ __forceinline__ int row_bcast(int v) {
 template <int N>
 __device__ __forceinline__ float row_bcast(float v) {
     return __int_as_float(row_bcast<N>(__float_as_int(v)));
+}
+
+// Number of set lanes of a ballot among the 16 lanes starting at gbase (a
+// multiple of 16): a 32-bit count on the ballot's half that holds them.
+__device__ __forceinline__ int count16(uint64_t ballot, int gbase) {
+    const uint32_t half = static_cast<uint32_t>(gbase < 32 ? ballot : ballot >> 32);
+    return __popc(half & (0xFFFFu << (gbase & 31)));
 }
 
 // An LDS byte address: lane N's row offset (bytes) plus this lane's own base.

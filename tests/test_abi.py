@@ -75,6 +75,22 @@ def test_spmm_argument_errors(lib):
     assert spmm(csr(), K=0) == 0
 
 
+def test_tile_plan_limits(lib):
+    """TILE plans are refused before launch when they do not fit: groups of K/4
+    lanes at least, slabs within the two-buffer LDS budget, and a slab spanning
+    less than 4 GiB of the dense operand (32-bit copy offsets)."""
+    tile = lambda lanes, chunk, flags=0: _lib.spk_plan(4, lanes, chunk, flags)  # noqa: E731
+    assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(8, 16)) == -6            # 8 lanes x 4 < 64
+    assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(16, 129)) == -6          # 2 x 129 x 256 B > 64 KiB
+    assert spmm(csr(), K=64, ldb=1 << 25, ldc=64, plan=tile(16, 32)) == -6      # 32 x 2^25 x 4 B = 4 GiB
+    assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(16, 16, 4)) == -6        # unknown flag
+    f = lib.sddmm_csr
+    A = csr()
+    assert f(ctypes.byref(A), FAKE, 64, FAKE, 1 << 25, 0, 64, FAKE, ctypes.byref(tile(16, 32)), None, 0,
+             None) == -6
+    assert f(ctypes.byref(A), FAKE, 64, FAKE, 64, 0, 64, FAKE, ctypes.byref(tile(8, 16)), None, 0, None) == -6
+
+
 def test_sddmm_argument_errors(lib):
     A = csr()
     f = lib.sddmm_csr
