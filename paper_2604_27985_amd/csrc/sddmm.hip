@@ -41,16 +41,17 @@ __device__ __forceinline__ const T *row_elem(const T *base, int32_t row, int64_t
 // quad_perm [1,0,3,2] = 0xB1 (partner lane ^ 1), quad_perm [2,3,0,1] = 0x4E
 // (lane ^ 2), row_half_mirror = 0x141 (7 - lane within 8), row_mirror =
 // 0x140 (15 - lane within 16), row_ror:8 = 0x128 (lane ^ 8 within 16).  In
-// each of them every lane has a valid source and all lanes are written, so
-// mov_dpp (no prior value, hence no zeroing move) serves.
+// each of them every lane has a valid source and all lanes are written; with
+// bound_ctrl set the move needs no prior value, and the compiler folds a move
+// whose only use is an add into that add (v_add_f32_dpp).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
