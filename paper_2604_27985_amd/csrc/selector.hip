@@ -39,6 +39,8 @@ __device__ __forceinline__ int params_count(Dims d) { return d.H * d.F + d.H + d
 // f: 0 m, 1 n, 2 nnz, 3..22 row-length histogram (bin 0 empty rows, bin b =
 // [2^(b-1), 2^b), bin 19 >= 2^18), 23 max length, 24 sum of squared lengths,
 // 25 max |i - j|, 26 sum |i - j|, 27 nonempty 4x4 blocks.
+// Grid-stride: a wave per row, rows t, t + stride, ...; each workgroup sums
+// into LDS and adds to f once (a few thousand global atomics in all).
 __global__ __launch_bounds__(kBlock) void features_rows_kernel(int64_t m, const int32_t *__restrict__ rp,
                                                                const int32_t *__restrict__ ci,
                                                                unsigned long long *__restrict__ f) {
@@ -46,8 +48,9 @@ __global__ __launch_bounds__(kBlock) void features_rows_kernel(int64_t m, const 
     if (threadIdx.x < kNFeat) acc[threadIdx.x] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
-    if (row < m) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    for (int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave; row < m;
+         row += stride) {
         const int64_t a = rp[row], b = rp[row + 1];
         unsigned long long bw = 0;
         for (int64_t p = a + lane; p < b; p += kWave) {
@@ -92,15 +95,17 @@ __global__ void features_init_kernel(int64_t m, int64_t n, int64_t nnz, unsigned
 // Number of nonempty 4x4 blocks into f[27].  Entry (i, j) opens block
 // (i/4, j/4) when it is the first entry of row i in block column j/4 and no
 // earlier row of the same block row holds a column in [4(j/4), 4(j/4)+4)
-// (a binary search in each such row).  One wave per row, lanes over entries.
+// (a binary search in each such row).  One wave per row (grid-stride),
+// lanes over entries.
 __global__ __launch_bounds__(kBlock) void features_blocks_kernel(int64_t m, const int32_t *__restrict__ rp,
                                                                  const int32_t *__restrict__ ci,
                                                                  unsigned long long *__restrict__ f) {
     __shared__ unsigned long long part[kBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
     unsigned long long s = 0;
-    if (row < m) {
+    for (int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave; row < m;
+         row += stride) {
         const int64_t a = rp[row], b = rp[row + 1];
         const int64_t first_row = row & ~int64_t(3);
         for (int64_t p = a + lane; p < b; p += kWave) {
@@ -140,20 +145,24 @@ __global__ __launch_bounds__(kBlock) void features_blocks_lds_kernel(int64_t m, 
                                                                      unsigned long long *__restrict__ f) {
     extern __shared__ unsigned int bm[];
     __shared__ unsigned long long part[kBlock / kWave];
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 4;
-    const int64_t r1 = r0 + 4 < m ? r0 + 4 : m;
-    const int64_t a = rp[r0], b = rp[r1];
-    if (a == b) return;  // workgroup-uniform: an empty block row has no blocks
     const int64_t nwords = (n + 127) / 128;
-    for (int64_t w = threadIdx.x; w < nwords; w += kBlock) bm[w] = 0u;
-    __syncthreads();
-    for (int64_t p = a + threadIdx.x; p < b; p += kBlock) {
-        const uint32_t J = static_cast<uint32_t>(ci[p]) >> 2;
-        atomicOr(&bm[J >> 5], 1u << (J & 31));
-    }
-    __syncthreads();
+    const int64_t nbr = (m + 3) / 4;
     unsigned long long s = 0;
-    for (int64_t w = threadIdx.x; w < nwords; w += kBlock) s += __popc(bm[w]);
+    for (int64_t br = blockIdx.x; br < nbr; br += gridDim.x) {  // workgroup-uniform
+        const int64_t r0 = br * 4;
+        const int64_t r1 = r0 + 4 < m ? r0 + 4 : m;
+        const int64_t a = rp[r0], b = rp[r1];
+        if (a == b) continue;  // an empty block row has no blocks
+        for (int64_t w = threadIdx.x; w < nwords; w += kBlock) bm[w] = 0u;
+        __syncthreads();
+        for (int64_t p = a + threadIdx.x; p < b; p += kBlock) {
+            const uint32_t J = static_cast<uint32_t>(ci[p]) >> 2;
+            atomicOr(&bm[J >> 5], 1u << (J & 31));
+        }
+        __syncthreads();
+        for (int64_t w = threadIdx.x; w < nwords; w += kBlock) s += __popc(bm[w]);
+        __syncthreads();  // the next block row clears the bitmap
+    }
     const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int o = kWave / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
@@ -421,17 +430,22 @@ hipError_t features_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
     hipLaunchKernelGGL(features_init_kernel, dim3(1), dim3(64), 0, s, m, n, nnz, uf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || m == 0) return e;
-    const int64_t nb = (m + (kBlock / kWave) - 1) / (kBlock / kWave);
-    hipLaunchKernelGGL(features_rows_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, rp, ci, uf);
+    // grid-stride launches of at most kFeatureBlocks workgroups
+    constexpr int64_t kFeatureBlocks = 2048;
+    const int64_t rows_wg = (m + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const unsigned nb = static_cast<unsigned>(rows_wg < kFeatureBlocks ? rows_wg : kFeatureBlocks);
+    hipLaunchKernelGGL(features_rows_kernel, dim3(nb), dim3(kBlock), 0, s, m, rp, ci, uf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     (void)ws;
     const int64_t bm_bytes = (n + 127) / 128 * 4;
     const int64_t nbr = (m + 3) / 4;
-    if (bm_bytes <= kBitmapLds && nbr <= 0x7FFFFFFF)
-        hipLaunchKernelGGL(features_blocks_lds_kernel, dim3(static_cast<unsigned>(nbr)), dim3(kBlock),
-                           static_cast<size_t>(bm_bytes), s, m, n, rp, ci, uf);
-    else
-        hipLaunchKernelGGL(features_blocks_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, rp, ci, uf);
+    if (bm_bytes <= kBitmapLds) {
+        const unsigned nbb = static_cast<unsigned>(nbr < kFeatureBlocks ? nbr : kFeatureBlocks);
+        hipLaunchKernelGGL(features_blocks_lds_kernel, dim3(nbb), dim3(kBlock), static_cast<size_t>(bm_bytes), s, m,
+                           n, rp, ci, uf);
+    } else {
+        hipLaunchKernelGGL(features_blocks_kernel, dim3(nb), dim3(kBlock), 0, s, m, rp, ci, uf);
+    }
     return hipGetLastError();
 }
 

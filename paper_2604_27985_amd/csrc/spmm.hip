@@ -442,9 +442,20 @@ __global__ __launch_bounds__(kBlock) void merge_fixup_kernel(int64_t ngroups, in
     if (r < 0 || (g > 0 && carry_row[g - 1] == r)) return;
     int64_t g_end = g + 1;
     while (g_end < ngroups && carry_row[g_end] == r) ++g_end;
+    // A long row's run spans many shares: eight carries are loaded at a time
+    // (independent loads in flight) and added in share order, so the sum is
+    // the same as one carry at a time.
+    constexpr int D = 8;
     for (int k = threadIdx.x & (kWave - 1); k < K; k += kWave) {
         A s = A(0);
-        for (int64_t h = g; h < g_end; ++h) s += carry_val[h * K + k];
+        for (int64_t h = g; h < g_end; h += D) {
+            A v[D];
+#pragma unroll
+            for (int u = 0; u < D; ++u) v[u] = h + u < g_end ? carry_val[(h + u) * K + k] : A(0);
+#pragma unroll
+            for (int u = 0; u < D; ++u)
+                if (h + u < g_end) s += v[u];  // wave-uniform condition
+        }
         C[static_cast<int64_t>(r) * ldc + k] += s;
     }
 }

@@ -302,3 +302,33 @@ def test_f64_kernels_match_oracle(spk):
     S64, SM = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
     S = spk.sddmm(dA, dev(U, torch.float64), dev(V, torch.float64)).cpu().numpy()
     assert_within(S, S64, SM, TOL_F64, "f64 sddmm")
+
+
+def test_uniform_90_percent_full_size_sampled(spk):
+    """n = 65536 at 90% sparsity (4.3e8 entries), K = 64, seed 0: the plans the
+    bench times (the learned ones) and the LDS-slab plans, on sampled rows of C
+    and the entries of sampled rows of S."""
+    from paper_2604_27985_amd import selector
+    from spk_testutil import sub_rows
+
+    n, K = 65536, 64
+    p = synth.uniform_problem(n, 0.1, K, 0)
+    A, v = p.A, p.vals
+    dA = spk.CSR.from_host(A, v)
+    B, U, V = dev(p.B), dev(p.U), dev(p.V)
+    rows = np.unique(np.concatenate([[0, n - 1], synth.randint(64, n, 12)]))
+    srp, sci, idx = sub_rows(A, rows)
+    C64, CM = oracle.spmm(srp, sci, v[idx], p.B)
+    S64, SM = oracle.sddmm(srp, sci, v[idx], p.U[rows], p.V)
+    r = torch.from_numpy(rows).cuda()
+    lo = torch.from_numpy(A.row_ptr[rows].astype(np.int64)).cuda()
+    cnt = torch.from_numpy((A.row_ptr[rows + 1] - A.row_ptr[rows]).astype(np.int64)).cuda()
+    ent = torch.cat([torch.arange(int(a), int(a) + int(c), device="cuda") for a, c in zip(lo, cnt)])
+    for plan in (selector.select(dA, K, spk.OP_SPMM), spk.Plan(4, 16, 64), spk.Plan(4, 16, 128, 2)):
+        C = spk.spmm(dA, B, plan=plan)
+        assert_within(C[r].cpu().numpy(), C64, CM, TOL_F32, f"full-size spmm {plan.name()}")
+    for plan in (selector.select(dA, K, spk.OP_SDDMM), spk.Plan(4, 16, 64), spk.Plan(4, 16, 128, 2)):
+        S = spk.sddmm(dA, U, V, plan=plan)
+        assert_within(S[ent].cpu().numpy(), S64, SM, TOL_F32, f"full-size sddmm {plan.name()}")
+    del dA, B, U, V
+    torch.cuda.empty_cache()
