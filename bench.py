@@ -131,6 +131,8 @@ def _part_of(kernel):
 def profile_summary(args):
     """Markdown summary of one rocprofv3 trace pass and two counter passes
     (FETCH_SIZE, WRITE_SIZE) of the same bench command, written to --out.
+    DIR also holds cmd.txt (the commands), trace.log (the run's output) and
+    digest.txt (kernel_source_digest() of the profiled tree).
     Counter readings (KiB per dispatch) are scaled by what the same counters
     read for the run's device copy of --calib-copy GiB (that many GiB read and
     written), then summed per part of a step and divided by the steps run."""
@@ -177,7 +179,10 @@ def profile_summary(args):
             if part:
                 part_bytes[part] = part_bytes.get(part, 0.0) + scaled * nf / runs
         rows.append((short, part or "-", nf, fkib, wkib, scaled))
-    digest = kernel_source_digest()
+    # the digest of the sources the profiled run was built from, recorded
+    # beside the counters when they were taken
+    with open(os.path.join(d, "digest.txt")) as fh:
+        digest = fh.read().strip()
     out = [f"# rocprofv3: {line['config']['workload']}", "",
            "Commands (repository root, one MI355X; each counter in a pass of its own):", ""]
     out += ["    " + c for c in cmds]
@@ -530,8 +535,8 @@ def main():
     ap.add_argument("--sweep", default=None, help="write the grid sweep to this JSONL file")
     ap.add_argument("--sweep-modes", default="plain,tuned")
     ap.add_argument("--profile-summary", default=None, metavar="DIR",
-                    help="summarise the rocprofv3 passes under DIR (cmd.txt, trace.log, trace/, fetch/, "
-                         "write/) into --out; no GPU needed")
+                    help="summarise the rocprofv3 passes under DIR (cmd.txt, digest.txt, trace.log, trace/, "
+                         "fetch/, write/) into --out; no GPU needed")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.profile_summary:
@@ -553,4 +558,7 @@ def main():
 
 
 if __name__ == "__main__":
+    if sys.argv[1:] == ["--source-digest"]:  # recorded beside profiles when they are taken
+        print(kernel_source_digest())
+        sys.exit(0)
     main()
