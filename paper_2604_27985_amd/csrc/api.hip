@@ -44,6 +44,7 @@ struct Resolved {
     int32_t variant, lanes, vec;
     int64_t chunk;
     int32_t rows_per_group = 4;
+    int32_t quad_split = 0;
 };
 
 int32_t default_spmm_lanes(int64_t K) {
@@ -73,11 +74,16 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
         // one K-tile of 16-byte (F32) or 8-byte (BF16) lanes; the slab fits kTileLds
         const size_t es = elem_size(b_dtype);
         const int64_t sv = 16 / static_cast<int64_t>(es);
-        if (b_dtype == SPK_F64 || (plan && (plan->flags & ~3)) || (plan && plan->chunk < 0)) return SPK_ERR_PLAN;
+        if (b_dtype == SPK_F64 || (plan && (plan->flags & ~6)) || (plan && plan->chunk < 0)) return SPK_ERR_PLAN;
         r.rows_per_group = plan && (plan->flags & 2) ? 8 : 4;
-        if (K > 4 * r.lanes || K % sv != 0 || ldb % sv != 0 || !aligned(B, 16) || ldc % 4 != 0 || !aligned(C, 16))
-            return SPK_ERR_PLAN;
         const int64_t row_bytes = K * static_cast<int64_t>(es);
+        // one entry per quad where a row of B is 128 or 256 bytes (16-lane
+        // groups whatever the plan's lanes), else the plain split
+        r.quad_split = plan && (plan->flags & 4) && (row_bytes == 128 || row_bytes == 256) ? 1 : 0;
+        if (r.quad_split) r.lanes = 16;
+        if ((!r.quad_split && K > 4 * r.lanes) || K % sv != 0 || ldb % sv != 0 || !aligned(B, 16) || ldc % 4 != 0 ||
+            !aligned(C, 16))
+            return SPK_ERR_PLAN;
         const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * row_bytes);  // two buffers
         int64_t w = 16;  // default: the largest power of two whose slab fits 16 KiB
         while (w * 2 * row_bytes <= 16384) w *= 2;
@@ -117,14 +123,22 @@ int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U
         // groups of 16, 32 or 64 lanes, one 4-wide slice of U and V per lane,
         // slabs of V rows in 16-byte pieces, two slab buffers in kTileLds
         const int64_t sv = 16 / static_cast<int64_t>(es);
-        if (dt == SPK_F64 || (plan->flags & ~2) || plan->chunk < 0) return SPK_ERR_PLAN;
+        if (dt == SPK_F64 || (plan->flags & ~6) || plan->chunk < 0) return SPK_ERR_PLAN;
         r.lanes = plan->lanes;
         r.rows_per_group = (plan->flags & 2) ? 8 : 4;
-        if (r.lanes != 16 && r.lanes != 32 && r.lanes != 64) return SPK_ERR_PLAN;
-        if (K > 4 * r.lanes || K % sv != 0 || ldv % sv != 0 || !aligned(V, 16) || ldu % 4 != 0 ||
-            !aligned(U, 4 * es))
-            return SPK_ERR_PLAN;
         const int64_t row_bytes = K * static_cast<int64_t>(es);
+        // one entry per quad where rows are 128 or 256 bytes and U is read in
+        // 16-byte pieces (16-lane groups whatever the plan's lanes), else the
+        // plain split
+        r.quad_split = (plan->flags & 4) && (row_bytes == 128 || row_bytes == 256) && ldu % sv == 0 &&
+                               aligned(U, 16) && K % sv == 0 && ldv % sv == 0 && aligned(V, 16)
+                           ? 1
+                           : 0;
+        if (r.quad_split) r.lanes = 16;
+        if (r.lanes != 16 && r.lanes != 32 && r.lanes != 64) return SPK_ERR_PLAN;
+        if ((!r.quad_split && K > 4 * r.lanes) || K % sv != 0 || ldv % sv != 0 || !aligned(V, 16) ||
+            ldu % 4 != 0 || !aligned(U, 4 * es))
+            return SPK_ERR_PLAN;
         const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * row_bytes);
         int64_t w = 16;  // default: the largest power of two whose slab fits 16 KiB
         while (w * 2 * row_bytes <= 16384) w *= 2;
@@ -292,7 +306,7 @@ int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, 
     const size_t need = spmm_ws(A->m, A->n, A->nnz, K, b_dtype, r, false);
     if ((st = check_ws(need, ws, ws_bytes))) return st;
     SpmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, nullptr, B, ldb, b_dtype, C, ldc,
-               r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group};
+               r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group, r.quad_split};
     return hip_status(spmm_launch(a, s));
 }
 
@@ -309,7 +323,7 @@ int32_t sddmm_csr(const spk_csr *A, const void *U, int64_t ldu, const void *V, i
     if ((st = resolve_sddmm(plan, K, uv_dtype, U, ldu, V, ldv, r))) return st;
     if ((st = check_ws(sddmm_ws(A->m, A->n, r), ws, ws_bytes))) return st;
     SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, U, ldu, V, ldv, uv_dtype, S,
-                r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group};
+                r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group, r.quad_split};
     return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
 }
 
@@ -345,7 +359,7 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
             const size_t need = spmm_ws(A->n, A->m, A->nnz, K, dtype, r, true);
             if ((st = check_ws(need, ws, ws_bytes))) return st;
             SpmmArgs a{A->n, A->m, A->nnz, K, at_row_ptr, at_col_idx, A->vals, perm, G, ldg, dtype, dB, lddb,
-                       r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group};
+                       r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group, r.quad_split};
             if ((st = hip_status(spmm_launch(a, s)))) return st;
         }
     }
@@ -374,7 +388,7 @@ static int current_device() {
     return d;
 }
 
-int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 20 : op == SPK_OP_SDDMM ? 19 : 0; }
+int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 22 : op == SPK_OP_SDDMM ? 21 : 0; }
 
 int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid) {
     if (!out) return SPK_ERR_NULL;
@@ -383,14 +397,17 @@ int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32
     if (op == SPK_OP_SPMM && index == 15) {
         *out = spk_plan{SPK_VAR_BSR4, 64, 0, 0};
     } else if ((op == SPK_OP_SPMM && index >= 16) || (op == SPK_OP_SDDMM && index >= 15)) {
-        // LDS slabs of 16 or 32 KiB of F32 rows (half that for BF16), 4 or 8 rows per lane group
+        // LDS slabs of 16 or 32 KiB of F32 rows (half that for BF16), 4 or 8
+        // rows per lane group; the last two split the work one entry per quad
+        // (16 KiB slabs)
         const int t = index - (op == SPK_OP_SPMM ? 16 : 15);
-        const int64_t bytes = t % 2 == 0 ? 16384 : 32768;
+        const int64_t bytes = t < 4 && t % 2 == 1 ? 32768 : 16384;
         const int64_t k = K > 0 ? K : 1;
         const int64_t w = bytes / (4 * k);
         int32_t lanes = default_spmm_lanes(K);
         if (op == SPK_OP_SDDMM && lanes < 16) lanes = 16;  // SDDMM TILE reduces over 16-lane rows
-        *out = spk_plan{SPK_VAR_TILE, lanes, static_cast<int32_t>(w > 0 ? w : 1), t >= 2 ? 2 : 0};
+        const int32_t flags = t < 4 ? (t >= 2 ? 2 : 0) : (t == 5 ? 6 : 4);
+        *out = spk_plan{SPK_VAR_TILE, lanes, static_cast<int32_t>(w > 0 ? w : 1), flags};
     } else {
         static const int32_t variants[3] = {SPK_VAR_ROWS, SPK_VAR_MERGE, SPK_VAR_SLAB};
         const int32_t v = variants[index / 5];

@@ -26,6 +26,7 @@ struct SpmmArgs {
     int64_t chunk;
     void *ws;
     int32_t rows_per_group = 4;  // TILE: rows each lane group owns (4 or 8)
+    int32_t quad_split = 0;      // TILE: one entry per 4-lane quad, 16-lane groups
 };
 
 struct SddmmArgs {
@@ -42,6 +43,7 @@ struct SddmmArgs {
     int64_t chunk;
     void *ws;
     int32_t rows_per_group = 4;  // TILE: rows each lane group owns (4 or 8)
+    int32_t quad_split = 0;      // TILE: one entry per 4-lane quad, 16-lane groups
 };
 
 // Column slabs of the SLAB variants: nslabs slabs of `width` columns; the

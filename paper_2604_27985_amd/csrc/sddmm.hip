@@ -424,6 +424,194 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
     }
 }
 
+// TILE with one entry per 4-lane quad.  The same slabs and chunks, another
+// split of the work inside a 16-lane group: its four quads take four entries
+// at once and each lane covers a quarter of the row (NP pieces of 16 bytes),
+// so a dot product is summed with two quad exchanges instead of the
+// transposing reduction over the group, at the price of four copies of the
+// rows of U per group.  A chunk is fetched so that lane 4q + j holds entry
+// 4j + q: in step s quad q works on entry 4s + q, whose row offset sits on
+// lane 4q + s of the same quad (a quad_perm broadcast, DPP 0x55 * s), and the
+// total of entry 4j + q ends on the lane that fetched it, which stores it
+// with its own weight.  In read i of a step quad q reads the 64-byte group
+// (i + q) mod NP of its row, piece j of it, so the four quads of a group read
+// different bank groups although their rows are unrelated.
+// Partial dot product of two 16-byte pieces of a row: four FMAs on F32, four
+// two-element dot products (v_dot2c_f32_bf16: exact products, F32 sums) on
+// BF16, so the BF16 rows need no unpacking.
+template <typename TUV>
+__device__ __forceinline__ float dot_piece(const u32x4 &a, const u32x4 &b, float acc);
+template <>
+__device__ __forceinline__ float dot_piece<float>(const u32x4 &a, const u32x4 &b, float acc) {
+    acc = fma(__uint_as_float(a.x), __uint_as_float(b.x), acc);
+    acc = fma(__uint_as_float(a.y), __uint_as_float(b.y), acc);
+    acc = fma(__uint_as_float(a.z), __uint_as_float(b.z), acc);
+    return fma(__uint_as_float(a.w), __uint_as_float(b.w), acc);
+}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float acc) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), acc,
+                                           false);
+}
+template <>
+__device__ __forceinline__ float dot_piece<bf16>(const u32x4 &a, const u32x4 &b, float acc) {
+    acc = dot2_bf16(a.x, b.x, acc);
+    acc = dot2_bf16(a.y, b.y, acc);
+    acc = dot2_bf16(a.z, b.z, acc);
+    return dot2_bf16(a.w, b.w, acc);
+}
+
+template <typename TUV, int NP, int S>
+__device__ __forceinline__ float sddmm_qstep(const unsigned char *__restrict__ smem, const uint32_t (&pb)[NP],
+                                             int offb, const u32x4 (&u)[NP]) {
+    u32x4 vv[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) vv[i] = *reinterpret_cast<const u32x4 *>(smem + quad_bcast_add<S>(offb, pb[i]));
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc = dot_piece<TUV>(u[i], vv[i], acc);
+    acc += dpp<0xB1>(acc);
+    return acc + dpp<0x4E>(acc);
+}
+
+template <typename TUV, typename TV, int NP>
+__device__ __forceinline__ int sddmm_tileq_pass(const unsigned char *__restrict__ smem, int32_t c0, int32_t c1,
+                                                int slot, int j, int gbase16, bool has_vals,
+                                                const int32_t *__restrict__ ci, const TV *__restrict__ vsrc,
+                                                int32_t last, int32_t &cur, int32_t end, int &c, TV &v,
+                                                const uint32_t (&pb)[NP], const u32x4 (&u)[NP],
+                                                float *__restrict__ S) {
+    constexpr int kRowShift = NP == 2 ? 7 : 8;  // log2 of a row's bytes
+    const bool in = cur + slot < end && c < c1;
+    const int cnt = count16(__builtin_amdgcn_ballot_w64(in), gbase16);
+    const int offb = in ? (c - c0) << kRowShift : 0;
+    const float w = pin(has_vals ? static_cast<float>(v) : 1.f);
+    const int32_t p = cur + slot;
+    cur += cnt;
+    tile_fetch(cur + slot, last, ci, vsrc, c, v);
+    float res = 0.f;
+    if (cnt > 0) {
+        const float t = sddmm_qstep<TUV, NP, 0>(smem, pb, offb, u);
+        res = j == 0 ? t : res;
+    }
+    if (cnt > 4) {
+        const float t = sddmm_qstep<TUV, NP, 1>(smem, pb, offb, u);
+        res = j == 1 ? t : res;
+    }
+    if (cnt > 8) {
+        const float t = sddmm_qstep<TUV, NP, 2>(smem, pb, offb, u);
+        res = j == 2 ? t : res;
+    }
+    if (cnt > 12) {
+        const float t = sddmm_qstep<TUV, NP, 3>(smem, pb, offb, u);
+        res = j == 3 ? t : res;
+    }
+    if (in) S[static_cast<uint32_t>(p)] = w * res;
+    return cnt;
+}
+
+template <typename TUV, typename TV, int NP, int RPG, int NPT>
+__global__ __launch_bounds__(kBlock) void sddmm_tileq_kernel(int64_t m, int64_t n, int64_t nnz,
+                                                             const int32_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ ci,
+                                                             const TV *__restrict__ vals,
+                                                             const TUV *__restrict__ U, int64_t ldu,
+                                                             const TUV *__restrict__ V, int64_t ldv,
+                                                             float *__restrict__ S, int W) {
+    constexpr int SV = kTileSV<TUV>;
+    constexpr int per_row = 4 * NP;  // 16-byte pieces in a row of U or V
+    constexpr int buf_bytes = NPT * kTilePiece;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int GPB = kBlock / 16;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & 15;
+    const int q = lig >> 2, j = lig & 3;
+    const int slot = 4 * j + q;
+    const int gbase = lane & ~15;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = (blk * GPB + threadIdx.x / 16) * RPG;
+    const int32_t last = static_cast<int32_t>(nnz - 1);  // row_ptr is int32: positions fit
+    const bool has_vals = vals != nullptr;
+    const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
+    uint32_t pb[NP];  // byte offset in a row of piece j of group (i + q) mod NP
+#pragma unroll
+    for (int i = 0; i < NP; ++i) pb[i] = static_cast<uint32_t>((((i + q) % NP) * 4 + j) * 16);
+    int32_t cur[RPG], end[RPG];
+    u32x4 u[RPG][NP];  // this lane's pieces of the rows of U, as stored
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+        const int64_t row = row0 + r;
+        cur[r] = row < m ? rp[row] : 0;
+        end[r] = row < m ? rp[row + 1] : 0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            u[r][i] = row < m ? *reinterpret_cast<const u32x4 *>(U + row * ldu + (pb[i] / 16) * SV) : u32x4{0, 0, 0, 0};
+    }
+    u32x4 stg[NPT];
+    TileCopy<TUV, NPT> copy;
+    copy.layout(static_cast<int>(n < W ? n : W), per_row, ldv);
+    copy.load(V, ldv, 0, stg);
+    tile_store<TUV, NPT>(reinterpret_cast<TUV *>(smem), stg);
+    int pc[RPG];
+    TV pv[RPG];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) tile_fetch(cur[r] + slot, last, ci, vsrc, pc[r], pv[r]);
+    int sl = 0;
+    for (int32_t c0 = 0; c0 < n; c0 += W, ++sl) {
+        const int32_t c1 = static_cast<int32_t>(n - c0 < W ? n : c0 + W);
+        __syncthreads();  // slab sl is in LDS; every group is done with the other buffer
+        const int32_t nx = c1 < n ? c1 : c0;  // the last slab reads itself again: same loads every slab
+        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row, ldv);
+        copy.load(V, ldv, nx, stg);
+        const unsigned char *buf = smem + (sl & 1) * buf_bytes;
+#pragma unroll
+        for (int r = 0; r < RPG; ++r) {
+            if (sddmm_tileq_pass<TUV, TV, NP>(buf, c0, c1, slot, j, gbase, has_vals, ci, vsrc, last, cur[r],
+                                                   end[r], pc[r], pv[r], pb, u[r], S) == 16) {
+                while (sddmm_tileq_pass<TUV, TV, NP>(buf, c0, c1, slot, j, gbase, has_vals, ci, vsrc, last,
+                                                          cur[r], end[r], pc[r], pv[r], pb, u[r], S) == 16) {
+                }
+            }
+        }
+        tile_store<TUV, NPT>(reinterpret_cast<TUV *>(smem + ((sl + 1) & 1) * buf_bytes), stg);
+    }
+}
+
+template <typename TUV, typename TV, int NP, int RPG, int NPT>
+static hipError_t launch_tileq_npt(const SddmmArgs &a, hipStream_t s) {
+    constexpr int GPB = kBlock / 16;
+    const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
+    const size_t lds = 2 * static_cast<size_t>(NPT) * kTilePiece;  // two slab buffers
+    hipLaunchKernelGGL((sddmm_tileq_kernel<TUV, TV, NP, RPG, NPT>), dim3(static_cast<unsigned>(nb)), dim3(kBlock),
+                       lds, s, a.m, a.n, a.nnz, a.rp, a.ci, static_cast<const TV *>(a.vals),
+                       static_cast<const TUV *>(a.U), a.ldu, static_cast<const TUV *>(a.V), a.ldv,
+                       static_cast<float *>(a.S), static_cast<int>(a.chunk));
+    return hipGetLastError();
+}
+
+template <typename TUV, typename TV, int NP, int RPG>
+static hipError_t launch_tileq_rpg(const SddmmArgs &a, hipStream_t s) {
+    constexpr int GPB = kBlock / 16;
+    const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
+    const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TUV));
+    if (nb > 0x7FFFFFFF || a.K * static_cast<int64_t>(sizeof(TUV)) != 64 * NP || a.chunk < 1 ||
+        2 * slab_bytes > static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
+        return hipErrorInvalidValue;
+    if (slab_bytes <= 2 * kTilePiece) return launch_tileq_npt<TUV, TV, NP, RPG, 2>(a, s);
+    if (slab_bytes <= 4 * kTilePiece) return launch_tileq_npt<TUV, TV, NP, RPG, 4>(a, s);
+    return launch_tileq_npt<TUV, TV, NP, RPG, 8>(a, s);
+}
+
+template <typename TUV, typename TV>
+static hipError_t launch_tileq(const SddmmArgs &a, hipStream_t s) {
+    const bool r8 = a.rows_per_group == 8;
+    switch (a.K * static_cast<int64_t>(sizeof(TUV))) {
+    case 128: return r8 ? launch_tileq_rpg<TUV, TV, 2, 8>(a, s) : launch_tileq_rpg<TUV, TV, 2, 4>(a, s);
+    case 256: return r8 ? launch_tileq_rpg<TUV, TV, 4, 8>(a, s) : launch_tileq_rpg<TUV, TV, 4, 4>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename TUV, typename TV, int LANES, int RPG, int NPT>
 static hipError_t launch_tile_npt(const SddmmArgs &a, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
@@ -528,6 +716,10 @@ static hipError_t dispatch_off(const SddmmArgs &a, hipStream_t s) {
 
 hipError_t sddmm_launch(const SddmmArgs &a, hipStream_t s) {
     if (a.variant == SPK_VAR_TILE) {
+        if (a.quad_split) {
+            if (a.uv_dtype == SPK_F32) return launch_tileq<float, float>(a, s);
+            if (a.uv_dtype == SPK_BF16) return launch_tileq<bf16, float>(a, s);
+        }
         if (a.uv_dtype == SPK_F32) return launch_tile<float, float>(a, s);
         if (a.uv_dtype == SPK_BF16) return launch_tile<bf16, float>(a, s);
         return hipErrorInvalidValue;

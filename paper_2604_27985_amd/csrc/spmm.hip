@@ -349,6 +349,184 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
     }
 }
 
+// TILE with one entry per 4-lane quad (16-lane groups, rows of B of 128 or
+// 256 bytes).  The same slabs and chunks as above; inside a group the four
+// quads take four entries at once and each lane covers a quarter of the row
+// (NP pieces of 16 bytes), so an entry costs its FMAs, one address and one
+// weight broadcast per quad instead of per lane.  A chunk is fetched so that
+// lane 4q + j holds entry 4j + q: in step s quad q adds entry 4s + q, whose
+// row offset and weight sit on lane 4q + s (quad_perm broadcasts).  In read i
+// of a step quad q reads the 64-byte group (i + q) mod NP of its row, so the
+// four quads of a group hit different bank groups.  Each quad thus
+// accumulates every group of the row in a rotated order: acc[i] holds group
+// (i + q) mod NP.  At the end, group g of
+// the row is the sum over quads q' of their acc[(g - q') mod NP]; lane
+// (q, j) gathers group q from quad q - k with row_ror:4k (DPP 0x120 + 4k,
+// lane l reads lane l - 4k of its row), whose register is acc[k mod NP].
+template <typename TB, int NP, int S>
+__device__ __forceinline__ void spmm_qstep(const unsigned char *__restrict__ smem, const uint32_t (&pb)[NP],
+                                           int offb, float w, float (&acc)[NP][kTileSV<TB>]) {
+    constexpr int SV = kTileSV<TB>;
+    const float x = quad_bcast<S>(w);
+    float bv[NP][SV];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+        vec_load<TB, SV>::run(reinterpret_cast<const TB *>(smem + quad_bcast_add<S>(offb, pb[i])), bv[i]);
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int e = 0; e < SV; ++e) acc[i][e] = fma(x, bv[i][e], acc[i][e]);
+}
+
+template <typename TB, typename TV, int NP>
+__device__ __forceinline__ int spmm_tileq_pass(const unsigned char *__restrict__ smem, int32_t c0, int32_t c1,
+                                               int slot, int gbase16, bool has_vals, const int32_t *__restrict__ ci,
+                                               const TV *__restrict__ vsrc, int32_t last, int32_t &cur, int32_t end,
+                                               int &c, TV &v, const uint32_t (&pb)[NP],
+                                               float (&acc)[NP][kTileSV<TB>]) {
+    constexpr int kRowShift = NP == 2 ? 7 : 8;  // log2 of a row's bytes
+    const bool in = cur + slot < end && c < c1;
+    const int cnt = count16(__builtin_amdgcn_ballot_w64(in), gbase16);
+    const int offb = in ? (c - c0) << kRowShift : 0;
+    // entries past the in-slab prefix are added with weight zero (valid row 0)
+    const float w = in ? (has_vals ? static_cast<float>(v) : 1.f) : 0.f;
+    cur += cnt;
+    tile_fetch(cur + slot, last, ci, vsrc, c, v);
+    if (cnt > 0) spmm_qstep<TB, NP, 0>(smem, pb, offb, w, acc);
+    if (cnt > 4) spmm_qstep<TB, NP, 1>(smem, pb, offb, w, acc);
+    if (cnt > 8) spmm_qstep<TB, NP, 2>(smem, pb, offb, w, acc);
+    if (cnt > 12) spmm_qstep<TB, NP, 3>(smem, pb, offb, w, acc);
+    return cnt;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+template <typename TB, typename TV, int NP, int RPG, int NPT>
+__global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n, int64_t nnz,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const TV *__restrict__ vals, const TB *__restrict__ B,
+                                                            int64_t ldb, float *__restrict__ C, int64_t ldc, int W) {
+    static_assert(sizeof(TV) == 4, "values are F32 on this path");
+    constexpr int SV = kTileSV<TB>;
+    constexpr int per_row = 4 * NP;
+    constexpr int buf_bytes = NPT * kTilePiece;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int GPB = kBlock / 16;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & 15;
+    const int q = lig >> 2, j = lig & 3;
+    const int slot = 4 * j + q;
+    const int gbase = lane & ~15;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row0 = (blk * GPB + threadIdx.x / 16) * RPG;
+    const int32_t last = static_cast<int32_t>(nnz - 1);  // row_ptr is int32: positions fit
+    const bool has_vals = vals != nullptr;
+    const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
+    uint32_t pb[NP];  // byte offset in a row of piece j of group (i + q) mod NP
+#pragma unroll
+    for (int i = 0; i < NP; ++i) pb[i] = static_cast<uint32_t>((((i + q) % NP) * 4 + j) * 16);
+    int32_t cur[RPG], end[RPG];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+        const int64_t row = row0 + r;
+        cur[r] = row < m ? rp[row] : 0;
+        end[r] = row < m ? rp[row + 1] : 0;
+    }
+    u32x4 stg[NPT];
+    TileCopy<TB, NPT> copy;
+    copy.layout(static_cast<int>(n < W ? n : W), per_row, ldb);
+    copy.load(B, ldb, 0, stg);
+    tile_store<TB, NPT>(reinterpret_cast<TB *>(smem), stg);
+    int pc[RPG];
+    TV pv[RPG];
+    float acc[RPG][NP][SV];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) zero<float, SV>(acc[r][i]);
+        tile_fetch(cur[r] + slot, last, ci, vsrc, pc[r], pv[r]);
+    }
+    int sl = 0;
+    for (int32_t c0 = 0; c0 < n; c0 += W, ++sl) {
+        const int32_t c1 = static_cast<int32_t>(n - c0 < W ? n : c0 + W);
+        __syncthreads();  // slab sl is in LDS; every group is done with the other buffer
+        const int32_t nx = c1 < n ? c1 : c0;  // the last slab reads itself again: same loads every slab
+        if (n - nx < W) copy.layout(static_cast<int>(n - nx), per_row, ldb);
+        copy.load(B, ldb, nx, stg);
+        const unsigned char *buf = smem + (sl & 1) * buf_bytes;
+#pragma unroll
+        for (int r = 0; r < RPG; ++r) {
+            if (spmm_tileq_pass<TB, TV, NP>(buf, c0, c1, slot, gbase, has_vals, ci, vsrc, last, cur[r], end[r],
+                                                 pc[r], pv[r], pb, acc[r]) == 16) {
+                while (spmm_tileq_pass<TB, TV, NP>(buf, c0, c1, slot, gbase, has_vals, ci, vsrc, last, cur[r],
+                                                        end[r], pc[r], pv[r], pb, acc[r]) == 16) {
+                }
+            }
+        }
+        tile_store<TB, NPT>(reinterpret_cast<TB *>(smem + ((sl + 1) & 1) * buf_bytes), stg);
+    }
+    // lane (q, j) sums group q of each row over the four quads and, for q < NP,
+    // stores piece j of it: elements (4q + j) * SV .. + SV
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+        float out[SV];
+#pragma unroll
+        for (int e = 0; e < SV; ++e) {
+            float t = acc[r][0][e];
+            t += dpp_move<0x124>(acc[r][1 % NP][e]);
+            t += dpp_move<0x128>(acc[r][2 % NP][e]);
+            t += dpp_move<0x12C>(acc[r][3 % NP][e]);
+            out[e] = t;
+        }
+        const int64_t row = row0 + r;
+        if (row < m && q < NP) vec_store<float, SV>::run(C + row * ldc + (4 * q + j) * SV, out);
+    }
+}
+
+template <typename TB, typename TV, int NP, int RPG, int NPT>
+static hipError_t launch_tileq_npt(const SpmmArgs &a, const TV *vals, hipStream_t s) {
+    constexpr int GPB = kBlock / 16;
+    const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
+    const size_t lds = 2 * static_cast<size_t>(NPT) * kTilePiece;  // two slab buffers
+    hipLaunchKernelGGL((spmm_tileq_kernel<TB, TV, NP, RPG, NPT>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), lds,
+                       s, a.m, a.n, a.nnz, a.rp, a.ci, vals, static_cast<const TB *>(a.B), a.ldb,
+                       static_cast<float *>(a.C), a.ldc, static_cast<int>(a.chunk));
+    return hipGetLastError();
+}
+
+template <typename TB, typename TV, int NP, int RPG>
+static hipError_t launch_tileq_rpg(const SpmmArgs &a, const TV *vals, hipStream_t s) {
+    constexpr int GPB = kBlock / 16;
+    const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
+    const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TB));
+    if (nb > 0x7FFFFFFF || a.K * static_cast<int64_t>(sizeof(TB)) != 64 * NP || a.chunk < 1 ||
+        2 * slab_bytes > static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
+        return hipErrorInvalidValue;
+    if (slab_bytes <= 2 * kTilePiece) return launch_tileq_npt<TB, TV, NP, RPG, 2>(a, vals, s);
+    if (slab_bytes <= 4 * kTilePiece) return launch_tileq_npt<TB, TV, NP, RPG, 4>(a, vals, s);
+    return launch_tileq_npt<TB, TV, NP, RPG, 8>(a, vals, s);
+}
+
+// Rows of 128 bytes (NP = 2) or 256 bytes (NP = 4); a BF16 row of 256 bytes
+// holds 128 elements, 32 per lane, and keeps 4 rows per group whatever the
+// plan asks (8 rows of 32 accumulators would not fit the registers).
+template <typename TB, typename TV>
+static hipError_t launch_tileq(const SpmmArgs &a, const TV *vals, hipStream_t s) {
+    const bool r8 = a.rows_per_group == 8;
+    switch (a.K * static_cast<int64_t>(sizeof(TB))) {
+    case 128: return r8 ? launch_tileq_rpg<TB, TV, 2, 8>(a, vals, s) : launch_tileq_rpg<TB, TV, 2, 4>(a, vals, s);
+    case 256:
+        if constexpr (sizeof(TB) == 4)
+            if (r8) return launch_tileq_rpg<TB, TV, 4, 8>(a, vals, s);
+        return launch_tileq_rpg<TB, TV, 4, 4>(a, vals, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // Interior slab boundaries: bnd[(s-1)*m + i] = first entry of row i whose
 // column is >= s*W, for s = 1 .. nslabs-1 (binary search in the sorted row).
 __global__ void slab_bounds_kernel(int64_t m, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -575,6 +753,7 @@ static hipError_t launch_tile(const SpmmArgs &a, hipStream_t s) {
             if (e != hipSuccess) return e;
             vals = dense;
         }
+        if (a.quad_split) return launch_tileq<TB, TV>(a, vals, s);
         return a.rows_per_group == 8 ? launch_tile_rpg<TB, TV, VW, LANES, 8>(a, vals, s)
                                      : launch_tile_rpg<TB, TV, VW, LANES, 4>(a, vals, s);
     }

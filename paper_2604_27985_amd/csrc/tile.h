@@ -62,6 +62,15 @@ __device__ __forceinline__ void tile_fetch(int32_t p, int32_t last, const int32_
     v = vsrc[q];
 }
 
+// A value held in a register from here on.  Used for a chunk entry's weight
+// before the next chunk's fetch overwrites the entry: left to itself, the
+// compiler may move the weight's use past the fetch, which then needs a
+// second register and a copy back that waits for the load to arrive.
+__device__ __forceinline__ float pin(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // row_newbcast:N (DPP control 0x150 + N): every lane of a 16-lane row reads
 // lane N of the same row.  A VALU move; no LDS crossbar traffic.  Every lane
 // has a valid source and all rows and banks are written, so the move needs no
@@ -90,6 +99,18 @@ __device__ __forceinline__ int count16(uint64_t ballot, int gbase) {
 template <int N>
 __device__ __forceinline__ uint32_t row_bcast_add(int offb, uint32_t base) {
     return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, offb, 0x150 + N, 0xF, 0xF, true)) + base;
+}
+
+// quad_perm [S,S,S,S] (DPP control 0x55 * S): every lane of a 4-lane quad
+// reads lane S of the quad.  As with row_bcast_add, the broadcast of a row
+// offset is folded into the add of this lane's own offset.
+template <int S>
+__device__ __forceinline__ uint32_t quad_bcast_add(int offb, uint32_t base) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, offb, S * 0x55, 0xF, 0xF, true)) + base;
+}
+template <int S>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), S * 0x55, 0xF, 0xF, false));
 }
 
 }  // namespace spk

@@ -83,7 +83,7 @@ def test_tile_plan_limits(lib):
     assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(8, 16)) == -6            # 8 lanes x 4 < 64
     assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(16, 129)) == -6          # 2 x 129 x 256 B > 64 KiB
     assert spmm(csr(), K=64, ldb=1 << 25, ldc=64, plan=tile(16, 32)) == -6      # 32 x 2^25 x 4 B = 4 GiB
-    assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(16, 16, 4)) == -6        # unknown flag
+    assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(16, 16, 16)) == -6       # unknown flag
     f = lib.sddmm_csr
     A = csr()
     assert f(ctypes.byref(A), FAKE, 64, FAKE, 1 << 25, 0, 64, FAKE, ctypes.byref(tile(16, 32)), None, 0,

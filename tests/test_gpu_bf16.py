@@ -45,7 +45,10 @@ def powerlaw_bf16(n, mean, K, seed):
 
 
 @pytest.mark.parametrize("K,plans", [(256, [None, (1, 64, 0), (0, 32, 0), (3, 32, 0), (4, 64, 0), (4, 64, 33)]),
-                                     (64, [None, (1, 8, 0), (0, 16, 0), (4, 16, 0), (4, 16, 5, 2)]), (36, [None, (1, 8, 0)])])
+                                     (64, [None, (1, 8, 0), (0, 16, 0), (4, 16, 0), (4, 16, 5, 2), (4, 16, 0, 4),
+                                           (4, 16, 7, 6)]),
+                                     (128, [(4, 32, 0, 4), (4, 32, 9, 6)]),  # one entry per quad, 256-byte rows
+                                     (36, [None, (1, 8, 0)])])
 def test_spmm_bf16(spk, K, plans):
     A, v, B32, _ = powerlaw_bf16(40000, 32, K, 1)
     Bt, Br = bf16_dev(B32)
@@ -61,7 +64,7 @@ def test_spmm_bf16(spk, K, plans):
         assert rel <= 2.0 ** -8, rel
 
 
-@pytest.mark.parametrize("K", [256, 64])
+@pytest.mark.parametrize("K", [256, 64, 128])
 def test_sddmm_bf16(spk, K):
     A, v, V32, U32 = powerlaw_bf16(40000, 32, K, 2)
     Ut, Ur = bf16_dev(U32)
@@ -70,8 +73,10 @@ def test_sddmm_bf16(spk, K):
     S_s, M_s = oracle.sddmm(A.row_ptr, A.col_idx, v, U32, V32)
     dA = spk.CSR.from_host(A, v)
     tl = K // 4  # TILE plans: default and odd slab widths, 4 or 8 rows per group
-    for plan in (None, spk.Plan(1, 16, 256), spk.Plan(0, 32), spk.Plan(3, 16, 0), spk.Plan(4, tl, 0),
-                 spk.Plan(4, tl, 9, 2)):
+    # flags bit 2: one entry per quad (two-element BF16 dot products) at K = 64 and 128
+    quad = [spk.Plan(4, 16, 0, 4), spk.Plan(4, 16, 11, 6)] if K in (64, 128) else []
+    for plan in [None, spk.Plan(1, 16, 256), spk.Plan(0, 32), spk.Plan(3, 16, 0), spk.Plan(4, tl, 0),
+                 spk.Plan(4, tl, 9, 2)] + quad:
         S = spk.sddmm(dA, Ut, Vt, plan=plan).cpu().numpy()
         assert_within(S, S_r, M_r, TOL_F32, f"bf16 sddmm rounded {plan}")
         assert_within(S, S_s, M_s, TOL_BF16_SRC, f"bf16 sddmm vs fp32 sources {plan}")

@@ -91,11 +91,40 @@ def test_spmm_tile(spk, K, lanes, kind, m, n, d):
             assert_within(C, C64, M, TOL_F32, f"tile K={K} lanes={lanes} chunk={chunk} flags={flags}")
 
 
+@pytest.mark.parametrize("K", [64, 32])
+@pytest.mark.parametrize("kind,m,n,d", [("uniform", 3001, 2500, 0.05), ("powerlaw", 6000, 6000, 12),
+                                        ("block4", 1024, 4096, 0.02), ("uniform", 7, 5, 0.5)])
+def test_spmm_tile_quad_split(spk, K, kind, m, n, d):
+    """One entry per 4-lane quad (flags bit 2), 4 or 8 rows per group: default, odd and one-row slabs."""
+    A, v, B, _ = problem(m, n, d, K, 13, kind)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    for chunk in (0, 7, 1, 31):
+        for flags in (4, 6):
+            plan = spk.Plan(4, 16, chunk, flags)
+            assert_within(run_spmm(spk, A, v, B, plan), C64, M, TOL_F32, f"quad spmm K={K} {plan.name()}")
+    P64, PM = oracle.spmm(A.row_ptr, A.col_idx, None, B)
+    assert_within(run_spmm(spk, A, v, B, spk.Plan(4, 16, 5, 4), pattern=True), P64, PM, TOL_F32,
+                  "quad spmm pattern")
+
+
+@pytest.mark.parametrize("K,lanes", [(48, 16), (128, 32), (16, 4), (8, 4)])
+def test_tile_quad_flag_falls_back_to_plain_split(spk, K, lanes):
+    """Rows other than 128 or 256 bytes run the plain TILE split with the plan's lanes."""
+    A, v, B, U = problem(1500, 1200, 0.03, K, 14)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    for flags in (4, 6):
+        assert_within(run_spmm(spk, A, v, B, spk.Plan(4, lanes, 0, flags)), C64, M, TOL_F32, f"fallback K={K}")
+    S64, SM = oracle.sddmm(A.row_ptr, A.col_idx, v, U, B)
+    sl = max(lanes, 16)
+    assert_within(run_sddmm(spk, A, v, U, B, spk.Plan(4, sl, 0, 6)), S64, SM, TOL_F32, f"fallback sddmm K={K}")
+
+
 def test_spmm_tile_rejects_unfit_plans(spk):
     A, v, B, _ = problem(100, 100, 0.1, 64, 1)
     for plan in (spk.Plan(4, 8, 0),      # 8 lanes x 4 < K
                  spk.Plan(4, 16, 1 << 20),  # slab larger than the LDS budget
-                 spk.Plan(4, 16, 0, 4)):    # unknown flag
+                 spk.Plan(4, 16, 129, 4),   # one entry per quad: 2 x 129 x 256 B > 64 KiB
+                 spk.Plan(4, 16, 0, 8)):    # unknown flag
         with pytest.raises(spk.SpkError) as e:
             run_spmm(spk, A, v, B, plan)
         assert e.value.status == -6
@@ -245,12 +274,31 @@ def test_sddmm_tile(spk, K, lanes, kind, m, n, d):
                   "tile sddmm pattern")
 
 
+@pytest.mark.parametrize("K", [64, 32])
+@pytest.mark.parametrize("kind,m,n,d", [("uniform", 3001, 2500, 0.05), ("powerlaw", 6000, 6000, 12),
+                                        ("block4", 1024, 4096, 0.02), ("uniform", 7, 5, 0.5)])
+def test_sddmm_tile_quad_split(spk, K, kind, m, n, d):
+    """One entry per 4-lane quad (flags bit 2): rows of 128 and 256 bytes, odd and one-row slabs."""
+    A, v, V, U = problem(m, n, d, K, 12, kind)
+    S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    for chunk in (0, 7, 1, 31):
+        for flags in (4, 6):
+            plan = spk.Plan(4, 16, chunk, flags)
+            assert_within(run_sddmm(spk, A, v, U, V, plan), S64, M, TOL_F32, f"quad sddmm K={K} {plan.name()}")
+    # the quad split uses 16-lane groups whatever the plan's lanes
+    assert_within(run_sddmm(spk, A, v, U, V, spk.Plan(4, 64, 0, 4)), S64, M, TOL_F32, "quad sddmm lanes 64")
+    P64, PM = oracle.sddmm(A.row_ptr, A.col_idx, None, U, V)
+    assert_within(run_sddmm(spk, A, v, U, V, spk.Plan(4, 16, 5, 4), pattern=True), P64, PM, TOL_F32,
+                  "quad sddmm pattern")
+
+
 def test_sddmm_tile_rejects_unfit_plans(spk):
     A, v, V, U = problem(100, 100, 0.1, 64, 1)
     for plan in (spk.Plan(4, 8, 0),      # groups narrower than a 16-lane row
                  spk.Plan(4, 16, 1 << 20),  # slab beyond the LDS budget
                  spk.Plan(4, 16, 0, 1),     # scalar loads are not a TILE option
-                 spk.Plan(4, 32, 0, 4)):    # unknown flag
+                 spk.Plan(4, 16, 129, 4),   # one entry per quad: 2 x 129 x 256 B > 64 KiB
+                 spk.Plan(4, 16, 0, 8)):    # unknown flag
         with pytest.raises(spk.SpkError) as e:
             run_sddmm(spk, A, v, U, V, plan)
         assert e.value.status == -6
