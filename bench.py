@@ -262,6 +262,16 @@ def to_device(p, kind):
     return dA, B, U, V
 
 
+VERIFY = 3  # candidates of the learned ranking timed before the run
+
+
+def autotune_sweep(A, K, B, plans):
+    import paper_2604_27985_amd as spk
+    from paper_2604_27985_amd import autotune
+
+    return autotune.sweep(A, K, spk.OP_SPMM, B=B, plans=plans, reps=3, warmup=1)
+
+
 def choose_plans(mode, dA, K, B, U, V, kind):
     """(spmm plan, sddmm plan): NULL plans (plain), a timed search (tuned), or the selector."""
     import paper_2604_27985_amd as spk
@@ -271,15 +281,15 @@ def choose_plans(mode, dA, K, B, U, V, kind):
     if mode == "learned":
         from paper_2604_27985_amd import selector
 
-        p1 = selector.select(dA, K, spk.OP_SPMM)
+        # the network's three best plans, timed once on these operands
+        p1 = selector.select(dA, K, spk.OP_SPMM, verify=VERIFY, B=B)
         if kind == "gcn":
             # the backward's product runs on A^T: ask for a plan for that matrix
             trp, tci, _ = dA.transpose()
-            p2 = selector.select(spk.CSR(trp, tci, None, (dA.n, dA.m)), K, spk.OP_SPMM)
-            if p2.variant == spk.VAR_BSR4:  # no block form of A^T in the backward
-                p2 = spk.Plan(spk.VAR_MERGE, p2.lanes)
-            return p1, p2
-        return p1, selector.select(dA, K, spk.OP_SDDMM)
+            AT = spk.CSR(trp, tci, None, (dA.n, dA.m))
+            cands = [p for p in selector.rank(AT, K, spk.OP_SPMM, VERIFY + 1) if p.variant != spk.VAR_BSR4]
+            return p1, min(autotune_sweep(AT, K, U, cands[:VERIFY]), key=lambda r: r[1])[0]
+        return p1, selector.select(dA, K, spk.OP_SDDMM, verify=VERIFY, U=U, V=V)
     from paper_2604_27985_amd import autotune
 
     p1 = autotune.best_plan(dA, K, spk.OP_SPMM, B=B)[0]
@@ -461,7 +471,8 @@ def run_workload(args):
         for key in ("_b", "_f", "_t"):
             v.pop(key)
     cfg = {"workload": name, "n": n, "nnz": nnz, "K": K, "pattern": "uniform" if kind == "uniform" else "powerlaw",
-           "ops": "spmm+backward" if kind == "gcn" else "spmm+sddmm", "plan": args.plan,
+           "ops": "spmm+backward" if kind == "gcn" else "spmm+sddmm",
+           "plan": f"learned, best of the top {VERIFY} timed" if args.plan == "learned" else args.plan,
            "plans": {"spmm": p_spmm.name() if p_spmm else "plain",
                      ("backward" if kind == "gcn" else "sddmm"): p_sddmm.name() if p_sddmm else "plain"}}
     if kind == "uniform":

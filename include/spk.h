@@ -306,6 +306,15 @@ int32_t selector_load(int32_t op, const float *table, int64_t F, int64_t H, int6
 int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void *ws, size_t ws_bytes,
                     void *stream);
 
+/* The network's k best plans (1 <= k <= 32) for op on A with dense width K,
+ * in ascending predicted time, into out[0 .. *count) (host; *count <= k, the
+ * number of plans valid for K).  Same features, network and workspace as
+ * plan_select (whose plan is out[0]); a caller may time these few candidates
+ * and keep the fastest, which guards against a mispredicted first choice at
+ * the cost of a short timed search.  Synchronises `stream`. */
+int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t k, spk_plan *out, int32_t *count, void *ws,
+                  size_t ws_bytes, void *stream);
+
 /* Opt-in O(nnz) structural check of A (canonical CSR as described above).
  * ws    at least 16 bytes.  Synchronises `stream`.  Returns SPK_OK or
  *       SPK_ERR_STRUCTURE. */

@@ -79,6 +79,7 @@ SIGNATURES = {
                      _P], _I32),
     "selector_load": ([_I32, _P, _I64, _I64, _I64], _I32),
     "plan_select": ([_CSR_P, _I64, _I32, _PLAN_P, _P, _SZ, _P], _I32),
+    "plan_rank": ([_CSR_P, _I64, _I32, _I32, _PLAN_P, ctypes.POINTER(_I32), _P, _SZ, _P], _I32),
 }
 
 _lib = None

@@ -10,6 +10,7 @@ using namespace spk;
 namespace {
 
 constexpr int64_t kMaxIndex = 0x7FFFFFFF;
+constexpr int32_t kRankSlots = 32;  // plans a ranking can hold (the network's output limit)
 
 bool valid_lanes(int32_t l) { return l == 4 || l == 8 || l == 16 || l == 32 || l == 64; }
 
@@ -235,7 +236,7 @@ size_t spk_workspace_bytes(int32_t op, const spk_csr *A, int64_t K, const spk_pl
     case SPK_OP_TRANSPOSE: return transpose_ws_bytes(A->m, A->n, A->nnz);
     case SPK_OP_BSR4: return scan_ws_bytes_i32((A->m + 3) / 4 + 1);
     case SPK_OP_SELECT:
-        return align_up(sizeof(int64_t) * 28) + align_up(sizeof(int32_t) * 4) + features_ws_bytes(A->m);
+        return align_up(sizeof(int64_t) * 28) + align_up(sizeof(int32_t) * kRankSlots) + features_ws_bytes(A->m);
     default: return 0;
     }
 }
@@ -479,16 +480,18 @@ int32_t selector_load(int32_t op, const float *table, int64_t F, int64_t H, int6
     return SPK_OK;
 }
 
-int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void *ws, size_t ws_bytes, void *stream) {
+int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t k, spk_plan *out, int32_t *count, void *ws,
+                  size_t ws_bytes, void *stream) {
     int32_t st = check_csr(A);
     if (st) return st;
-    if (!out) return SPK_ERR_NULL;
+    if (!out || !count) return SPK_ERR_NULL;
+    if (k < 1 || k > kRankSlots) return SPK_ERR_SIZE;
     if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
     if (op != SPK_OP_SPMM && op != SPK_OP_SDDMM) return SPK_ERR_OP;
     const int dev = current_device();
     if (dev < 0) return SPK_ERR_HIP;
     if (!g_loaded[dev][op]) return SPK_ERR_NO_MODEL;
-    const size_t f_bytes = align_up(sizeof(int64_t) * 28), o_bytes = align_up(sizeof(int32_t) * 4);
+    const size_t f_bytes = align_up(sizeof(int64_t) * 28), o_bytes = align_up(sizeof(int32_t) * kRankSlots);
     if ((st = check_ws(f_bytes + o_bytes + features_ws_bytes(A->m), ws, ws_bytes))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
@@ -498,11 +501,20 @@ int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void
         return st;
     const int64_t *d = g_dims[dev][op];
     if ((st = hip_status(select_launch(op, f, K, d[0], d[1], d[2], idx, s)))) return st;
-    int32_t host = -1;
-    if (hipMemcpyAsync(&host, idx, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return SPK_ERR_HIP;
+    int32_t host[kRankSlots];
+    if (hipMemcpyAsync(host, idx, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess) return SPK_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return SPK_ERR_HIP;
-    if (host < 0) return SPK_ERR_PLAN;
-    return plan_of_index(op, host, K, out, nullptr);
+    int32_t c = 0;
+    for (; c < k && host[c] >= 0; ++c)
+        if ((st = plan_of_index(op, host[c], K, &out[c], nullptr))) return st;
+    *count = c;
+    return c > 0 ? SPK_OK : SPK_ERR_PLAN;
+}
+
+int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void *ws, size_t ws_bytes, void *stream) {
+    if (!out) return SPK_ERR_NULL;
+    int32_t count = 0;
+    return plan_rank(A, K, op, 1, out, &count, ws, ws_bytes, stream);
 }
 
 int32_t spk_csr_validate(const spk_csr *A, void *ws, size_t ws_bytes, void *stream) {

@@ -263,10 +263,17 @@ __global__ __launch_bounds__(kMaxHidden) void select_kernel(int32_t op, const lo
     __syncthreads();
     mlp_eval(tab + 2 * kMaxIn, d, x, a1, a2, y);
     if (threadIdx.x == 0) {
-        int best = -1;
-        for (int p = 0; p < d.P; ++p)
-            if (plan_valid(op, p, K) && (best < 0 || y[p] < y[best])) best = p;
-        out[0] = best;
+        // the plans valid for K in ascending predicted time (ties: lower
+        // index first), -1 after the last
+        bool taken[kMaxOut];
+        for (int p = 0; p < kMaxOut; ++p) taken[p] = false;
+        for (int r = 0; r < kMaxOut; ++r) {
+            int best = -1;
+            for (int p = 0; p < d.P; ++p)
+                if (!taken[p] && plan_valid(op, p, K) && (best < 0 || y[p] < y[best])) best = p;
+            out[r] = best;
+            if (best >= 0) taken[best] = true;
+        }
     }
 }
 

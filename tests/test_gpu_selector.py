@@ -135,6 +135,44 @@ def test_plan_select_matches_oracle_argmin(spk, sel):
     sel._loaded.clear()
 
 
+def test_plan_rank_matches_oracle_order(spk, sel):
+    """plan_rank lists the valid plans in ascending output of the FP64 oracle network (near-ties
+    excluded); its first plan is plan_select's, and select(verify=k) keeps one of the k."""
+    P = sel.plan_count(1)
+    parts = rand_params(P, seed=4)
+    mean = np.linspace(0, 0.5, 32).astype(np.float32)
+    scale = np.linspace(0.5, 1.5, 32).astype(np.float32)
+    table = {"op": 1, "F": 32, "H": 64, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
+             "params": np.concatenate([a.reshape(-1) for a in parts]).tolist()}
+    sel.load_table(table)
+    sel._loaded.add(torch.cuda.current_device())
+    net = oracle.MLP(*parts)
+    checked = 0
+    key = lambda p: (p.variant, p.lanes, p.chunk, p.flags)  # noqa: E731
+    for i, (n, d, K) in enumerate([(3000, 0.01, 64), (8000, 0.001, 256), (2048, 0.1, 32), (500, 0.3, 16)]):
+        A = synth.bernoulli(n, n, d, 20 + i)
+        dA = spk.CSR.from_host(A)
+        got = sel.rank(dA, K, 1, 6)
+        x = oracle.selector_inputs(oracle.features(A.row_ptr, A.col_idx, n), K)
+        y = net.forward(((x - mean) / scale)[None])[0]
+        plans = sel.plan_list(1, K)
+        valid = np.array([ok for _, ok in plans])
+        order = [int(j) for j in np.argsort(np.where(valid, y, np.inf), kind="stable") if valid[j]]
+        assert len(got) == min(6, len(order))
+        for j in range(len(got)):
+            if (j > 0 and y[order[j]] - y[order[j - 1]] < 1e-3) or (
+                    j + 1 < len(order) and y[order[j + 1]] - y[order[j]] < 1e-3):
+                continue
+            assert key(got[j]) == key(plans[order[j]][0]), (i, j)
+            checked += 1
+        assert key(sel.select(dA, K, 1, fallback=False)) == key(got[0])
+        assert key(sel.select(dA, K, 1, fallback=False, verify=3)) in {key(p) for p in got[:3]}
+    assert checked >= 10
+    with pytest.raises(spk.SpkError):
+        sel.rank(spk.CSR.from_host(synth.bernoulli(100, 100, 0.1, 1)), 64, 1, 33)
+    sel._loaded.clear()
+
+
 def test_training_reduces_loss(spk, sel):
     """A few hundred full-batch steps on a synthetic regression task."""
     P, N = 16, 512
