@@ -446,7 +446,12 @@ def run_workload(args):
     gen_s = time.perf_counter() - t0
     dA, B, U, V = to_device(p, kind)
     torch.cuda.synchronize()
-    p_spmm, p_sddmm = choose_plans(args.plan, dA, K, B, U, V, kind)
+    if args.plans:  # fixed plans (a profiled run repeats those of a bench line)
+        from paper_2604_27985_amd.api import Plan
+
+        p_spmm, p_sddmm = (None if x == "plain" else Plan.from_name(x) for x in args.plans.split(","))
+    else:
+        p_spmm, p_sddmm = choose_plans(args.plan, dA, K, B, U, V, kind)
     step = Step(dA, B, U, V, p_spmm, p_sddmm, kind)
     if args.calib_copy:
         # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE readings
@@ -472,7 +477,8 @@ def run_workload(args):
             v.pop(key)
     cfg = {"workload": name, "n": n, "nnz": nnz, "K": K, "pattern": "uniform" if kind == "uniform" else "powerlaw",
            "ops": "spmm+backward" if kind == "gcn" else "spmm+sddmm",
-           "plan": f"learned, best of the top {VERIFY} timed" if args.plan == "learned" else args.plan,
+           "plan": ("fixed" if args.plans else
+                    f"learned, best of the top {VERIFY} timed" if args.plan == "learned" else args.plan),
            "plans": {"spmm": p_spmm.name() if p_spmm else "plain",
                      ("backward" if kind == "gcn" else "sddmm"): p_sddmm.name() if p_sddmm else "plain"}}
     if kind == "uniform":
@@ -538,6 +544,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--plan", default="learned", choices=["plain", "tuned", "learned"])
+    ap.add_argument("--plans", default=None, help="fixed plans SPMM,SDDMM (or SPMM,BACKWARD) by name, e.g. "
+                    "tile/l16/c128/f2,tile/l16/c64/f6; overrides --plan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain-plan comparison")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="GIB",

@@ -38,6 +38,14 @@ class Plan:
             s += f"/f{self.flags}"
         return s
 
+    @classmethod
+    def from_name(cls, name: str) -> "Plan":
+        """Inverse of name(): "tile/l16/c64/f6" and the like."""
+        parts = name.split("/")
+        v = {"rows": VAR_ROWS, "merge": VAR_MERGE, "bsr4": 2, "slab": VAR_SLAB, "tile": 4}[parts[0]]
+        fields = {p[0]: int(p[1:]) for p in parts[1:]}
+        return cls(v, fields.get("l", 16), fields.get("c", 0), fields.get("f", 0))
+
 
 def _stream() -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
