@@ -91,6 +91,22 @@ def test_tile_plan_limits(lib):
     assert f(ctypes.byref(A), FAKE, 64, FAKE, 64, 0, 64, FAKE, ctypes.byref(tile(8, 16)), None, 0, None) == -6
 
 
+def test_plan_rank_argument_errors(lib):
+    """Checked before the device is touched: null outputs, k outside 1..32, K, op."""
+    A = csr()
+    out = (_lib.spk_plan * 4)()
+    count = ctypes.c_int32(-1)
+    f = lib.plan_rank
+    assert f(ctypes.byref(A), 64, 0, 4, None, ctypes.byref(count), FAKE, 1 << 20, None) == -1
+    assert f(ctypes.byref(A), 64, 0, 4, out, None, FAKE, 1 << 20, None) == -1
+    assert f(ctypes.byref(A), 64, 0, 0, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
+    assert f(ctypes.byref(A), 64, 0, 33, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
+    assert f(ctypes.byref(A), -1, 0, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
+    assert f(ctypes.byref(A), 64, 7, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) < 0
+    assert f(None, 64, 0, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) == -1
+    assert count.value == -1  # untouched on errors
+
+
 def test_sddmm_argument_errors(lib):
     A = csr()
     f = lib.sddmm_csr
