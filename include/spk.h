@@ -107,11 +107,13 @@ enum spk_variant {
                           16-byte aligned, ldu a multiple of 4, chunk * ldv *
                           element size below 4 GiB.
                           With flags bit 2, where a row of the dense operand
-                          is 128 or 256 bytes (SDDMM: ldu a multiple of 16
+                          is 128 or 256 bytes, or 512 bytes with F32 rows or
+                          (SDDMM) either type (SDDMM: ldu a multiple of 16
                           bytes and U 16-byte aligned too), the work inside a
                           16-lane group is split one entry per 4-lane quad
-                          (the lanes field is then not used); other shapes run
-                          the split above. */
+                          (the lanes field is then not used; rows of 512
+                          bytes keep 4 rows per group); other shapes run the
+                          split above. */
 };
 
 /* An execution plan: plain data, owned by the caller.
@@ -130,10 +132,10 @@ enum spk_variant {
  *          of two >= 16 whose slab fits 16 KiB).
  * flags    bit 0: use scalar (one element per lane) loads even when the
  *          operands allow 8/16-byte vector loads (not TILE).  bit 1 (TILE
- *          only): 8 rows per lane group instead of 4 (SpMM with BF16 rows of
- *          128 elements split by quads keeps 4).  bit 2 (TILE only): one entry
- *          per 4-lane quad where the rows fit (see SPK_VAR_TILE).  Other bits
- *          must be 0.
+ *          only): 8 rows per lane group instead of 4 (quad splits of 512-byte
+ *          rows and SpMM quad splits of BF16 rows of 128 elements keep 4).
+ *          bit 2 (TILE only): one entry per 4-lane quad where the rows fit
+ *          (see SPK_VAR_TILE).  Other bits must be 0.
  * Vector loads are used when K and the leading dimensions are multiples of
  * the vector width and the base pointers are aligned to it; otherwise the
  * call falls back to scalar loads by itself.
@@ -234,17 +236,17 @@ int32_t spmm_bsr4(const spk_bsr4 *A, const void *B, int64_t ldb, int32_t b_dtype
  * the fallback and the judge.
  * ------------------------------------------------------------------------ */
 
-/* Number of plans in an op's plan list (SPK_OP_SPMM: 22, SPK_OP_SDDMM: 21),
+/* Number of plans in an op's plan list (SPK_OP_SPMM: 24, SPK_OP_SDDMM: 23),
  * or 0 for other ops. */
 int32_t plan_count(int32_t op);
 
 /* Plan `index` of an op's plan list: index = 5 v + l (< 15) picks variant v
  * (ROWS, MERGE, SLAB) and lanes 4 << l; SpMM index 15 is SPK_VAR_BSR4 (lanes
- * 64); SpMM indices 16..21 are SPK_VAR_TILE with the plain lanes for K and a
- * slab of 16 KiB (16, 18, 20, 21) or 32 KiB (17, 19) of F32 rows, 8 rows per
- * group for 18, 19 and 21, one entry per quad (flags bit 2) for 20 and 21;
- * SDDMM indices 15..20 are the same six SPK_VAR_TILE plans (at least 16
- * lanes).  SDDMM MERGE plans use 256 entries per group.  *valid is 1
+ * 64); SpMM indices 16..23 are SPK_VAR_TILE with the plain lanes for K and a
+ * slab of 16 KiB (16, 18, 20, 21) or 32 KiB (17, 19, 22, 23) of F32 rows,
+ * 8 rows per group for the odd indices, one entry per quad (flags bit 2) for
+ * 20..23; SDDMM indices 15..22 are the same eight SPK_VAR_TILE plans (at
+ * least 16 lanes).  SDDMM MERGE plans use 256 entries per group.  *valid is 1
  * when the plan suits dense width K (lanes not wider than twice K rounded up
  * to a power of two, at least 16; SDDMM: at most 8 register slices; TILE: K
  * a multiple of 8 in [8, 256]).  Host only. */

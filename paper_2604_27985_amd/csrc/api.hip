@@ -80,7 +80,10 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
         const int64_t row_bytes = K * static_cast<int64_t>(es);
         // one entry per quad where a row of B is 128 or 256 bytes (16-lane
         // groups whatever the plan's lanes), else the plain split
-        r.quad_split = plan && (plan->flags & 4) && (row_bytes == 128 || row_bytes == 256) ? 1 : 0;
+        r.quad_split = plan && (plan->flags & 4) &&
+                               (row_bytes == 128 || row_bytes == 256 || (row_bytes == 512 && es == 4))
+                           ? 1
+                           : 0;
         if (r.quad_split) r.lanes = 16;
         if ((!r.quad_split && K > 4 * r.lanes) || K % sv != 0 || ldb % sv != 0 || !aligned(B, 16) || ldc % 4 != 0 ||
             !aligned(C, 16))
@@ -131,7 +134,8 @@ int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U
         // one entry per quad where rows are 128 or 256 bytes and U is read in
         // 16-byte pieces (16-lane groups whatever the plan's lanes), else the
         // plain split
-        r.quad_split = (plan->flags & 4) && (row_bytes == 128 || row_bytes == 256) && ldu % sv == 0 &&
+        r.quad_split = (plan->flags & 4) && (row_bytes == 128 || row_bytes == 256 || row_bytes == 512) &&
+                               ldu % sv == 0 &&
                                aligned(U, 16) && K % sv == 0 && ldv % sv == 0 && aligned(V, 16)
                            ? 1
                            : 0;
@@ -389,7 +393,7 @@ static int current_device() {
     return d;
 }
 
-int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 22 : op == SPK_OP_SDDMM ? 21 : 0; }
+int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 24 : op == SPK_OP_SDDMM ? 23 : 0; }
 
 int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid) {
     if (!out) return SPK_ERR_NULL;
@@ -399,15 +403,15 @@ int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32
         *out = spk_plan{SPK_VAR_BSR4, 64, 0, 0};
     } else if ((op == SPK_OP_SPMM && index >= 16) || (op == SPK_OP_SDDMM && index >= 15)) {
         // LDS slabs of 16 or 32 KiB of F32 rows (half that for BF16), 4 or 8
-        // rows per lane group; the last two split the work one entry per quad
-        // (16 KiB slabs)
+        // rows per lane group; the last four split the work one entry per
+        // quad (16 KiB slabs, then 32 KiB)
         const int t = index - (op == SPK_OP_SPMM ? 16 : 15);
-        const int64_t bytes = t < 4 && t % 2 == 1 ? 32768 : 16384;
+        const int64_t bytes = (t < 4 ? t % 2 == 1 : t >= 6) ? 32768 : 16384;
         const int64_t k = K > 0 ? K : 1;
         const int64_t w = bytes / (4 * k);
         int32_t lanes = default_spmm_lanes(K);
         if (op == SPK_OP_SDDMM && lanes < 16) lanes = 16;  // SDDMM TILE reduces over 16-lane rows
-        const int32_t flags = t < 4 ? (t >= 2 ? 2 : 0) : (t == 5 ? 6 : 4);
+        const int32_t flags = t < 4 ? (t >= 2 ? 2 : 0) : 4 | (t % 2 == 1 ? 2 : 0);
         *out = spk_plan{SPK_VAR_TILE, lanes, static_cast<int32_t>(w > 0 ? w : 1), flags};
     } else {
         static const int32_t variants[3] = {SPK_VAR_ROWS, SPK_VAR_MERGE, SPK_VAR_SLAB};

@@ -434,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void sddmm_tile_kernel(int64_t m, int64_t n
 // lane 4q + s of the same quad (a quad_perm broadcast, DPP 0x55 * s), and the
 // total of entry 4j + q ends on the lane that fetched it, which stores it
 // with its own weight.  In read i of a step quad q reads the 64-byte group
-// (i + q) mod NP of its row, piece j of it, so the four quads of a group read
-// different bank groups although their rows are unrelated.
+// quad_group(i, q) of its row, piece j of it, so the four quads of a group
+// read different bank groups although their rows are unrelated.
 // Partial dot product of two 16-byte pieces of a row: four FMAs on F32, four
 // two-element dot products (v_dot2c_f32_bf16: exact products, F32 sums) on
 // BF16, so the BF16 rows need no unpacking.
@@ -481,7 +481,7 @@ __device__ __forceinline__ int sddmm_tileq_pass(const unsigned char *__restrict_
                                                 int32_t last, int32_t &cur, int32_t end, int &c, TV &v,
                                                 const uint32_t (&pb)[NP], const u32x4 (&u)[NP],
                                                 float *__restrict__ S) {
-    constexpr int kRowShift = NP == 2 ? 7 : 8;  // log2 of a row's bytes
+    constexpr int kRowShift = NP == 2 ? 7 : NP == 4 ? 8 : 9;  // log2 of a row's bytes
     const bool in = cur + slot < end && c < c1;
     const int cnt = count16(__builtin_amdgcn_ballot_w64(in), gbase16);
     const int offb = in ? (c - c0) << kRowShift : 0;
@@ -533,9 +533,9 @@ __global__ __launch_bounds__(kBlock) void sddmm_tileq_kernel(int64_t m, int64_t 
     const int32_t last = static_cast<int32_t>(nnz - 1);  // row_ptr is int32: positions fit
     const bool has_vals = vals != nullptr;
     const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
-    uint32_t pb[NP];  // byte offset in a row of piece j of group (i + q) mod NP
+    uint32_t pb[NP];  // byte offset in a row of piece j of group quad_group(i, q)
 #pragma unroll
-    for (int i = 0; i < NP; ++i) pb[i] = static_cast<uint32_t>((((i + q) % NP) * 4 + j) * 16);
+    for (int i = 0; i < NP; ++i) pb[i] = static_cast<uint32_t>((quad_group<NP>(i, q) * 4 + j) * 16);
     int32_t cur[RPG], end[RPG];
     u32x4 u[RPG][NP];  // this lane's pieces of the rows of U, as stored
 #pragma unroll
@@ -608,6 +608,7 @@ static hipError_t launch_tileq(const SddmmArgs &a, hipStream_t s) {
     switch (a.K * static_cast<int64_t>(sizeof(TUV))) {
     case 128: return r8 ? launch_tileq_rpg<TUV, TV, 2, 8>(a, s) : launch_tileq_rpg<TUV, TV, 2, 4>(a, s);
     case 256: return r8 ? launch_tileq_rpg<TUV, TV, 4, 8>(a, s) : launch_tileq_rpg<TUV, TV, 4, 4>(a, s);
+    case 512: return launch_tileq_rpg<TUV, TV, 8, 4>(a, s);  // 32 registers of U per row: 4 rows per group
     default: return hipErrorInvalidValue;
     }
 }

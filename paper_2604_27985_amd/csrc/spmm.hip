@@ -349,20 +349,19 @@ __global__ __launch_bounds__(kBlock) void spmm_tile_kernel(int64_t m, int64_t n,
     }
 }
 
-// TILE with one entry per 4-lane quad (16-lane groups, rows of B of 128 or
-// 256 bytes).  The same slabs and chunks as above; inside a group the four
+// TILE with one entry per 4-lane quad (16-lane groups, rows of B of 128, 256
+// or 512 bytes).  The same slabs and chunks as above; inside a group the four
 // quads take four entries at once and each lane covers a quarter of the row
 // (NP pieces of 16 bytes), so an entry costs its FMAs, one address and one
 // weight broadcast per quad instead of per lane.  A chunk is fetched so that
 // lane 4q + j holds entry 4j + q: in step s quad q adds entry 4s + q, whose
 // row offset and weight sit on lane 4q + s (quad_perm broadcasts).  In read i
-// of a step quad q reads the 64-byte group (i + q) mod NP of its row, so the
-// four quads of a group hit different bank groups.  Each quad thus
-// accumulates every group of the row in a rotated order: acc[i] holds group
-// (i + q) mod NP.  At the end, group g of
-// the row is the sum over quads q' of their acc[(g - q') mod NP]; lane
-// (q, j) gathers group q from quad q - k with row_ror:4k (DPP 0x120 + 4k,
-// lane l reads lane l - 4k of its row), whose register is acc[k mod NP].
+// of a step quad q reads the 64-byte group quad_group(i, q) of its row
+// ((i + q) mod NP, rotated within halves for NP = 8), so the four quads of a
+// group hit different bank groups.  Each quad thus accumulates every group of
+// the row in a rotated order.  At the end lane (q, j) gathers groups q + 4h
+// from quad (q - k) mod 4 with row_ror:4k (DPP 0x120 + 4k, lane l reads lane
+// l - 4k of its row): that quad holds group q + 4h in acc[(4h + k) mod NP].
 template <typename TB, int NP, int S>
 __device__ __forceinline__ void spmm_qstep(const unsigned char *__restrict__ smem, const uint32_t (&pb)[NP],
                                            int offb, float w, float (&acc)[NP][kTileSV<TB>]) {
@@ -384,7 +383,7 @@ __device__ __forceinline__ int spmm_tileq_pass(const unsigned char *__restrict__
                                                const TV *__restrict__ vsrc, int32_t last, int32_t &cur, int32_t end,
                                                int &c, TV &v, const uint32_t (&pb)[NP],
                                                float (&acc)[NP][kTileSV<TB>]) {
-    constexpr int kRowShift = NP == 2 ? 7 : 8;  // log2 of a row's bytes
+    constexpr int kRowShift = NP == 2 ? 7 : NP == 4 ? 8 : 9;  // log2 of a row's bytes
     const bool in = cur + slot < end && c < c1;
     const int cnt = count16(__builtin_amdgcn_ballot_w64(in), gbase16);
     const int offb = in ? (c - c0) << kRowShift : 0;
@@ -426,9 +425,9 @@ __global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n
     const int32_t last = static_cast<int32_t>(nnz - 1);  // row_ptr is int32: positions fit
     const bool has_vals = vals != nullptr;
     const TV *vsrc = has_vals ? vals : reinterpret_cast<const TV *>(ci);
-    uint32_t pb[NP];  // byte offset in a row of piece j of group (i + q) mod NP
+    uint32_t pb[NP];  // byte offset in a row of piece j of group quad_group(i, q)
 #pragma unroll
-    for (int i = 0; i < NP; ++i) pb[i] = static_cast<uint32_t>((((i + q) % NP) * 4 + j) * 16);
+    for (int i = 0; i < NP; ++i) pb[i] = static_cast<uint32_t>((quad_group<NP>(i, q) * 4 + j) * 16);
     int32_t cur[RPG], end[RPG];
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
@@ -469,21 +468,26 @@ __global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n
         }
         tile_store<TB, NPT>(reinterpret_cast<TB *>(smem + ((sl + 1) & 1) * buf_bytes), stg);
     }
-    // lane (q, j) sums group q of each row over the four quads and, for q < NP,
-    // stores piece j of it: elements (4q + j) * SV .. + SV
+    // lane (q, j) sums groups g = q + 4h of each row over the four quads and,
+    // for g < NP, stores piece j of it: elements (4g + j) * SV .. + SV
+    constexpr int H = NP > 4 ? NP / 4 : 1;
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
-        float out[SV];
-#pragma unroll
-        for (int e = 0; e < SV; ++e) {
-            float t = acc[r][0][e];
-            t += dpp_move<0x124>(acc[r][1 % NP][e]);
-            t += dpp_move<0x128>(acc[r][2 % NP][e]);
-            t += dpp_move<0x12C>(acc[r][3 % NP][e]);
-            out[e] = t;
-        }
         const int64_t row = row0 + r;
-        if (row < m && q < NP) vec_store<float, SV>::run(C + row * ldc + (4 * q + j) * SV, out);
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            float out[SV];
+#pragma unroll
+            for (int e = 0; e < SV; ++e) {
+                float t = acc[r][(4 * h) % NP][e];
+                t += dpp_move<0x124>(acc[r][(4 * h + 1) % NP][e]);
+                t += dpp_move<0x128>(acc[r][(4 * h + 2) % NP][e]);
+                t += dpp_move<0x12C>(acc[r][(4 * h + 3) % NP][e]);
+                out[e] = t;
+            }
+            const int g = q + 4 * h;
+            if (row < m && g < NP) vec_store<float, SV>::run(C + row * ldc + (4 * g + j) * SV, out);
+        }
     }
 }
 
@@ -511,9 +515,10 @@ static hipError_t launch_tileq_rpg(const SpmmArgs &a, const TV *vals, hipStream_
     return launch_tileq_npt<TB, TV, NP, RPG, 8>(a, vals, s);
 }
 
-// Rows of 128 bytes (NP = 2) or 256 bytes (NP = 4); a BF16 row of 256 bytes
-// holds 128 elements, 32 per lane, and keeps 4 rows per group whatever the
-// plan asks (8 rows of 32 accumulators would not fit the registers).
+// Rows of 128 bytes (NP = 2), 256 bytes (NP = 4) or 512 bytes (NP = 8, F32
+// only).  A row of 32 accumulators per lane (F32 rows of 512 bytes, BF16 rows
+// of 256) keeps 4 rows per group whatever the plan asks: 8 would not fit the
+// registers.
 template <typename TB, typename TV>
 static hipError_t launch_tileq(const SpmmArgs &a, const TV *vals, hipStream_t s) {
     const bool r8 = a.rows_per_group == 8;
@@ -523,6 +528,9 @@ static hipError_t launch_tileq(const SpmmArgs &a, const TV *vals, hipStream_t s)
         if constexpr (sizeof(TB) == 4)
             if (r8) return launch_tileq_rpg<TB, TV, 4, 8>(a, vals, s);
         return launch_tileq_rpg<TB, TV, 4, 4>(a, vals, s);
+    case 512:
+        if constexpr (sizeof(TB) == 4) return launch_tileq_rpg<TB, TV, 8, 4>(a, vals, s);
+        return hipErrorInvalidValue;  // BF16 rows of 256 elements: 64 accumulators per lane and row
     default: return hipErrorInvalidValue;
     }
 }

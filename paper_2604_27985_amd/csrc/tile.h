@@ -113,4 +113,16 @@ __device__ __forceinline__ float quad_bcast(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), S * 0x55, 0xF, 0xF, false));
 }
 
+// The 64-byte group of a row that quad q reads in read i of a step, when a
+// lane covers NP pieces of 16 bytes: (i + q) mod NP for NP <= 4; for NP = 8
+// the rotation stays within each half of the row, (i + q) mod 4 + 4 (i / 4),
+// so that the group a quad holds in register i depends on q only mod 4, the
+// way the four quads of a 16-lane row are numbered.  In every read the four
+// quads of a row take four different groups (different LDS banks).
+template <int NP>
+__device__ __forceinline__ int quad_group(int i, int q) {
+    if constexpr (NP <= 4) return (i + q) % NP;
+    else return (i + q) % 4 + 4 * (i / 4);
+}
+
 }  // namespace spk

@@ -74,7 +74,7 @@ def test_sddmm_bf16(spk, K):
     dA = spk.CSR.from_host(A, v)
     tl = K // 4  # TILE plans: default and odd slab widths, 4 or 8 rows per group
     # flags bit 2: one entry per quad (two-element BF16 dot products) at K = 64 and 128
-    quad = [spk.Plan(4, 16, 0, 4), spk.Plan(4, 16, 11, 6)] if K in (64, 128) else []
+    quad = [spk.Plan(4, 16, 0, 4), spk.Plan(4, 16, 11, 6)]  # rows of 128, 256 and 512 bytes
     for plan in [None, spk.Plan(1, 16, 256), spk.Plan(0, 32), spk.Plan(3, 16, 0), spk.Plan(4, tl, 0),
                  spk.Plan(4, tl, 9, 2)] + quad:
         S = spk.sddmm(dA, Ut, Vt, plan=plan).cpu().numpy()

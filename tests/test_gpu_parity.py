@@ -91,7 +91,7 @@ def test_spmm_tile(spk, K, lanes, kind, m, n, d):
             assert_within(C, C64, M, TOL_F32, f"tile K={K} lanes={lanes} chunk={chunk} flags={flags}")
 
 
-@pytest.mark.parametrize("K", [64, 32])
+@pytest.mark.parametrize("K", [64, 32, 128])
 @pytest.mark.parametrize("kind,m,n,d", [("uniform", 3001, 2500, 0.05), ("powerlaw", 6000, 6000, 12),
                                         ("block4", 1024, 4096, 0.02), ("uniform", 7, 5, 0.5)])
 def test_spmm_tile_quad_split(spk, K, kind, m, n, d):
@@ -107,9 +107,9 @@ def test_spmm_tile_quad_split(spk, K, kind, m, n, d):
                   "quad spmm pattern")
 
 
-@pytest.mark.parametrize("K,lanes", [(48, 16), (128, 32), (16, 4), (8, 4)])
+@pytest.mark.parametrize("K,lanes", [(48, 16), (256, 64), (16, 4), (8, 4)])
 def test_tile_quad_flag_falls_back_to_plain_split(spk, K, lanes):
-    """Rows other than 128 or 256 bytes run the plain TILE split with the plan's lanes."""
+    """Rows other than 128, 256 or 512 bytes run the plain TILE split with the plan's lanes."""
     A, v, B, U = problem(1500, 1200, 0.03, K, 14)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
     for flags in (4, 6):
@@ -274,11 +274,11 @@ def test_sddmm_tile(spk, K, lanes, kind, m, n, d):
                   "tile sddmm pattern")
 
 
-@pytest.mark.parametrize("K", [64, 32])
+@pytest.mark.parametrize("K", [64, 32, 128])
 @pytest.mark.parametrize("kind,m,n,d", [("uniform", 3001, 2500, 0.05), ("powerlaw", 6000, 6000, 12),
                                         ("block4", 1024, 4096, 0.02), ("uniform", 7, 5, 0.5)])
 def test_sddmm_tile_quad_split(spk, K, kind, m, n, d):
-    """One entry per 4-lane quad (flags bit 2): rows of 128 and 256 bytes, odd and one-row slabs."""
+    """One entry per 4-lane quad (flags bit 2): rows of 128, 256 and 512 bytes, odd and one-row slabs."""
     A, v, V, U = problem(m, n, d, K, 12, kind)
     S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
     for chunk in (0, 7, 1, 31):

@@ -15,13 +15,14 @@ from paper_2604_27985_amd import selector  # noqa: E402
 
 
 def test_plan_lists():
-    assert selector.plan_count(_lib.OP_SPMM) == 22 and selector.plan_count(_lib.OP_SDDMM) == 21
+    assert selector.plan_count(_lib.OP_SPMM) == 24 and selector.plan_count(_lib.OP_SDDMM) == 23
     pl = selector.plan_list(_lib.OP_SPMM, 64)
     assert [p.variant for p, _ in pl[:15]] == [0] * 5 + [1] * 5 + [3] * 5 and pl[15][0].variant == 2
     # LDS slabs of 16 / 32 KiB of F32 rows (K = 64: 256-byte rows), 4 or 8 rows per group, then one
-    # entry per quad (flags bit 2) with 16 KiB slabs
+    # entry per quad (flags bit 2) with 16 and 32 KiB slabs
     assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in pl[16:]] == [
-        (4, 16, 64, 0), (4, 16, 128, 0), (4, 16, 64, 2), (4, 16, 128, 2), (4, 16, 64, 4), (4, 16, 64, 6)]
+        (4, 16, 64, 0), (4, 16, 128, 0), (4, 16, 64, 2), (4, 16, 128, 2), (4, 16, 64, 4), (4, 16, 64, 6),
+        (4, 16, 128, 4), (4, 16, 128, 6)]
     assert all(ok for _, ok in pl[16:])
     for K, ok in ((8, True), (36, False), (256, True), (512, False)):
         assert all(v == ok for _, v in selector.plan_list(_lib.OP_SPMM, K)[16:]), K
@@ -36,8 +37,9 @@ def test_plan_lists():
     assert all(p.chunk == 256 for p, _ in sd[5:10])
     # SDDMM TILE plans: at least 16 lanes (reductions over 16-lane rows)
     assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in selector.plan_list(_lib.OP_SDDMM, 32)[15:]] == [
-        (4, 16, 128, 0), (4, 16, 256, 0), (4, 16, 128, 2), (4, 16, 256, 2), (4, 16, 128, 4), (4, 16, 128, 6)]
-    assert [p.lanes for p, _ in sd[15:]] == [64] * 6 and all(ok for _, ok in sd[15:])
+        (4, 16, 128, 0), (4, 16, 256, 0), (4, 16, 128, 2), (4, 16, 256, 2), (4, 16, 128, 4), (4, 16, 128, 6),
+        (4, 16, 256, 4), (4, 16, 256, 6)]
+    assert [p.lanes for p, _ in sd[15:]] == [64] * 8 and all(ok for _, ok in sd[15:])
 
 
 def test_plain_index_matches_null_plan_rule():
@@ -102,6 +104,6 @@ def test_extended_timings_merge(tmp_path):
     ext.write_text(json.dumps({"index": 1, "op": "spmm", "plans": [16, 17, 18, 19], "ms": [0.5, None, 0.7, 0.8]}) + "\n")
     assert selector.merge_timings(str(base), str(ext), str(out)) == 1
     m = selector.load_timings(str(out))
-    assert m[0]["ms_spmm"] == [1.0] * 16 + [None] * 6
-    assert m[1]["ms_spmm"] == [3.0] * 16 + [0.5, None, 0.7, 0.8, None, None]
-    assert m[1]["ms_sddmm"] == [4.0] * 15 + [None] * 6  # widened to the SDDMM plan count
+    assert m[0]["ms_spmm"] == [1.0] * 16 + [None] * 8
+    assert m[1]["ms_spmm"] == [3.0] * 16 + [0.5, None, 0.7, 0.8] + [None] * 4
+    assert m[1]["ms_sddmm"] == [4.0] * 15 + [None] * 8  # widened to the SDDMM plan count
