@@ -262,7 +262,7 @@ def to_device(p, kind):
     return dA, B, U, V
 
 
-VERIFY = 3  # candidates of the learned ranking timed before the run
+VERIFY = 5  # candidates of the learned ranking timed before the run
 
 
 def autotune_sweep(A, K, B, plans):
@@ -281,7 +281,7 @@ def choose_plans(mode, dA, K, B, U, V, kind):
     if mode == "learned":
         from paper_2604_27985_amd import selector
 
-        # the network's three best plans, timed once on these operands
+        # the network's VERIFY best plans, timed once on these operands
         p1 = selector.select(dA, K, spk.OP_SPMM, verify=VERIFY, B=B)
         if kind == "gcn":
             # the backward's product runs on A^T: ask for a plan for that matrix

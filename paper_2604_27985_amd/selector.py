@@ -394,11 +394,12 @@ def train_op(records: list[dict], op: int, steps: int = 4000, lr: float = 3e-3, 
     Y = trainer.forward(torch.from_numpy(Xs).cuda()).cpu().numpy()
     pick = choose(Y, mask)
     plain = np.array([plain_index(op, r["K"]) for r in records])
-    pick3 = best_of_top(Y, mask, times, 3)
     report = {"op": "spmm" if op == OP_SPMM else "sddmm", "loss_history": hist,
               "train": regret_stats(times[tr], pick[tr], plain[tr]),
-              "test": regret_stats(times[te], pick[te], plain[te]),
-              "test_best_of_top3": regret_stats(times[te], pick3[te], plain[te])}
+              "test": regret_stats(times[te], pick[te], plain[te])}
+    for k in (3, 5):
+        pk = best_of_top(Y, mask, times, k)
+        report[f"test_best_of_top{k}"] = regret_stats(times[te], pk[te], plain[te])
     table = {"op": int(op), "F": F, "H": trainer.H, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
              "params": trainer.params.cpu().tolist(), "seed": seed, "steps": steps, "lr": lr,
              "plans": [p.name() for p, _ in plan_list(op, 64)]}

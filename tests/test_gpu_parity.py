@@ -354,7 +354,7 @@ def test_f64_kernels_match_oracle(spk):
 
 def test_uniform_90_percent_full_size_sampled(spk):
     """n = 65536 at 90% sparsity (4.3e8 entries), K = 64, seed 0: the plans the
-    bench times (the learned ones, best of the network's top three) and the
+    bench times (the learned ones, best of the network's top five) and the
     LDS-slab plans, plain and one entry per quad, on sampled rows of C and the
     entries of sampled rows of S."""
     from paper_2604_27985_amd import selector
@@ -373,11 +373,11 @@ def test_uniform_90_percent_full_size_sampled(spk):
     lo = torch.from_numpy(A.row_ptr[rows].astype(np.int64)).cuda()
     cnt = torch.from_numpy((A.row_ptr[rows + 1] - A.row_ptr[rows]).astype(np.int64)).cuda()
     ent = torch.cat([torch.arange(int(a), int(a) + int(c), device="cuda") for a, c in zip(lo, cnt)])
-    for plan in (selector.select(dA, K, spk.OP_SPMM, verify=3, B=B), spk.Plan(4, 16, 64), spk.Plan(4, 16, 128, 2),
+    for plan in (selector.select(dA, K, spk.OP_SPMM, verify=5, B=B), spk.Plan(4, 16, 64), spk.Plan(4, 16, 128, 2),
                  spk.Plan(4, 16, 64, 4), spk.Plan(4, 16, 64, 6)):
         C = spk.spmm(dA, B, plan=plan)
         assert_within(C[r].cpu().numpy(), C64, CM, TOL_F32, f"full-size spmm {plan.name()}")
-    for plan in (selector.select(dA, K, spk.OP_SDDMM, verify=3, U=U, V=V), spk.Plan(4, 16, 64),
+    for plan in (selector.select(dA, K, spk.OP_SDDMM, verify=5, U=U, V=V), spk.Plan(4, 16, 64),
                  spk.Plan(4, 16, 128, 2), spk.Plan(4, 16, 64, 4), spk.Plan(4, 16, 64, 6)):
         S = spk.sddmm(dA, U, V, plan=plan)
         assert_within(S[ent].cpu().numpy(), S64, SM, TOL_F32, f"full-size sddmm {plan.name()}")
