@@ -18,6 +18,10 @@ Prints ONE JSON line on stdout:
                 rate of 78.6 TFLOP/s without packed FP32)
   cpu_baseline  the FP64 CPU oracle timed on the first rows of the same
                 workload (about --cpu-budget seconds) on this host's cores
+  kernels       per part: mean time over the timed steps (warm: operands the
+                previous step left in L2 and the MALL stay there) and
+                cold_ms, the median of five launches each preceded by a 1 GiB
+                read that evicts them
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--plan plain|tuned|learned]
   python bench.py --sweep OUT.jsonl    # the n x sparsity x K grid, one record per op
@@ -370,6 +374,33 @@ def time_steps(step, steps, warmup):
     return total_ms, wall, first_ms, second_ms
 
 
+def time_cold(step, reps=5, flush_bytes=1 << 30):
+    """Median per-part times with the caches cold: before each launch a 1 GiB
+    buffer (four times the 256 MB MALL, far beyond the L2s) is read, so the
+    launch finds none of its operands cached.  Reading rather than writing
+    leaves clean lines behind, so no write-backs compete with the launch."""
+    import numpy as np
+    import torch
+
+    scratch = torch.ones(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    out = []
+    for part in (step.first, step.second):
+        ts = []
+        for _ in range(reps):
+            scratch.sum()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            part()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out.append(float(np.median(ts)))
+    del scratch
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(p, kind, C, S, budget_s=12.0):
     """FP64 oracle (SpMM + SDDMM) on the first rows of the workload, sized to about
     budget_s of CPU work, timed on this host; also the scaled error of the GPU
@@ -462,8 +493,11 @@ def run_workload(args):
         torch.cuda.synchronize()
         del src, dst
     total_ms, wall, first_ms, second_ms = time_steps(step, args.steps, args.warmup)
+    cold = time_cold(step)
     nnz = p.A.nnz
     kt = kernel_table(p, kind, K, float(np.mean(first_ms)) * 1e-3, float(np.mean(second_ms)) * 1e-3)
+    for part, c in zip(kt, cold):  # warm (the steps above) and cold (caches flushed before each launch)
+        kt[part]["cold_ms"] = round(c, 4)
     flops_step = sum(v["_f"] for v in kt.values())
     ms_step = total_ms / args.steps
     value = flops_step / (ms_step * 1e-3) / 1e9
