@@ -107,3 +107,14 @@ def test_extended_timings_merge(tmp_path):
     assert m[0]["ms_spmm"] == [1.0] * 16 + [None] * 8
     assert m[1]["ms_spmm"] == [3.0] * 16 + [0.5, None, 0.7, 0.8] + [None] * 4
     assert m[1]["ms_sddmm"] == [4.0] * 15 + [None] * 8  # widened to the SDDMM plan count
+
+
+def test_plan_names_round_trip():
+    """Plan.name() and Plan.from_name() are inverse (bench --plans reads the names bench lines print)."""
+    from paper_2604_27985_amd.api import Plan
+
+    for op in (_lib.OP_SPMM, _lib.OP_SDDMM):
+        for K in (8, 32, 64, 128, 256):
+            for p, _ in selector.plan_list(op, K):
+                q = Plan.from_name(p.name())
+                assert (q.variant, q.lanes, q.chunk, q.flags) == (p.variant, p.lanes, p.chunk, p.flags)
