@@ -191,6 +191,29 @@ def test_spmm_strided_operands(spk):
     assert (out[:, 40:] == 9.0).all()
 
 
+@pytest.mark.parametrize("K,lanes", [(64, 16), (128, 32), (32, 8)])
+def test_tile_strided_operands(spk, K, lanes):
+    """TILE plans, plain and one entry per quad, on views of wider tensors: ldb, ldc, ldu and
+    ldv above K (multiples of 16 bytes), outputs outside the view untouched."""
+    A, v, B, U = problem(700, 600, 0.05, K, 15)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    S64, SM = oracle.sddmm(A.row_ptr, A.col_idx, v, U, B)
+    dA = spk.CSR.from_host(A, v)
+    Bw = torch.zeros(600, K + 12, device="cuda")
+    Bw[:, :K] = dev(B)
+    Uw = torch.zeros(700, K + 20, device="cuda")
+    Uw[:, :K] = dev(U)
+    for flags in (0, 2, 4, 6):
+        Cw = torch.full((700, K + 8), 9.0, device="cuda")
+        spk.spmm(dA, Bw[:, :K], plan=spk.Plan(4, lanes, 0, flags), out=Cw[:, :K])
+        S = spk.sddmm(dA, Uw[:, :K], Bw[:, :K], plan=spk.Plan(4, max(lanes, 16), 0, flags))
+        torch.cuda.synchronize()
+        out = Cw.cpu().numpy()
+        assert_within(out[:, :K], C64, M, TOL_F32, f"strided tile spmm K={K} flags={flags}")
+        assert (out[:, K:] == 9.0).all()
+        assert_within(S.cpu().numpy(), S64, SM, TOL_F32, f"strided tile sddmm K={K} flags={flags}")
+
+
 @pytest.mark.parametrize("kind,n,d", [("powerlaw", 20000, 16), ("banded", 5000, 0.2), ("block4", 4096, 0.01)])
 def test_spmm_structured_patterns(spk, kind, n, d):
     A, v, B, _ = problem(n, n, d, 64, 5, kind)
