@@ -493,11 +493,13 @@ def run_workload(args):
         torch.cuda.synchronize()
         del src, dst
     total_ms, wall, first_ms, second_ms = time_steps(step, args.steps, args.warmup)
-    cold = time_cold(step)
+    # a profiled run (--calib-copy) launches only the steps, so that its
+    # counters divide by steps + warmup
+    cold = [None, None] if args.calib_copy else time_cold(step)
     nnz = p.A.nnz
     kt = kernel_table(p, kind, K, float(np.mean(first_ms)) * 1e-3, float(np.mean(second_ms)) * 1e-3)
     for part, c in zip(kt, cold):  # warm (the steps above) and cold (caches flushed before each launch)
-        kt[part]["cold_ms"] = round(c, 4)
+        kt[part]["cold_ms"] = None if c is None else round(c, 4)
     flops_step = sum(v["_f"] for v in kt.values())
     ms_step = total_ms / args.steps
     value = flops_step / (ms_step * 1e-3) / 1e9
