@@ -305,17 +305,33 @@ def choose_plans(mode, dA, K, B, U, V, kind):
     return p1, autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
 
 
+def choose_dvals_plan(mode, dA, K, U, V):
+    """The GCN backward's pattern SDDMM (dvals = SDDMM(pattern, G, B)): NULL
+    (plain), the timed search, or the network's best plans timed once."""
+    import paper_2604_27985_amd as spk
+
+    if mode == "plain":
+        return None
+    if mode == "learned":
+        from paper_2604_27985_amd import selector
+
+        return selector.select(dA, K, spk.OP_SDDMM, verify=VERIFY, U=U, V=V)
+    from paper_2604_27985_amd import autotune
+
+    return autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
+
+
 class Step:
     """One pass of the hot path with preallocated outputs and workspaces."""
 
-    def __init__(self, dA, B, U, V, p_spmm, p_sddmm, kind):
+    def __init__(self, dA, B, U, V, p_spmm, p_sddmm, kind, p_dvals=None):
         import torch
 
         import paper_2604_27985_amd as spk
 
         self.spk, self.kind = spk, kind
         self.dA, self.B, self.U, self.V = dA, B, U, V
-        self.p_spmm, self.p_sddmm = p_spmm, p_sddmm
+        self.p_spmm, self.p_sddmm, self.p_dvals = p_spmm, p_sddmm, p_dvals
         K = B.shape[1]
         self.C = torch.empty((dA.m, K), dtype=torch.float32, device="cuda")
         self.S = torch.empty(dA.nnz, dtype=torch.float32, device="cuda")
@@ -325,6 +341,8 @@ class Step:
         self.ws2 = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
         if kind == "gcn":
             self.G = U
+            nb = spk.workspace_bytes(spk.OP_SDDMM, dA, K, p_dvals)
+            self.ws3 = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             spk.csr_transpose(dA)  # warm
             ev0.record()
@@ -339,8 +357,10 @@ class Step:
 
     def second(self):
         if self.kind == "gcn":
-            # p_sddmm carries the plan of the backward's A^T product
-            self.dB, self.S = self.spk.spmm_backward(self.dA, self.B, self.G, plan=self.p_sddmm)
+            # p_sddmm carries the plan of the backward's A^T product; dvals runs
+            # as its own pattern SDDMM on the plan chosen for it
+            self.dB, _ = self.spk.spmm_backward(self.dA, self.B, self.G, need_dvals=False, plan=self.p_sddmm)
+            self.spk.sddmm(self.dA, self.G, self.B, plan=self.p_dvals, out=self.S, workspace=self.ws3, pattern=True)
         else:
             self.spk.sddmm(self.dA, self.U, self.V, plan=self.p_sddmm, out=self.S, workspace=self.ws2)
 
@@ -477,13 +497,19 @@ def run_workload(args):
     gen_s = time.perf_counter() - t0
     dA, B, U, V = to_device(p, kind)
     torch.cuda.synchronize()
+    p_dvals = None
     if args.plans:  # fixed plans (a profiled run repeats those of a bench line)
         from paper_2604_27985_amd.api import Plan
 
-        p_spmm, p_sddmm = (None if x == "plain" else Plan.from_name(x) for x in args.plans.split(","))
+        named = [None if x == "plain" else Plan.from_name(x) for x in args.plans.split(",")]
+        p_spmm, p_sddmm = named[0], named[1]
+        if kind == "gcn" and len(named) > 2:
+            p_dvals = named[2]
     else:
         p_spmm, p_sddmm = choose_plans(args.plan, dA, K, B, U, V, kind)
-    step = Step(dA, B, U, V, p_spmm, p_sddmm, kind)
+        if kind == "gcn":
+            p_dvals = choose_dvals_plan(args.plan, dA, K, U, V)
+    step = Step(dA, B, U, V, p_spmm, p_sddmm, kind, p_dvals)
     if args.calib_copy:
         # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE readings
         # calibrate the counters of the kernels profiled in the same run
@@ -517,6 +543,8 @@ def run_workload(args):
                     f"learned, best of the top {VERIFY} timed" if args.plan == "learned" else args.plan),
            "plans": {"spmm": p_spmm.name() if p_spmm else "plain",
                      ("backward" if kind == "gcn" else "sddmm"): p_sddmm.name() if p_sddmm else "plain"}}
+    if kind == "gcn":
+        cfg["plans"]["backward_sddmm"] = p_dvals.name() if p_dvals else "plain"
     if kind == "uniform":
         cfg["sparsity"] = 1 - d
     else:
@@ -580,7 +608,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--plan", default="learned", choices=["plain", "tuned", "learned"])
-    ap.add_argument("--plans", default=None, help="fixed plans SPMM,SDDMM (or SPMM,BACKWARD) by name, e.g. "
+    ap.add_argument("--plans", default=None, help="fixed plans SPMM,SDDMM (or SPMM,BACKWARD,BACKWARD_SDDMM) by name, e.g. "
                     "tile/l16/c128/f2,tile/l16/c64/f6; overrides --plan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain-plan comparison")
