@@ -626,12 +626,25 @@ __global__ __launch_bounds__(kBlock) void merge_fixup_kernel(int64_t ngroups, in
     if (g >= ngroups) return;
     const int32_t r = carry_row[g];
     if (r < 0 || (g > 0 && carry_row[g - 1] == r)) return;
+    // The run's end, 64 shares per probe: each lane tests one share and the
+    // first lane whose share carries another row (or lies past the end) marks
+    // it.  The conditions above are uniform over the wave, so all 64 lanes
+    // take part.
+    const int lane = threadIdx.x & (kWave - 1);
     int64_t g_end = g + 1;
-    while (g_end < ngroups && carry_row[g_end] == r) ++g_end;
-    // A long row's run spans many shares: eight carries are loaded at a time
+    for (;;) {
+        const int64_t h = g_end + lane;
+        const uint64_t other = __ballot(!(h < ngroups && carry_row[h] == r));
+        if (other) {
+            g_end += __ffsll(static_cast<long long>(other)) - 1;
+            break;
+        }
+        g_end += kWave;
+    }
+    // A long row's run spans many shares: 16 carries are loaded at a time
     // (independent loads in flight) and added in share order, so the sum is
     // the same as one carry at a time.
-    constexpr int D = 8;
+    constexpr int D = 16;
     for (int k = threadIdx.x & (kWave - 1); k < K; k += kWave) {
         A s = A(0);
         for (int64_t h = g; h < g_end; h += D) {
