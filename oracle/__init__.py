@@ -67,6 +67,8 @@ def _load():
     lib.oracle_adam.restype = None
     lib.oracle_selector_inputs.argtypes = [vp, i64, vp]
     lib.oracle_selector_inputs.restype = None
+    lib.oracle_csr_canonical.argtypes = [i64, i64, i64, vp, vp]
+    lib.oracle_csr_canonical.restype = ctypes.c_int32
     _lib = lib
     return lib
 
@@ -144,6 +146,19 @@ def spmm_backward(row_ptr, col_idx, vals, B, G, n: int):
     dB, dBM = spmm_t(row_ptr, col_idx, vals, G, n)
     dv, dvM = sddmm(row_ptr, col_idx, None, G, B)
     return dB, dBM, dv, dvM
+
+
+# Rules of canonical CSR (bit values of csr_canonical's result).
+CSR_BAD_START, CSR_BAD_END, CSR_BAD_ORDER, CSR_BAD_COL, CSR_BAD_SORT, CSR_BAD_DUP = 1, 2, 4, 8, 16, 32
+
+
+def csr_canonical(row_ptr, col_idx, m: int, n: int, nnz: int | None = None) -> int:
+    """OR of the canonical-CSR rules the arrays break (0: canonical); see oracle.c."""
+    lib = _load()
+    rp = None if row_ptr is None else _i32(row_ptr)
+    ci = _i32(col_idx if col_idx is not None else np.zeros(0, np.int32))
+    nnz = ci.shape[0] if nnz is None else nnz
+    return int(lib.oracle_csr_canonical(m, n, nnz, _p(rp), _p(ci)))
 
 
 def round_bf16(x) -> np.ndarray:

@@ -136,6 +136,44 @@ void oracle_spmm_t(int64_t m, int64_t n, int64_t K, const int32_t *row_ptr,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Canonical CSR, the input form every product assumes (the paper sends    */
+/* CSR with 32-bit column indices, Section III-A, and is silent on order   */
+/* and duplicates; the reading taken here is the usual canonical form).    */
+/* Returns the OR of the rules A breaks, 0 when it is canonical:           */
+/*   1  row_ptr[0] != 0                       (m > 0)                      */
+/*   2  row_ptr[m] != nnz                     (for m = 0: nnz != 0)        */
+/*   4  some row has row_ptr[i+1] < row_ptr[i], row_ptr[i] < 0 or           */
+/*      row_ptr[i+1] > nnz                                                  */
+/*   8  a column outside [0, n) in a row that passed rule 4                 */
+/*  16  two neighbours of such a row in decreasing column order             */
+/*  32  two neighbours of such a row with the same column (a duplicate)     */
+/* Rules 8..32 look only at rows whose range lies inside [0, nnz], so no   */
+/* rule reads outside the arrays.  row_ptr may be NULL when m = 0.          */
+/* ---------------------------------------------------------------------- */
+int32_t oracle_csr_canonical(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx) {
+    int32_t bad = 0;
+    if (m == 0) return nnz != 0 ? 2 : 0;
+    if (row_ptr[0] != 0) bad |= 1;
+    if ((int64_t)row_ptr[m] != nnz) bad |= 2;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t a = row_ptr[i], b = row_ptr[i + 1];
+        if (b < a || a < 0 || b > nnz) {
+            bad |= 4;
+            continue;
+        }
+        for (int64_t p = a; p < b; ++p) {
+            if (col_idx[p] < 0 || (int64_t)col_idx[p] >= n) bad |= 8;
+            if (p + 1 < b) {
+                if (col_idx[p + 1] < col_idx[p]) bad |= 16;
+                if (col_idx[p + 1] == col_idx[p]) bad |= 32;
+            }
+        }
+    }
+    return bad;
+}
+
+/* ---------------------------------------------------------------------- */
 /* bfloat16 rounding of binary32 values, round to nearest, ties to even.   */
 /* The result is returned as a binary32 value whose low 16 bits are zero.  */
 /* NaN inputs stay NaN (quiet bit forced); infinities are kept.            */

@@ -324,3 +324,50 @@ def test_adam_first_step_closed_form():
     # a constant gradient keeps m_hat = g, v_hat = g^2 at every step
     oracle.adam(w, g, mom, vel, 1e-3, 0.9, 0.999, 1e-8, 2)
     assert np.allclose(w, w0 - 2e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- canonical CSR
+def test_csr_canonical_hand_cases():
+    """One hand-worked case per rule of canonical CSR (tests/golden/csr_canonical.json)."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "csr_canonical.json")))
+    for c in g["cases"]:
+        got = oracle.csr_canonical(np.array(c["row_ptr"]), np.array(c["col_idx"], np.int32), c["m"], c["n"], c["nnz"])
+        assert got == c["bits"], (c["name"], got)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_csr_canonical_against_scipy_and_single_mutations(seed):
+    """Generated patterns are canonical (scipy agrees); a swap of two neighbours
+    breaks only the order rule, a copied neighbour only the duplicate rule, a
+    column pushed to n only the range rule, and every such matrix is flagged
+    exactly when scipy's has_canonical_format (sorted, no duplicates) says no."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    for A in (synth.bernoulli(300, 200, 0.05, seed), synth.powerlaw(500, 8, 2.1, seed),
+              synth.block4(64, 96, 0.1, seed), synth.bernoulli(200, 200, 0.05, seed, band=8)):
+        assert oracle.csr_canonical(A.row_ptr, A.col_idx, A.m, A.n) == 0
+        lens = np.diff(A.row_ptr)
+        for kind in ("swap", "dup", "range"):
+            ci = A.col_idx.copy()
+            rows = np.flatnonzero(lens >= 2)
+            i = int(rng.choice(rows))
+            p = int(A.row_ptr[i] + rng.integers(0, lens[i] - 1))
+            if kind == "swap":
+                ci[p], ci[p + 1] = ci[p + 1], ci[p]
+                want = oracle.CSR_BAD_SORT
+            elif kind == "dup":
+                ci[p + 1] = ci[p]
+                want = oracle.CSR_BAD_DUP
+            else:
+                ci[A.row_ptr[i + 1] - 1] = A.n  # the last entry of the row: stays increasing
+                want = oracle.CSR_BAD_COL
+            assert oracle.csr_canonical(A.row_ptr, ci, A.m, A.n) == want, kind
+            if kind != "range":
+                M = sp.csr_matrix((np.ones(A.nnz), ci, A.row_ptr), shape=(A.m, A.n))
+                assert not M.has_canonical_format
+        M = sp.csr_matrix((np.ones(A.nnz), A.col_idx, A.row_ptr), shape=(A.m, A.n))
+        assert M.has_canonical_format
