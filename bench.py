@@ -6,9 +6,10 @@ operand resident in HBM before the timed region:
   powerlaw-bf16  the same two products with BF16 dense operands, FP32 accumulation
   gcn            forward SpMM + backward (dB = A^T G, dvals = SDDMM(pattern, G, B)),
                  FP32; the transpose is per-pattern preprocessing, timed once
-The default workload is the paper's headline shape (random N x N at 90%
-sparsity, the largest N = 65536, Section IV-A) with dense width 64: uniform
-column positions, values and dense operands ~ N(0, 1), FP32, seed 0.
+The default workload is the largest single-GPU configuration of the scaling
+sweep: the paper's headline shape (random N x N at 90% sparsity, the largest
+N = 65536, Section IV-A) with dense width 128: uniform column positions,
+values and dense operands ~ N(0, 1), FP32, seed 0.
 
 Prints ONE JSON line on stdout:
   value         whole-job GFLOP/s (2 nnz K flops per product, all products)
@@ -18,10 +19,12 @@ Prints ONE JSON line on stdout:
                 rate of 78.6 TFLOP/s without packed FP32)
   cpu_baseline  the FP64 CPU oracle timed on the first rows of the same
                 workload (about --cpu-budget seconds) on this host's cores
-  kernels       per part: mean time over the timed steps (warm: operands the
-                previous step left in L2 and the MALL stay there) and
-                cold_ms, the median of five launches each preceded by a 1 GiB
-                read that evicts them
+  kernels       per part: mean and median time over the timed steps (warm:
+                operands the previous step left in L2 and the MALL stay
+                there) and cold_ms, the median of five launches each preceded
+                by a 1 GiB read that evicts them
+  parity        the largest |gpu - oracle| / (|A| |B|) over the oracle's
+                sample, against the 1e-5 gate
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--plan plain|tuned|learned]
   python bench.py --sweep OUT.jsonl    # the n x sparsity x K grid, one record per op
@@ -58,7 +61,7 @@ WORKLOADS = {
     "uniform-n16384-s99.9-K128": (16384, 0.001, 128, "uniform"),
     "uniform-n1024-s90-K64": (1024, 0.1, 64, "uniform"),
 }
-DEFAULT_WORKLOAD = "uniform-n65536-s90-K64"
+DEFAULT_WORKLOAD = "uniform-n65536-s90-K128"
 SWEEP = [w for w, v in WORKLOADS.items() if v[3] == "uniform" and v[0] >= 16384]
 
 
@@ -341,7 +344,8 @@ class Step:
         self.ws2 = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
         if kind == "gcn":
             self.G = U
-            nb = spk.workspace_bytes(spk.OP_SDDMM, dA, K, p_dvals)
+            self.dB = torch.empty((dA.n, K), dtype=torch.float32, device="cuda")
+            nb = spk.backward_workspace_bytes(dA, K, p_sddmm, p_dvals)
             self.ws3 = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             spk.csr_transpose(dA)  # warm
@@ -357,10 +361,10 @@ class Step:
 
     def second(self):
         if self.kind == "gcn":
-            # p_sddmm carries the plan of the backward's A^T product; dvals runs
-            # as its own pattern SDDMM on the plan chosen for it
-            self.dB, _ = self.spk.spmm_backward(self.dA, self.B, self.G, need_dvals=False, plan=self.p_sddmm)
-            self.spk.sddmm(self.dA, self.G, self.B, plan=self.p_dvals, out=self.S, workspace=self.ws3, pattern=True)
+            # one backward call: p_sddmm is the plan of its A^T product,
+            # p_dvals that of its pattern SDDMM
+            self.spk.spmm_backward(self.dA, self.B, self.G, plan=self.p_sddmm, dvals_plan=self.p_dvals,
+                                   out_dB=self.dB, out_dvals=self.S, workspace=self.ws3)
         else:
             self.spk.sddmm(self.dA, self.U, self.V, plan=self.p_sddmm, out=self.S, workspace=self.ws2)
 
@@ -461,8 +465,25 @@ def cpu_baseline(p, kind, C, S, budget_s=12.0):
         es = np.where(SM > 0, np.abs(s - S64) / SM, np.abs(s - S64))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"first {rows} of {A.m} rows ({nnz_s} entries): SpMM + SDDMM in FP64, {dt:.1f} s",
-            "gpu_max_scaled_err": float(max(ec.max(initial=0.0), es.max(initial=0.0)))}
+            "gpu_max_scaled_err": float(max(ec.max(initial=0.0), es.max(initial=0.0))),
+            "gpu_max_scaled_err_parts": {"spmm": float(ec.max(initial=0.0)),
+                                         ("dvals" if kind == "gcn" else "sddmm"): float(es.max(initial=0.0))}}
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or platform.machine()
 
 
 def kernel_table(p, kind, K, t1, t2):
@@ -524,7 +545,9 @@ def run_workload(args):
     cold = [None, None] if args.calib_copy else time_cold(step)
     nnz = p.A.nnz
     kt = kernel_table(p, kind, K, float(np.mean(first_ms)) * 1e-3, float(np.mean(second_ms)) * 1e-3)
-    for part, c in zip(kt, cold):  # warm (the steps above) and cold (caches flushed before each launch)
+    for part, c, ts in zip(kt, cold, (first_ms, second_ms)):
+        # warm (the steps above: mean and median) and cold (caches flushed before each launch)
+        kt[part]["ms_median"] = round(float(np.median(ts)), 4)
         kt[part]["cold_ms"] = None if c is None else round(c, 4)
     flops_step = sum(v["_f"] for v in kt.values())
     ms_step = total_ms / args.steps
@@ -569,6 +592,9 @@ def run_workload(args):
         out["speedup_vs_plain"] = round(p_ms / ms_step, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, kind, step.C, step.S, args.cpu_budget)
+        out["parity"] = {"max_scaled_err": out["cpu_baseline"]["gpu_max_scaled_err"], "gate": 1e-5,
+                         "ok": out["cpu_baseline"]["gpu_max_scaled_err"] <= 1e-5,
+                         "sample": out["cpu_baseline"]["sample"].split(":")[0]}
     print(json.dumps(out), flush=True)
 
 
@@ -604,8 +630,8 @@ def run_sweep(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--plan", default="learned", choices=["plain", "tuned", "learned"])
     ap.add_argument("--plans", default=None, help="fixed plans SPMM,SDDMM (or SPMM,BACKWARD,BACKWARD_SDDMM) by name, e.g. "

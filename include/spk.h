@@ -188,16 +188,23 @@ int32_t csr_transpose(const spk_csr *A, int32_t *at_row_ptr, int32_t *at_col_idx
 /* Backward of C = A B for a loss with dL/dC = G (device [m x K]):
  *   dB    = A^T G                    device [n x K], nullable (skipped)
  *   dvals = SDDMM(pattern of A, G, B) device [nnz],  nullable (skipped)
+ * (chain rule on Eq. (1): dC/dB[j,:] collects the entries of column j, and
+ * dC[i,:]/da_p = B[col(p), :], sampled on A's pattern as in Eq. (2)).
  * The transpose (at_row_ptr, at_col_idx, perm) comes from csr_transpose; the
- * values of A^T are gathered through perm.  dtype is F32 (B and G F32, or
- * BF16 operands with F32 outputs) or F64 (everything F64).
- * plan  applies to the A^T SpMM (NULL = plain); the SDDMM uses its default.
- * ws    spk_workspace_bytes(SPK_OP_BACKWARD, ...) bytes. */
+ * values of A^T are gathered through perm.  dtype is F32 (B and G F32) or
+ * F64 (everything F64).
+ * plan        applies to the A^T SpMM (NULL = plain row-split), as a plan of
+ *             spmm_csr would on the matrix A^T (BSR4 is not accepted).
+ * dvals_plan  applies to the pattern SDDMM, as a plan of sddmm_csr would on A
+ *             (NULL = the default entry-split plan).
+ * ws    the two products run one after the other on `stream` and share it:
+ *       max(spk_workspace_bytes(SPK_OP_BACKWARD, A, K, plan),
+ *           spk_workspace_bytes(SPK_OP_SDDMM, A, K, dvals_plan)) bytes. */
 int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int32_t *at_col_idx,
                           const int32_t *perm, const void *B, int64_t ldb, const void *G,
                           int64_t ldg, int32_t dtype, int64_t K, void *dB, int64_t lddb,
-                          void *dvals, const spk_plan *plan, void *ws, size_t ws_bytes,
-                          void *stream);
+                          void *dvals, const spk_plan *plan, const spk_plan *dvals_plan, void *ws,
+                          size_t ws_bytes, void *stream);
 
 /* A 4x4 block-sparse matrix (block CSR): block row I holds rows 4I..4I+3 of
  * A, block column J columns 4J..4J+3; edge blocks are padded with zeros. */
@@ -317,10 +324,27 @@ int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void
 int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t k, spk_plan *out, int32_t *count, void *ws,
                   size_t ws_bytes, void *stream);
 
-/* Opt-in O(nnz) structural check of A (canonical CSR as described above).
- * ws    at least 16 bytes.  Synchronises `stream`.  Returns SPK_OK or
- *       SPK_ERR_STRUCTURE. */
-int32_t spk_csr_validate(const spk_csr *A, void *ws, size_t ws_bytes, void *stream);
+/* Rules of canonical CSR, as bits of spk_csr_validate's *rules.  The paper
+ * sends CSR with 32-bit column indices (Section III-A) and leaves order and
+ * duplicates open; the library reads it as the canonical form. */
+enum spk_csr_rule {
+    SPK_CSR_BAD_START = 1,  /* m > 0 and row_ptr[0] != 0 */
+    SPK_CSR_BAD_END = 2,    /* row_ptr[m] != nnz (m = 0: nnz != 0) */
+    SPK_CSR_BAD_ORDER = 4,  /* a row with row_ptr[i+1] < row_ptr[i], row_ptr[i] < 0
+                               or row_ptr[i+1] > nnz */
+    SPK_CSR_BAD_COL = 8,    /* a column outside [0, n) (rows passing rule 4) */
+    SPK_CSR_BAD_SORT = 16,  /* neighbours in decreasing column order (same rows) */
+    SPK_CSR_BAD_DUP = 32    /* neighbours with equal columns (same rows) */
+};
+
+/* Opt-in O(nnz) structural check of A against canonical CSR (above).  Only
+ * rows whose range lies inside [0, nnz] are read, so any int32 contents of
+ * row_ptr are safe to check.
+ * rules  host, nullable: receives the OR of the spk_csr_rule bits A breaks
+ *        (0 when it is canonical).
+ * ws     device, at least 16 bytes.  Synchronises `stream`.  Returns SPK_OK,
+ *        SPK_ERR_STRUCTURE, or an argument error. */
+int32_t spk_csr_validate(const spk_csr *A, int32_t *rules, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

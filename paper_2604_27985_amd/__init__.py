@@ -9,7 +9,7 @@ from ._lib import BF16, F32, F64, OP_BACKWARD, OP_SDDMM, OP_SPMM, OP_TRANSPOSE, 
 
 __all__ = [
     "CSR", "Plan", "spmm", "sddmm", "csr_transpose", "spmm_backward", "spmm_autograd", "validate",
-    "workspace_bytes", "SpkError", "F32", "BF16", "F64", "OP_SPMM", "OP_SDDMM", "OP_BACKWARD", "OP_TRANSPOSE",
+    "validate_rules", "backward_workspace_bytes", "workspace_bytes", "SpkError", "F32", "BF16", "F64", "OP_SPMM", "OP_SDDMM", "OP_BACKWARD", "OP_TRANSPOSE",
     "VAR_ROWS", "VAR_MERGE", "VAR_BSR4", "VAR_SLAB",
 ]
 
@@ -18,7 +18,7 @@ def __getattr__(name):
     # torch-dependent API is imported lazily so that the generator subpackage
     # can be used without touching torch or the HIP library.
     if name in ("CSR", "Plan", "spmm", "sddmm", "csr_transpose", "spmm_backward", "spmm_autograd", "validate",
-                "workspace_bytes", "SpMMFunction", "BSR4", "csr_to_bsr4", "spmm_bsr4"):
+                "validate_rules", "backward_workspace_bytes", "workspace_bytes", "SpMMFunction", "BSR4", "csr_to_bsr4", "spmm_bsr4"):
         from . import api
 
         return getattr(api, name)

@@ -62,9 +62,9 @@ SIGNATURES = {
     "spmm_csr": ([_CSR_P, _P, _I64, _I32, _I64, _P, _I64, _PLAN_P, _P, _SZ, _P], _I32),
     "sddmm_csr": ([_CSR_P, _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P, _SZ, _P], _I32),
     "csr_transpose": ([_CSR_P, _P, _P, _P, _P, _SZ, _P], _I32),
-    "spmm_csr_backward": ([_CSR_P, _P, _P, _P, _P, _I64, _P, _I64, _I32, _I64, _P, _I64, _P, _PLAN_P, _P,
-                           _SZ, _P], _I32),
-    "spk_csr_validate": ([_CSR_P, _P, _SZ, _P], _I32),
+    "spmm_csr_backward": ([_CSR_P, _P, _P, _P, _P, _I64, _P, _I64, _I32, _I64, _P, _I64, _P, _PLAN_P, _PLAN_P,
+                           _P, _SZ, _P], _I32),
+    "spk_csr_validate": ([_CSR_P, ctypes.POINTER(_I32), _P, _SZ, _P], _I32),
     "csr_to_bsr4_count": ([_CSR_P, _P, ctypes.POINTER(ctypes.c_int64), _P, _SZ, _P], _I32),
     "csr_to_bsr4_fill": ([_CSR_P, _P, _P, _P, _P], _I32),
     "spmm_bsr4": ([ctypes.POINTER(spk_bsr4), _P, _I64, _I32, _I64, _P, _I64, _P], _I32),

@@ -7,6 +7,7 @@ on the host or falls back to another implementation.
 from __future__ import annotations
 
 import ctypes
+import weakref
 from dataclasses import dataclass, field
 
 import torch
@@ -122,13 +123,23 @@ class CSR:
         return self._transpose
 
     def block_form(self, vals: torch.Tensor | None = None) -> "BSR4":
-        """4x4 block form for these values, built on the GPU once and cached."""
+        """4x4 block form for these values, built on the GPU once and cached.
+
+        The cache is keyed on the values tensor itself (a weak reference, so
+        it holds no memory) and its in-place version counter: another tensor,
+        even one the allocator placed at the same address, or an in-place
+        update of the same tensor, rebuilds the tiles."""
         v = self.vals if vals is None else vals
-        key = None if v is None else (v.data_ptr(), v._version)
         cache = getattr(self, "_bsr4", None)
-        if cache is None or cache[0] != key:
-            self._bsr4 = (key, csr_to_bsr4(self, vals))
-        return self._bsr4[1]
+        if cache is not None:
+            ref, version, form = cache
+            same = (v is None and ref is None) or (v is not None and ref is not None and ref() is v
+                                                   and version == v._version)
+            if same:
+                return form
+        form = csr_to_bsr4(self, vals)
+        self._bsr4 = (None if v is None else weakref.ref(v), None if v is None else v._version, form)
+        return form
 
 
 def workspace_bytes(op: int, A: CSR, K: int, plan: Plan | None = None) -> int:
@@ -206,9 +217,19 @@ def csr_transpose(A: CSR):
     return trp, tci, perm
 
 
+def backward_workspace_bytes(A: CSR, K: int, plan: Plan | None = None, dvals_plan: Plan | None = None) -> int:
+    """Workspace of spmm_backward: its two products run in order and share it."""
+    return max(workspace_bytes(OP_BACKWARD, A, K, plan), workspace_bytes(OP_SDDMM, A, K, dvals_plan))
+
+
 def spmm_backward(A: CSR, B: torch.Tensor, G: torch.Tensor, need_dB: bool = True, need_dvals: bool = True,
-                  plan: Plan | None = None, vals: torch.Tensor | None = None):
-    """(dB, dvals) of C = A B for dL/dC = G: dB = A^T G, dvals = SDDMM(pattern, G, B)."""
+                  plan: Plan | None = None, vals: torch.Tensor | None = None, dvals_plan: Plan | None = None,
+                  out_dB: torch.Tensor | None = None, out_dvals: torch.Tensor | None = None,
+                  workspace: torch.Tensor | None = None):
+    """(dB, dvals) of C = A B for dL/dC = G: dB = A^T G, dvals = SDDMM(pattern, G, B).
+
+    plan is a plan for the A^T product (one chosen for A^T, not for A);
+    dvals_plan one for the pattern SDDMM on A.  BSR4 plans are not accepted."""
     lib = _lib.load()
     _require_device(A.row_ptr, B, G)
     _rowmajor(B, "B")
@@ -217,14 +238,25 @@ def spmm_backward(A: CSR, B: torch.Tensor, G: torch.Tensor, need_dB: bool = True
         raise ValueError("B and G must share dtype float32 or float64")
     K = int(B.shape[1])
     trp, tci, perm = A.transpose() if need_dB else (None, None, None)
-    dB = torch.empty((A.n, K), dtype=B.dtype, device=B.device) if need_dB else None
-    dv = torch.empty(A.nnz, dtype=B.dtype, device=B.device) if need_dvals else None
+    dB = None
+    if need_dB:
+        dB = out_dB if out_dB is not None else torch.empty((A.n, K), dtype=B.dtype, device=B.device)
+        _rowmajor(dB, "dB")
+    dv = None
+    if need_dvals:
+        dv = out_dvals if out_dvals is not None else torch.empty(A.nnz, dtype=B.dtype, device=B.device)
     ca = A.c(vals)
     cp = plan.c() if plan is not None else None
-    ws, nb = _workspace(OP_BACKWARD, A, K, plan, B.device)
+    cq = dvals_plan.c() if dvals_plan is not None else None
+    if workspace is not None:
+        ws, nb = workspace, workspace.numel()
+    else:
+        nb = backward_workspace_bytes(A, K, plan, dvals_plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device=B.device) if nb else None
     st = lib.spmm_csr_backward(ctypes.byref(ca), _ptr(trp), _ptr(tci), _ptr(perm), _ptr(B), B.stride(0), _ptr(G),
                                G.stride(0), _DT[B.dtype], K, _ptr(dB), dB.stride(0) if dB is not None else K,
-                               _ptr(dv), ctypes.byref(cp) if cp else None, _ptr(ws), nb, _stream())
+                               _ptr(dv), ctypes.byref(cp) if cp else None, ctypes.byref(cq) if cq else None,
+                               _ptr(ws), nb, _stream())
     _lib.check(st, "spmm_csr_backward")
     return dB, dv
 
@@ -285,26 +317,37 @@ def spmm_bsr4(Ab: BSR4, B: torch.Tensor, out: torch.Tensor | None = None) -> tor
     return C
 
 
-def validate(A: CSR) -> bool:
-    """Opt-in structural check on the GPU (synchronises the stream)."""
+def validate_rules(A: CSR) -> int:
+    """Opt-in structural check on the GPU (synchronises the stream): the OR of
+    the canonical-CSR rules A breaks (spk_csr_rule bits), 0 when canonical."""
     lib = _lib.load()
     ws = torch.empty(16, dtype=torch.uint8, device=A.row_ptr.device)
     ca = A.c(use_vals=False)
-    st = lib.spk_csr_validate(ctypes.byref(ca), _ptr(ws), 16, _stream())
-    if st == -8:
-        return False
-    _lib.check(st, "spk_csr_validate")
-    return True
+    rules = ctypes.c_int32(0)
+    st = lib.spk_csr_validate(ctypes.byref(ca), ctypes.byref(rules), _ptr(ws), 16, _stream())
+    if st not in (0, -8):
+        _lib.check(st, "spk_csr_validate")
+    return int(rules.value)
+
+
+def validate(A: CSR) -> bool:
+    """True when A is canonical CSR (see validate_rules)."""
+    return validate_rules(A) == 0
 
 
 class SpMMFunction(torch.autograd.Function):
-    """C = A(vals) B with gradients for vals and B from the library's backward."""
+    """C = A(vals) B with gradients for vals and B from the library's backward.
+
+    The forward plan is chosen for A; the backward's A^T product and pattern
+    SDDMM take their own plans (NULL, the plain ones, by default), since a
+    plan picked for A says nothing of A^T and a block plan has no transposed
+    form."""
 
     @staticmethod
-    def forward(ctx, vals, B, A, plan):
+    def forward(ctx, vals, B, A, plan, backward_plan, dvals_plan):
         C = spmm(A, B, plan=plan, vals=vals)
         ctx.save_for_backward(vals, B)
-        ctx.A, ctx.plan = A, plan
+        ctx.A, ctx.backward_plan, ctx.dvals_plan = A, backward_plan, dvals_plan
         return C
 
     @staticmethod
@@ -312,10 +355,15 @@ class SpMMFunction(torch.autograd.Function):
         vals, B = ctx.saved_tensors
         G = G.contiguous()
         dB, dv = spmm_backward(ctx.A, B, G, need_dB=ctx.needs_input_grad[1], need_dvals=ctx.needs_input_grad[0],
-                               plan=ctx.plan, vals=vals)
-        return dv, dB, None, None
+                               plan=ctx.backward_plan, vals=vals, dvals_plan=ctx.dvals_plan)
+        return dv, dB, None, None, None, None
 
 
-def spmm_autograd(A: CSR, vals: torch.Tensor, B: torch.Tensor, plan: Plan | None = None) -> torch.Tensor:
-    """Differentiable SpMM in vals and B."""
-    return SpMMFunction.apply(vals, B, A, plan)
+def spmm_autograd(A: CSR, vals: torch.Tensor, B: torch.Tensor, plan: Plan | None = None,
+                  backward_plan: Plan | None = None, dvals_plan: Plan | None = None) -> torch.Tensor:
+    """Differentiable SpMM in vals and B.  plan: the forward's (any SpMM plan,
+    BSR4 included); backward_plan: the A^T product's; dvals_plan: the pattern
+    SDDMM's."""
+    if backward_plan is not None and backward_plan.variant == _lib.VAR_BSR4:
+        raise ValueError("the A^T product has no block plan")
+    return SpMMFunction.apply(vals, B, A, plan, backward_plan, dvals_plan)

@@ -345,7 +345,8 @@ int32_t csr_transpose(const spk_csr *A, int32_t *at_row_ptr, int32_t *at_col_idx
 
 int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int32_t *at_col_idx, const int32_t *perm,
                           const void *B, int64_t ldb, const void *G, int64_t ldg, int32_t dtype, int64_t K, void *dB,
-                          int64_t lddb, void *dvals, const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+                          int64_t lddb, void *dvals, const spk_plan *plan, const spk_plan *dvals_plan, void *ws,
+                          size_t ws_bytes, void *stream) {
     int32_t st = check_csr(A);
     if (st) return st;
     if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
@@ -371,12 +372,13 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
     if (dvals && A->nnz > 0) {
         if (!G || !B) return SPK_ERR_NULL;
         if (K > 0 && (ldg < K || ldb < K)) return SPK_ERR_LD;
-        spk_csr P = *A;
-        P.vals = nullptr;
+        // the pattern SDDMM runs after A^T G on the same stream, so the two
+        // share the workspace
         Resolved r;
-        if ((st = resolve_sddmm(nullptr, K, dtype, G, ldg, B, ldb, r))) return st;
-        SddmmArgs a{P.m, P.n, P.nnz, K, P.row_ptr, P.col_idx, nullptr, G, ldg, B, ldb, dtype, dvals,
-                    r.variant, r.lanes, r.vec, r.chunk, nullptr};
+        if ((st = resolve_sddmm(dvals_plan, K, dtype, G, ldg, B, ldb, r))) return st;
+        if ((st = check_ws(sddmm_ws(A->m, A->n, r), ws, ws_bytes))) return st;
+        SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, nullptr, G, ldg, B, ldb, dtype, dvals,
+                    r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group, r.quad_split};
         if ((st = hip_status(sddmm_launch(a, s)))) return st;
     }
     return SPK_OK;
@@ -521,7 +523,7 @@ int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void
     return plan_rank(A, K, op, 1, out, &count, ws, ws_bytes, stream);
 }
 
-int32_t spk_csr_validate(const spk_csr *A, void *ws, size_t ws_bytes, void *stream) {
+int32_t spk_csr_validate(const spk_csr *A, int32_t *rules, void *ws, size_t ws_bytes, void *stream) {
     int32_t st = check_csr(A);
     if (st) return st;
     if (!ws || ws_bytes < 16) return SPK_ERR_WORKSPACE;
@@ -531,7 +533,8 @@ int32_t spk_csr_validate(const spk_csr *A, void *ws, size_t ws_bytes, void *stre
     int32_t host = 0;
     if (hipMemcpyAsync(&host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return SPK_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return SPK_ERR_HIP;
-    if (A->m == 0 && A->nnz != 0) return SPK_ERR_STRUCTURE;
+    if (A->m == 0 && A->nnz != 0) host |= SPK_CSR_BAD_END;  // no rows, yet stored entries
+    if (rules) *rules = host;
     return host == 0 ? SPK_OK : SPK_ERR_STRUCTURE;
 }
 

@@ -277,8 +277,11 @@ hipError_t transpose_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
 
 // ---------------------------------------------------------------- validation
 // Bits of the result flag.
-enum { kBadStart = 1, kBadEnd = 2, kBadOrder = 4, kBadCol = 8, kBadSort = 16 };
+// Rules of canonical CSR, one bit each (the same numbering as spk.h).
+enum { kBadStart = 1, kBadEnd = 2, kBadOrder = 4, kBadCol = 8, kBadSort = 16, kBadDup = 32 };
 
+// One wave per row: the row's range is checked first; only a range inside
+// [0, nnz] is read, so a broken row_ptr never sends a load out of bounds.
 __global__ __launch_bounds__(kBlock) void validate_kernel(int64_t m, int64_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ ci, int32_t *__restrict__ flag) {
     const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
@@ -289,12 +292,16 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(int64_t m, int64_t n, 
     if (row == m - 1 && lane == 0 && rp[m] != nnz) bad |= kBadEnd;
     const int64_t a = rp[row], b = rp[row + 1];
     if (b < a || a < 0 || b > nnz) {
-        bad |= kBadOrder;
+        if (lane == 0) bad |= kBadOrder;
     } else {
         for (int64_t p = a + lane; p < b; p += kWave) {
             const int32_t c = ci[p];
             if (c < 0 || c >= n) bad |= kBadCol;
-            if (p + 1 < b && ci[p + 1] <= c) bad |= kBadSort;
+            if (p + 1 < b) {
+                const int32_t d = ci[p + 1];
+                if (d < c) bad |= kBadSort;
+                if (d == c) bad |= kBadDup;
+            }
         }
     }
     if (bad) atomicOr(flag, bad);
@@ -304,7 +311,7 @@ hipError_t validate_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                            hipStream_t s) {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(kBlock), 0, s, flag, 1, 0);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || m == 0) return e;
+    if (e != hipSuccess || m == 0) return e;  // no rows: the caller checks nnz
     hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(m, kBlock / kWave)), dim3(kBlock), 0, s, m, n, nnz, rp, ci, flag);
     return hipGetLastError();
 }

@@ -126,13 +126,13 @@ def test_transpose_and_backward_argument_errors(lib):
     assert need > 0
     assert lib.csr_transpose(ctypes.byref(A), FAKE, FAKE, FAKE, FAKE, need - 1, None) == -5
     bw = lib.spmm_csr_backward
-    assert bw(ctypes.byref(A), FAKE, FAKE, FAKE, FAKE, 16, FAKE, 16, 1, 16, FAKE, 16, None, None, None, 0,
+    assert bw(ctypes.byref(A), FAKE, FAKE, FAKE, FAKE, 16, FAKE, 16, 1, 16, FAKE, 16, None, None, None, None, 0,
               None) == -3  # BF16 backward is not offered
-    assert bw(ctypes.byref(A), None, FAKE, FAKE, FAKE, 16, FAKE, 16, 0, 16, FAKE, 16, None, None, None, 0,
+    assert bw(ctypes.byref(A), None, FAKE, FAKE, FAKE, 16, FAKE, 16, 0, 16, FAKE, 16, None, None, None, None, 0,
               None) == -1
-    assert bw(ctypes.byref(A), FAKE, FAKE, FAKE, FAKE, 16, FAKE, 8, 0, 16, FAKE, 16, None, None, None, 0,
+    assert bw(ctypes.byref(A), FAKE, FAKE, FAKE, FAKE, 16, FAKE, 8, 0, 16, FAKE, 16, None, None, None, None, 0,
               None) == -4
-    assert lib.spk_csr_validate(ctypes.byref(A), None, 0, None) == -5
+    assert lib.spk_csr_validate(ctypes.byref(A), None, None, 0, None) == -5
 
 
 def test_workspace_sizes(lib):

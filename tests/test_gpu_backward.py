@@ -61,53 +61,116 @@ def gcn_layer(n=262144, mean=16, K=128, seed=0):
     return A, vals, B, G
 
 
-@pytest.mark.parametrize("plan_args", [None, (1, 32, 0), (0, 16, 0), (3, 32, 1000), (4, 32, 0), (4, 32, 7, 2)])
-def test_backward_matches_oracle(spk, plan_args):
+@pytest.mark.parametrize("plan_args,dvals_args", [(None, None), ((1, 32, 0), (1, 32, 256)), ((0, 16, 0), (0, 32, 0)),
+                                                   ((3, 32, 1000), (3, 16, 0)), ((4, 32, 0), (4, 32, 0, 4)),
+                                                   ((4, 32, 7, 2), (4, 32, 9, 6))])
+def test_backward_matches_oracle(spk, plan_args, dvals_args):
+    """Both products of the backward on their own plans (A^T G and the pattern
+    SDDMM), the workspace shared as the header states."""
     A, v, B, G = gcn_layer(n=30000, mean=16, K=128, seed=2)
     dB64, dBM, dv64, dvM = oracle.spmm_backward(A.row_ptr, A.col_idx, v, B, G, A.n)
     plan = None if plan_args is None else spk.Plan(*plan_args)
+    dplan = None if dvals_args is None else spk.Plan(*dvals_args)
     dA = spk.CSR.from_host(A, v)
-    dB, dv = spk.spmm_backward(dA, dev(B), dev(G), plan=plan)
+    dB, dv = spk.spmm_backward(dA, dev(B), dev(G), plan=plan, dvals_plan=dplan)
     torch.cuda.synchronize()
-    assert_within(dB.cpu().numpy(), dB64, dBM, TOL_F32, "dB")
-    assert_within(dv.cpu().numpy(), dv64, dvM, TOL_F32, "dvals")
+    assert_within(dB.cpu().numpy(), dB64, dBM, TOL_F32, f"dB {plan}")
+    assert_within(dv.cpu().numpy(), dv64, dvM, TOL_F32, f"dvals {dplan}")
+    # preallocated outputs and an explicit workspace of exactly the stated size
+    nb = spk.backward_workspace_bytes(dA, 128, plan, dplan)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    oB = torch.full((A.n, 128), 7.0, device="cuda")
+    ov = torch.full((A.nnz,), 7.0, device="cuda")
+    spk.spmm_backward(dA, dev(B), dev(G), plan=plan, dvals_plan=dplan, out_dB=oB, out_dvals=ov, workspace=ws)
+    assert torch.equal(oB, dB) and torch.equal(ov, dv)
 
 
 def test_backward_full_size_sampled(spk):
-    """n = 262144, mean degree 16, K = 128: sampled rows of dB and entries of dvals."""
+    """n = 262144, mean degree 16, K = 128: sampled rows of dB and entries of
+    dvals, on the plans the GCN bench line runs (the forward's merge-path
+    plan, row-split A^T G, merge-path pattern SDDMM: the recorded profile's
+    plans) and on the network's five best plans timed once for each product."""
+    from paper_2604_27985_amd import selector
+
     A, v, B, G = gcn_layer()
+    K = B.shape[1]
     dA = spk.CSR.from_host(A, v)
-    dB, dv = spk.spmm_backward(dA, dev(B), dev(G), plan=spk.Plan(1, 32, 0))
-    torch.cuda.synchronize()
-    dB, dv = dB.cpu().numpy(), dv.cpu().numpy()
-    # dB rows j: the oracle's A^T G restricted to sampled columns of A
+    Bd, Gd = dev(B), dev(G)
+    trp_d, tci_d, _ = dA.transpose()
+    AT_d = spk.CSR(trp_d, tci_d, None, (A.n, A.m))
+    cands = [p for p in selector.rank(AT_d, K, spk.OP_SPMM, 6) if p.variant != spk.VAR_BSR4]
+    from paper_2604_27985_amd import autotune
+    learned_bwd = min(autotune.sweep(AT_d, K, spk.OP_SPMM, B=Gd, plans=cands[:5], reps=2, warmup=1),
+                      key=lambda r: r[1])[0]
+    learned_dv = selector.select(dA, K, spk.OP_SDDMM, verify=5, U=Gd, V=Bd)
+    # dB rows j: the oracle's SpMM over the sampled rows of A^T (the oracle's
+    # own transpose), values gathered through its perm
     trp, tci, perm = oracle.csr_transpose(A.row_ptr, A.col_idx, A.n)
     AT = synth.HostCSR(A.n, A.m, trp, tci)
-    cols = np.unique(synth.randint(300, A.n, 3))
+    cols = np.unique(np.concatenate([synth.randint(300, A.n, 3), np.argsort(np.diff(trp))[-3:]]))
     srp, sci, idx = sub_rows(AT, cols)
-    ref, M = oracle.spmm(srp, sci, v[perm[idx]], G)
-    assert_within(dB[cols], ref, M, TOL_F32, "dB sampled")
-    ps = np.unique(synth.randint(5000, A.nnz, 4))
-    rows = np.searchsorted(A.row_ptr, ps, side="right") - 1
-    exact = np.einsum("ik,ik->i", G[rows].astype(np.float64), B[A.col_idx[ps]].astype(np.float64))
-    bound = np.einsum("ik,ik->i", np.abs(G[rows]).astype(np.float64), np.abs(B[A.col_idx[ps]]).astype(np.float64))
-    assert_within(dv[ps], exact, bound, TOL_F32, "dvals sampled")
+    ref_dB, M_dB = oracle.spmm(srp, sci, v[perm[idx]], G)
+    # dvals: the entries of sampled rows of A, from the oracle's pattern SDDMM
+    rows = np.unique(np.concatenate([synth.randint(400, A.m, 4), np.argsort(A.row_lengths())[-3:]]))
+    rrp, rci, ridx = sub_rows(A, rows)
+    ref_dv, M_dv = oracle.sddmm(rrp, rci, None, G[rows], B)
+    for plan, dplan in ((spk.Plan(0, 32, 0), spk.Plan(1, 32, 256)), (learned_bwd, learned_dv), (None, None)):
+        dB, dv = spk.spmm_backward(dA, Bd, Gd, plan=plan, dvals_plan=dplan)
+        torch.cuda.synchronize()
+        assert_within(dB[torch.from_numpy(cols).cuda()].cpu().numpy(), ref_dB, M_dB, TOL_F32, f"dB sampled {plan}")
+        assert_within(dv[torch.from_numpy(ridx).cuda()].cpu().numpy(), ref_dv, M_dv, TOL_F32,
+                      f"dvals sampled {dplan}")
 
 
-def test_autograd_function(spk):
+@pytest.mark.parametrize("fwd,bwd,dvp", [(None, None, None), ((4, 16, 0, 4), (4, 16, 0), (4, 16, 0, 4)),
+                                          ((2, 64, 0), None, (1, 16, 256)), ((1, 16, 0), (1, 16, 0), None)])
+def test_autograd_function(spk, fwd, bwd, dvp):
+    """Forward on any SpMM plan (TILE, 4x4 blocks, merge-path), backward on
+    the plans given for A^T and for the pattern SDDMM (NULL by default)."""
     A, v, B, G = gcn_layer(n=8000, mean=16, K=64, seed=3)
     dA = spk.CSR.from_host(A)
+    plan, bplan, dplan = (None if a is None else spk.Plan(*a) for a in (fwd, bwd, dvp))
     vt = dev(v).requires_grad_(True)
     Bt = dev(B).requires_grad_(True)
-    C = spk.spmm_autograd(dA, vt, Bt)
+    C = spk.spmm_autograd(dA, vt, Bt, plan=plan, backward_plan=bplan, dvals_plan=dplan)
+    C64, CM = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    assert_within(C.detach().cpu().numpy(), C64, CM, TOL_F32, f"autograd forward {plan}")
     C.backward(dev(G))
     dB64, dBM, dv64, dvM = oracle.spmm_backward(A.row_ptr, A.col_idx, v, B, G, A.n)
     assert_within(Bt.grad.cpu().numpy(), dB64, dBM, TOL_F32, "autograd dB")
     assert_within(vt.grad.cpu().numpy(), dv64, dvM, TOL_F32, "autograd dvals")
     # only one input needing a gradient
     vt2 = dev(v).requires_grad_(True)
-    spk.spmm_autograd(dA, vt2, dev(B)).sum().backward()
+    spk.spmm_autograd(dA, vt2, dev(B), plan=plan).sum().backward()
     assert vt2.grad is not None
+    with pytest.raises(ValueError):
+        spk.spmm_autograd(dA, vt2, dev(B), backward_plan=spk.Plan(2, 64, 0))
+
+
+def test_bsr4_plan_sees_new_values(spk):
+    """The block form cached on a matrix follows its values: a new values
+    tensor (here very likely at the freed tensor's address) and an in-place
+    update both rebuild it."""
+    A = synth.block4(2048, 2048, 0.02, 4)
+    B = synth.normal((2048, 64), 4, synth.S_B)
+    dA = spk.CSR.from_host(A)
+    Bd = dev(B)
+    plan = spk.Plan(2, 64, 0)
+    for seed in (10, 11, 12):
+        v = synth.normal(A.nnz, seed, synth.S_VALS)
+        vt = dev(v)
+        C = spk.spmm(dA, Bd, plan=plan, vals=vt).cpu().numpy()
+        C64, CM = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+        assert_within(C, C64, CM, TOL_F32, f"bsr4 values seed {seed}")
+        vt.mul_(2.0)
+        C = spk.spmm(dA, Bd, plan=plan, vals=vt).cpu().numpy()
+        assert_within(C, 2 * C64, 2 * CM, TOL_F32, f"bsr4 values seed {seed} doubled in place")
+        del vt, C
+    # values held by the matrix itself
+    v = synth.normal(A.nnz, 13, synth.S_VALS)
+    dV = dA.with_vals(dev(v))
+    C64, CM = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    assert_within(spk.spmm(dV, Bd, plan=plan).cpu().numpy(), C64, CM, TOL_F32, "bsr4 matrix values")
 
 
 def ego_subgraph(A, vals, B, rows):

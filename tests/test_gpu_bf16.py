@@ -44,7 +44,8 @@ def powerlaw_bf16(n, mean, K, seed):
     return A, v, B, U
 
 
-@pytest.mark.parametrize("K,plans", [(256, [None, (1, 64, 0), (0, 32, 0), (3, 32, 0), (4, 64, 0), (4, 64, 33)]),
+@pytest.mark.parametrize("K,plans", [(256, [None, (1, 64, 0), (1, 32, 0), (0, 32, 0), (3, 32, 0), (4, 64, 0),
+                                            (4, 64, 33)]),
                                      (64, [None, (1, 8, 0), (0, 16, 0), (4, 16, 0), (4, 16, 5, 2), (4, 16, 0, 4),
                                            (4, 16, 7, 6)]),
                                      (128, [(4, 32, 0, 4), (4, 32, 9, 6)]),  # one entry per quad, 256-byte rows
@@ -75,7 +76,7 @@ def test_sddmm_bf16(spk, K):
     tl = K // 4  # TILE plans: default and odd slab widths, 4 or 8 rows per group
     # flags bit 2: one entry per quad (two-element BF16 dot products) at K = 64 and 128
     quad = [spk.Plan(4, 16, 0, 4), spk.Plan(4, 16, 11, 6)]  # rows of 128, 256 and 512 bytes
-    for plan in [None, spk.Plan(1, 16, 256), spk.Plan(0, 32), spk.Plan(3, 16, 0), spk.Plan(4, tl, 0),
+    for plan in [None, spk.Plan(1, 16, 256), spk.Plan(1, 64, 256), spk.Plan(0, 32), spk.Plan(3, 16, 0), spk.Plan(4, tl, 0),
                  spk.Plan(4, tl, 9, 2)] + quad:
         S = spk.sddmm(dA, Ut, Vt, plan=plan).cpu().numpy()
         assert_within(S, S_r, M_r, TOL_F32, f"bf16 sddmm rounded {plan}")
@@ -85,26 +86,35 @@ def test_sddmm_bf16(spk, K):
 
 
 def test_bf16_full_size_sampled(spk):
-    """n = 2^20, mean degree 32, K = 256: sampled rows of C and entries of S."""
+    """n = 2^20, mean degree 32, K = 256: sampled rows of C and the entries of
+    sampled rows of S, against the oracle on the rounded operands, on the
+    plans the bench line of this workload runs (merge-path SpMM at 32 lanes,
+    the 8-wide BF16 instantiation; merge-path SDDMM at 64 lanes and 256
+    entries per group: the recorded profile's plans), on the network's five
+    best plans timed once, and on the NULL plans."""
+    from paper_2604_27985_amd import selector
+
     n, K = 1 << 20, 256
     A, v, B32, U32 = powerlaw_bf16(n, 32, K, 0)
     V32 = B32  # V and B share the draw: the products use them independently
     Bt, Br = bf16_dev(B32)
     Ut, Ur = bf16_dev(U32)
     dA = spk.CSR.from_host(A, v)
-    C = spk.spmm(dA, Bt, plan=spk.Plan(1, 64, 0))
-    S = spk.sddmm(dA, Ut, Bt)
-    torch.cuda.synchronize()
     rows = np.unique(np.concatenate([synth.randint(400, n, 7), np.argsort(A.row_lengths())[-3:]]))
     srp, sci, idx = sub_rows(A, rows)
     C_r, M_r = oracle.spmm(srp, sci, v[idx], Br)
-    assert_within(C[torch.from_numpy(rows).cuda()].cpu().numpy(), C_r, M_r, TOL_F32, "bf16 full C")
-    # at most 20000 entries of those rows for the SDDMM check
-    pick = np.sort(np.random.default_rng(8).choice(len(idx), min(len(idx), 20000), replace=False))
-    ent_rows = np.repeat(rows, A.row_lengths()[rows])[pick]
-    U_rows = Ur[ent_rows].astype(np.float64)
-    V_rows = Br[sci[pick]].astype(np.float64)
-    exact = (U_rows * V_rows).sum(1) * v[idx[pick]]
-    bound = (np.abs(U_rows) * np.abs(V_rows)).sum(1) * v[idx[pick]]
-    got = S[torch.from_numpy(idx[pick]).cuda()].cpu().numpy()
-    assert_within(got, exact, bound, TOL_F32, "bf16 full S")
+    S_r, SM_r = oracle.sddmm(srp, sci, v[idx], Ur[rows], Br)
+    r = torch.from_numpy(rows).cuda()
+    e = torch.from_numpy(idx).cuda()
+    spmm_plans = [spk.Plan(1, 32, 0), selector.select(dA, K, spk.OP_SPMM, verify=5, B=Bt), spk.Plan(1, 64, 0), None]
+    sddmm_plans = [spk.Plan(1, 64, 256), selector.select(dA, K, spk.OP_SDDMM, verify=5, U=Ut, V=Bt), None]
+    for plan in spmm_plans:
+        C = spk.spmm(dA, Bt, plan=plan)
+        assert_within(C[r].cpu().numpy(), C_r, M_r, TOL_F32, f"bf16 full C {plan}")
+        del C
+    for plan in sddmm_plans:
+        S = spk.sddmm(dA, Ut, Bt, plan=plan)
+        assert_within(S[e].cpu().numpy(), S_r, SM_r, TOL_F32, f"bf16 full S {plan}")
+        del S
+    del dA, Bt, Ut
+    torch.cuda.empty_cache()
