@@ -167,6 +167,22 @@ int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, 
                  void *C, int64_t ldc, const spk_plan *plan, void *ws, size_t ws_bytes,
                  void *stream);
 
+/* SpMM as spmm_csr, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): no
+ * workspace argument, and nothing is allocated by the call.  Plans that need
+ * scratch (MERGE, SLAB) use the library's own device array of
+ * spmm_csr_noalloc_max_bytes() bytes (64 MiB), one per GPU, kept until the
+ * process ends.  A call whose plan needs more than that returns
+ * SPK_ERR_WORKSPACE before launching anything.  Every call on one GPU shares
+ * that GPU's array, so calls that overlap on one GPU (other streams, other
+ * threads) race: serialise them.  Results are those of spmm_csr on the same
+ * arguments (the same kernels). */
+int32_t spmm_csr_noalloc(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K,
+                         void *C, int64_t ldc, const spk_plan *plan, void *stream);
+
+/* Size in bytes of spmm_csr_noalloc's per-GPU scratch array. */
+size_t spmm_csr_noalloc_max_bytes(void);
+
 /* SDDMM, Eq. (2):  S[p] = a_p * <U[row(p), :], V[col(p), :]> for every stored
  * entry p (a_p = 1 when A->vals is NULL: the pattern-only form used by the
  * backward).

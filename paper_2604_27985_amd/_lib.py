@@ -60,6 +60,8 @@ SIGNATURES = {
     "spk_workspace_bytes": ([_I32, _CSR_P, _I64, _PLAN_P], _SZ),
     "spk_strerror": ([_I32], ctypes.c_char_p),
     "spmm_csr": ([_CSR_P, _P, _I64, _I32, _I64, _P, _I64, _PLAN_P, _P, _SZ, _P], _I32),
+    "spmm_csr_noalloc": ([_CSR_P, _P, _I64, _I32, _I64, _P, _I64, _PLAN_P, _P], _I32),
+    "spmm_csr_noalloc_max_bytes": ([], _SZ),
     "sddmm_csr": ([_CSR_P, _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P, _SZ, _P], _I32),
     "csr_transpose": ([_CSR_P, _P, _P, _P, _P, _SZ, _P], _I32),
     "spmm_csr_backward": ([_CSR_P, _P, _P, _P, _P, _I64, _P, _I64, _I32, _I64, _P, _I64, _P, _PLAN_P, _PLAN_P,

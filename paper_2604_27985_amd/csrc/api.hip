@@ -2,6 +2,8 @@
 // dispatch to the HIP kernels.  Nothing here allocates device memory.
 #include <stdint.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "internal.h"
 
@@ -294,8 +296,37 @@ int32_t spmm_bsr4(const spk_bsr4 *A, const void *B, int64_t ldb, int32_t b_dtype
     return hip_status(bsr4_spmm_launch(a, s));
 }
 
-int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C, int64_t ldc,
-                 const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Scratch of the allocation-free SpMM entry point: a file-scope device array,
+// one copy per GPU, held until the process ends.  Host code never uses the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];
+
+int32_t scratch_of_current_device(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return SPK_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SPK_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPK_OK;
+}
+
+// spmm_csr's body; with from_scratch the workspace is this device's scratch
+// array (sizes beyond it are refused before anything is launched).
+int32_t spmm_common(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C, int64_t ldc,
+                    const spk_plan *plan, void *ws, size_t ws_bytes, bool from_scratch, hipStream_t s) {
     int32_t st = check_csr(A);
     if (st) return st;
     if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
@@ -303,17 +334,41 @@ int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, 
     if (A->m == 0 || K == 0) return SPK_OK;
     if (!C || (A->nnz > 0 && !B)) return SPK_ERR_NULL;
     if (ldc < K || (A->nnz > 0 && ldb < K)) return SPK_ERR_LD;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const int32_t out_dt = b_dtype == SPK_F64 ? SPK_F64 : SPK_F32;
     if (A->nnz == 0) return hip_status(zero_fill(C, A->m, K, ldc, out_dt, s));
     Resolved r;
     if ((st = resolve_spmm(plan, K, b_dtype, B, ldb, C, ldc, r))) return st;
     const size_t need = spmm_ws(A->m, A->n, A->nnz, K, b_dtype, r, false);
+    if (from_scratch) {
+        if (need > kNoAllocScratchBytes) return SPK_ERR_WORKSPACE;
+        ws = nullptr;
+        ws_bytes = 0;
+        if (need > 0) {
+            if ((st = scratch_of_current_device(&ws))) return st;
+            ws_bytes = kNoAllocScratchBytes;
+        }
+    }
     if ((st = check_ws(need, ws, ws_bytes))) return st;
     SpmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, nullptr, B, ldb, b_dtype, C, ldc,
                r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group, r.quad_split};
     return hip_status(spmm_launch(a, s));
 }
+
+}  // namespace
+
+extern "C" {
+
+int32_t spmm_csr(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C, int64_t ldc,
+                 const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+    return spmm_common(A, B, ldb, b_dtype, K, C, ldc, plan, ws, ws_bytes, false, static_cast<hipStream_t>(stream));
+}
+
+int32_t spmm_csr_noalloc(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C,
+                         int64_t ldc, const spk_plan *plan, void *stream) {
+    return spmm_common(A, B, ldb, b_dtype, K, C, ldc, plan, nullptr, 0, true, static_cast<hipStream_t>(stream));
+}
+
+size_t spmm_csr_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
 
 int32_t sddmm_csr(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv, int32_t uv_dtype,
                   int64_t K, void *S, const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {

@@ -145,3 +145,17 @@ def test_workspace_sizes(lib):
     assert nb >= groups * 64 * 4 + 2 * groups * 4
     assert lib.spk_workspace_bytes(9, ctypes.byref(A), 64, None) == 0
     assert lib.spk_strerror(-5).decode().startswith("workspace")
+
+
+def test_noalloc_argument_errors(lib):
+    """The allocation-free SpMM runs spmm_csr's O(1) checks before touching
+    the device; its scratch size is stated."""
+    na = lib.spmm_csr_noalloc
+    assert na(None, FAKE, 16, 0, 16, FAKE, 16, None, None) == -1
+    A = csr()
+    assert na(ctypes.byref(A), FAKE, 16, 0, 16, FAKE, 8, None, None) == -4
+    assert na(ctypes.byref(A), None, 16, 0, 16, FAKE, 16, None, None) == -1
+    assert na(ctypes.byref(A), FAKE, 16, 7, 16, FAKE, 16, None, None) == -3
+    bad = _lib.spk_plan(1, 5, 0, 0)
+    assert na(ctypes.byref(A), FAKE, 16, 0, 16, FAKE, 16, ctypes.byref(bad), None) == -6
+    assert lib.spmm_csr_noalloc_max_bytes() == 64 << 20
