@@ -209,6 +209,7 @@ def profile_summary(args):
             "| kernel | part | dispatches | FETCH KiB | WRITE KiB | scaled HBM bytes |", "|---|---|---|---|---|---|"]
     for short, part, n, f, w, sc in rows[:14]:
         out.append(f"| {short} | {part} | {n} | {f:.0f} | {w:.0f} | {'-' if sc is None else f'{sc:.4g}'} |")
+    out += _counter_tables(d)
     if line["config"]["ops"] == "spmm+sddmm":
         out += ["", "Per step (scaled bytes of a part's kernels over the steps run), read by bench.py while the",
                 "kernel sources keep the digest above:", "", "```"]
@@ -221,6 +222,59 @@ def profile_summary(args):
     with open(args.out, "w") as fh:
         fh.write("\n".join(out))
     print("\n".join(out))
+
+
+def _counter_medians(d):
+    """{kernel: {counter: median per dispatch}} of one counter pass under d."""
+    import numpy as np
+
+    vals = {}
+    for r in _read_csv(_find(d, "counter_collection.csv")):
+        key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+        vals.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], {}).setdefault(key, 0.0)
+        vals[r["Kernel_Name"]][r["Counter_Name"]][key] += float(r["Counter_Value"])
+    return {k: {c: float(np.median(list(v.values()))) for c, v in cs.items()} for k, cs in vals.items()}
+
+
+def _counter_tables(d):
+    """Optional passes: sq/ (LDS bank conflicts and instruction mix) and tcc/
+    (L2-to-fabric read requests by size, which FETCH_SIZE weighs)."""
+    out = []
+    sq_dir, tcc_dir = os.path.join(d, "sq"), os.path.join(d, "tcc")
+    if os.path.isdir(sq_dir):
+        med = _counter_medians(sq_dir)
+        out += ["", "## LDS bank conflicts and instruction mix (SQ counters, median per dispatch)", "",
+                "conflict ratio = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE (the stalled share of the cycles the "
+                "LDS serves indexed reads and writes).  waves/SIMD = SQ_WAVE_CYCLES / (8 SQ_BUSY_CYCLES): the mean "
+                "number of resident waves, with SQ_WAVE_CYCLES counted in 4-cycle units over all waves and "
+                "SQ_BUSY_CYCLES summed over the 32 shader engines of 1024 SIMDs.", "",
+                "| kernel | SQ_LDS_BANK_CONFLICT | SQ_LDS_IDX_ACTIVE | conflict ratio | SQ_INSTS_LDS | "
+                "SQ_INSTS_VALU | SQ_WAIT_INST_LDS | SQ_WAVES | SQ_WAVE_CYCLES | SQ_BUSY_CYCLES | waves/SIMD |",
+                "|---|---|---|---|---|---|---|---|---|---|---|"]
+        for k, c in sorted(med.items(), key=lambda kv: -kv[1].get("SQ_WAVE_CYCLES", 0.0)):
+            if "copy" in k.lower() or "elementwise" in k:
+                continue
+            g = lambda n: c.get(n, float("nan"))  # noqa: E731
+            ratio = g("SQ_LDS_BANK_CONFLICT") / g("SQ_LDS_IDX_ACTIVE") if g("SQ_LDS_IDX_ACTIVE") else float("nan")
+            out.append(f"| {_part_of(k)[1]} | {g('SQ_LDS_BANK_CONFLICT'):.3g} | {g('SQ_LDS_IDX_ACTIVE'):.3g} | "
+                       f"{ratio:.3f} | {g('SQ_INSTS_LDS'):.3g} | {g('SQ_INSTS_VALU'):.3g} | "
+                       f"{g('SQ_WAIT_INST_LDS'):.3g} | {g('SQ_WAVES'):.3g} | {g('SQ_WAVE_CYCLES'):.3g} | "
+                       f"{g('SQ_BUSY_CYCLES'):.3g} | {g('SQ_WAVE_CYCLES') / (8 * g('SQ_BUSY_CYCLES')):.2f} |")
+    if os.path.isdir(tcc_dir):
+        med = _counter_medians(tcc_dir)
+        out += ["", "## Read-request sizes behind FETCH_SIZE (TCC counters, median per dispatch)", "",
+                "FETCH_SIZE weighs TCC_BUBBLE requests as 128 B, TCC_EA0_RDREQ_32B as 32 B and the rest as 64 B. "
+                "The calibration factor measured on the device copy holds for a kernel whose requests split the "
+                "same way.", "",
+                "| kernel | TCC_EA0_RDREQ | 32 B share | TCC_BUBBLE share | other (64 B) share |", "|---|---|---|---|---|"]
+        for k, c in sorted(med.items(), key=lambda kv: -kv[1].get("TCC_EA0_RDREQ_sum", 0.0)):
+            tot = c.get("TCC_EA0_RDREQ_sum", 0.0)
+            if tot <= 0:
+                continue
+            r32 = c.get("TCC_EA0_RDREQ_32B_sum", 0.0) / tot
+            rb = c.get("TCC_BUBBLE_sum", 0.0) / tot
+            out.append(f"| {_part_of(k)[1]} | {tot:.4g} | {r32:.3f} | {rb:.3f} | {1 - r32 - rb:.3f} |")
+    return out
 
 
 def recorded_traffic(workload, part, plan):
