@@ -67,6 +67,8 @@ def _load():
     lib.oracle_adam.restype = None
     lib.oracle_selector_inputs.argtypes = [vp, i64, vp]
     lib.oracle_selector_inputs.restype = None
+    lib.oracle_csr_to_slab16.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp]
+    lib.oracle_csr_to_slab16.restype = i64
     lib.oracle_csr_canonical.argtypes = [i64, i64, i64, vp, vp]
     lib.oracle_csr_canonical.restype = ctypes.c_int32
     _lib = lib
@@ -146,6 +148,20 @@ def spmm_backward(row_ptr, col_idx, vals, B, G, n: int):
     dB, dBM = spmm_t(row_ptr, col_idx, vals, G, n)
     dv, dvM = sddmm(row_ptr, col_idx, None, G, B)
     return dB, dBM, dv, dvM
+
+
+def csr_to_slab16(row_ptr, col_idx, n: int, width: int):
+    """Slab-major form with 16-bit slab-relative columns: (seg[S m + 1],
+    apos[S m], col16[nnz] uint16, S); see oracle.c."""
+    lib = _load()
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    m = rp.shape[0] - 1
+    S = int(lib.oracle_csr_to_slab16(m, n, width, _p(rp), _p(ci), None, None, None))
+    seg = np.empty(S * m + 1, np.int32)
+    apos = np.empty(S * m, np.int32)
+    col16 = np.empty(ci.shape[0], np.uint16)
+    lib.oracle_csr_to_slab16(m, n, width, _p(rp), _p(ci), _p(seg), _p(apos), _p(col16))
+    return seg, apos, col16, S
 
 
 # Rules of canonical CSR (bit values of csr_canonical's result).

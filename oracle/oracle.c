@@ -136,6 +136,48 @@ void oracle_spmm_t(int64_t m, int64_t n, int64_t K, const int32_t *row_ptr,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Column-slab form with 16-bit slab-relative column indices (the paper    */
+/* sends a column as a 16-bit offset inside the range a worker row holds,  */
+/* Section III-A, and groups nonzeros by the worker that owns their column */
+/* range in its SELLPACK-like format, Optimization 1).  Columns are cut    */
+/* into S = max(1, ceil(n / W)) slabs of W <= 65536 columns.  The entries  */
+/* of slab s are stored together (slab-major), row by row; row i's entries */
+/* in slab s are the run of A's row whose columns lie in [s W, (s+1) W),   */
+/* a contiguous run of A's storage since rows are sorted.                  */
+/*   seg[s m + i]   position (slab-major) of the run of (slab s, row i);   */
+/*                  seg[S m] = nnz, so the run ends at seg[s m + i + 1]     */
+/*   apos[s m + i]  position in A of the run's first entry (where it would  */
+/*                  start when empty)                                       */
+/*   col16[q]       column minus s W of the run's entries, in order         */
+/* Values stay in A's array: entry k of run (s, i) has value               */
+/* vals[apos[s m + i] + k].  row_ptr must start at 0 and be canonical.      */
+/* Returns S; pass NULL outputs to ask for S alone.                        */
+/* ---------------------------------------------------------------------- */
+int64_t oracle_csr_to_slab16(int64_t m, int64_t n, int64_t W, const int32_t *row_ptr,
+                             const int32_t *col_idx, int32_t *seg, int32_t *apos,
+                             uint16_t *col16) {
+    int64_t S = n > 0 ? (n + W - 1) / W : 1;
+    if (!seg) return S;
+    int64_t q = 0;
+    for (int64_t s = 0; s < S; ++s) {
+        for (int64_t i = 0; i < m; ++i) {
+            /* first entry of row i with column >= s W, by a scan of the row */
+            int64_t p = row_ptr[i];
+            while (p < row_ptr[i + 1] && col_idx[p] < s * W) ++p;
+            seg[s * m + i] = (int32_t)q;
+            apos[s * m + i] = (int32_t)p;
+            while (p < row_ptr[i + 1] && col_idx[p] < (s + 1) * W) {
+                col16[q] = (uint16_t)(col_idx[p] - s * W);
+                ++q;
+                ++p;
+            }
+        }
+    }
+    seg[S * m] = (int32_t)q;
+    return S;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Canonical CSR, the input form every product assumes (the paper sends    */
 /* CSR with 32-bit column indices, Section III-A, and is silent on order   */
 /* and duplicates; the reading taken here is the usual canonical form).    */

@@ -371,3 +371,48 @@ def test_csr_canonical_against_scipy_and_single_mutations(seed):
                 assert not M.has_canonical_format
         M = sp.csr_matrix((np.ones(A.nnz), A.col_idx, A.row_ptr), shape=(A.m, A.n))
         assert M.has_canonical_format
+
+
+# ---------------------------------------------------------------- slab16 form
+def test_slab16_hand_examples(golden):
+    g = golden["spmm"]
+    for c in golden["slab16"]["cases"]:
+        seg, apos, col16, S = oracle.csr_to_slab16(g["row_ptr"], g["col_idx"], g["n"], c["width"])
+        assert S == c["slabs"]
+        assert seg.tolist() == c["seg"] and apos.tolist() == c["apos"] and col16.tolist() == c["col16"], c["width"]
+
+
+def _slab16_rebuild(seg, apos, col16, S, m, W):
+    """Rows of A rebuilt from the slab form: runs in slab order, columns s W + col16."""
+    rows = [[] for _ in range(m)]
+    positions = [[] for _ in range(m)]
+    for s in range(S):
+        for i in range(m):
+            a, b = int(seg[s * m + i]), int(seg[s * m + i + 1])
+            rows[i] += [s * W + int(c) for c in col16[a:b]]
+            positions[i] += list(range(int(apos[s * m + i]), int(apos[s * m + i]) + b - a))
+    return rows, positions
+
+
+@pytest.mark.parametrize("kind,m,n,W", [("uniform", 300, 1000, 128), ("uniform", 50, 70000, 65536),
+                                        ("powerlaw", 2000, 2000, 100), ("uniform", 40, 30, 1),
+                                        ("uniform", 64, 64, 64), ("empty", 9, 17, 4)])
+def test_slab16_reconstructs_csr(kind, m, n, W):
+    """The runs of every row, read slab by slab, give back the row's columns
+    in order and at the positions apos names; every run lies inside its slab
+    and 16-bit offsets stay below W."""
+    if kind == "powerlaw":
+        A = synth.powerlaw(n, 8, 2.1, 3)
+    elif kind == "empty":
+        A = synth.HostCSR(m, n, np.zeros(m + 1, np.int32), np.zeros(0, np.int32))
+    else:
+        A = synth.bernoulli(m, n, 0.05, 2)
+    seg, apos, col16, S = oracle.csr_to_slab16(A.row_ptr, A.col_idx, A.n, W)
+    assert S == max(1, -(-A.n // W))
+    assert seg[0] == 0 and seg[-1] == A.nnz and np.all(np.diff(seg.astype(np.int64)) >= 0)
+    assert np.all(col16.astype(np.int64) < W)
+    rows, positions = _slab16_rebuild(seg, apos, col16, S, A.m, W)
+    for i in range(A.m):
+        lo, hi = A.row_ptr[i], A.row_ptr[i + 1]
+        assert rows[i] == A.col_idx[lo:hi].tolist()
+        assert positions[i] == list(range(lo, hi))
