@@ -93,7 +93,7 @@ enum spk_variant {
     SPK_VAR_SLAB = 3,  /* row-split over column slabs: one launch per slab
                           of `chunk` columns, so the slab of the dense operand
                           being gathered stays in L2 */
-    SPK_VAR_TILE = 4   /* SpMM: a workgroup owns (256 / lanes) x 4 (or 8)
+    SPK_VAR_TILE = 4,  /* SpMM: a workgroup owns (256 / lanes) x 4 (or 8)
                           rows and stages each slab of `chunk` rows of B in
                           LDS once, so every staged row serves all of the
                           workgroup's entries in it.  F32 or BF16 operands
@@ -114,6 +114,9 @@ enum spk_variant {
                           (the lanes field is then not used; rows of 512
                           bytes keep 4 rows per group); other shapes run the
                           split above. */
+    SPK_VAR_SLAB16 = 5 /* the column-slab form with 16-bit columns
+                          (spmm_slab16 / sddmm_slab16 only): row-split over
+                          the slabs of the form, one launch per slab */
 };
 
 /* An execution plan: plain data, owned by the caller.
@@ -250,6 +253,54 @@ int32_t csr_to_bsr4_fill(const spk_csr *A, const int32_t *b_row_ptr, int32_t *b_
  * zeros add nothing. */
 int32_t spmm_bsr4(const spk_bsr4 *A, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C,
                   int64_t ldc, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Column-slab form with 16-bit slab-relative column indices.  The paper's
+ * host sends a nonzero's column as a 16-bit offset inside the column range of
+ * the worker row that owns it, and packs nonzeros by owner (Section III-A,
+ * Optimization 1; footprint in Section IV-B).  Here the owners are slabs of
+ * `width` columns: a product runs one launch per slab (as SPK_VAR_SLAB), reads
+ * 2 bytes of column per entry instead of 4, and needs no per-call search
+ * for the slab boundaries.  Built once per pattern on the GPU; values stay in
+ * A's own array (the form stores where each run starts in it), so new values
+ * need no rebuild.
+ * ------------------------------------------------------------------------ */
+typedef struct spk_slab16 {
+    int64_t m, n, nnz;      /* A's shape and entry count */
+    int64_t width;          /* W: columns per slab, 1..65536 */
+    int64_t nslabs;         /* S = ceil(n / W), at least 1; S * m < 2^31 - 1 */
+    const int32_t *seg;     /* device, S*m + 1: slab-major start of run (s, i)
+                               (row i's entries with columns in [sW, (s+1)W));
+                               seg[S*m] = nnz */
+    const int32_t *apos;    /* device, S*m: position in A of run (s, i)'s first
+                               entry (where it would start when empty) */
+    const uint16_t *col16;  /* device, nnz: column - s W, slab-major */
+} spk_slab16;
+
+/* Scratch bytes of csr_to_slab16 for A and this width (0 for bad arguments). */
+size_t slab16_workspace_bytes(const spk_csr *A, int64_t width);
+
+/* Build the form of A's pattern (A canonical): seg (device, S*m + 1), apos
+ * (device, S*m) and col16 (device, nnz), caller-allocated.  The result is
+ * unique.  ws: slab16_workspace_bytes(A, width) bytes.  SPK_ERR_SIZE when
+ * width is outside 1..65536 or S*m >= 2^31 - 1. */
+int32_t csr_to_slab16(const spk_csr *A, int64_t width, int32_t *seg, int32_t *apos, uint16_t *col16, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* SpMM (Eq. 1) on the form: C = A B with A's values vals (device, nnz F32 in
+ * A's storage order; NULL = pattern, every entry 1).  B F32 or BF16 [n x K],
+ * C F32 [m x K], as in spmm_csr.  plan NULL or SPK_VAR_SLAB16 with lanes 4..64
+ * and flags bit 0 (scalar loads).  Slab 0 writes C, later slabs add their
+ * runs (a row's partial sums are added in slab order: deterministic). */
+int32_t spmm_slab16(const spk_slab16 *F, const void *vals, const void *B, int64_t ldb, int32_t b_dtype,
+                    int64_t K, void *C, int64_t ldc, const spk_plan *plan, void *stream);
+
+/* SDDMM (Eq. 2) on the form: S[p] = a_p <U[row(p)], V[col(p)]> for every
+ * stored entry p, written at p's position in A (S device, nnz F32).  U, V F32
+ * or BF16 as in sddmm_csr; plan as for spmm_slab16 (at most 8 register
+ * slices of lanes * 4 columns). */
+int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64_t ldu, const void *V,
+                     int64_t ldv, int32_t uv_dtype, int64_t K, void *S, const spk_plan *plan, void *stream);
 
 /* ------------------------------------------------------------------------
  * Learned plan selection.  Not in the paper: the paper's kernels expose

@@ -16,7 +16,7 @@ F32, BF16, F64 = 0, 1, 2
 # enum spk_op
 OP_SPMM, OP_SDDMM, OP_BACKWARD, OP_TRANSPOSE, OP_BSR4, OP_SELECT = 0, 1, 2, 3, 4, 5
 # enum spk_variant
-VAR_ROWS, VAR_MERGE, VAR_BSR4, VAR_SLAB = 0, 1, 2, 3
+VAR_ROWS, VAR_MERGE, VAR_BSR4, VAR_SLAB, VAR_TILE, VAR_SLAB16 = 0, 1, 2, 3, 4, 5
 
 STATUS = {
     0: "SPK_OK", -1: "SPK_ERR_NULL", -2: "SPK_ERR_SIZE", -3: "SPK_ERR_DTYPE", -4: "SPK_ERR_LD",
@@ -42,6 +42,12 @@ class spk_plan(ctypes.Structure):
 class spk_bsr4(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nblocks", ctypes.c_int64),
                 ("b_row_ptr", ctypes.c_void_p), ("b_col", ctypes.c_void_p), ("b_vals", ctypes.c_void_p)]
+
+
+class spk_slab16(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("width", ctypes.c_int64),
+                ("nslabs", ctypes.c_int64), ("seg", ctypes.c_void_p), ("apos", ctypes.c_void_p),
+                ("col16", ctypes.c_void_p)]
 
 
 class SpkError(RuntimeError):
@@ -70,6 +76,10 @@ SIGNATURES = {
     "csr_to_bsr4_count": ([_CSR_P, _P, ctypes.POINTER(ctypes.c_int64), _P, _SZ, _P], _I32),
     "csr_to_bsr4_fill": ([_CSR_P, _P, _P, _P, _P], _I32),
     "spmm_bsr4": ([ctypes.POINTER(spk_bsr4), _P, _I64, _I32, _I64, _P, _I64, _P], _I32),
+    "slab16_workspace_bytes": ([_CSR_P, _I64], _SZ),
+    "csr_to_slab16": ([_CSR_P, _I64, _P, _P, _P, _P, _SZ, _P], _I32),
+    "spmm_slab16": ([ctypes.POINTER(spk_slab16), _P, _P, _I64, _I32, _I64, _P, _I64, _PLAN_P, _P], _I32),
+    "sddmm_slab16": ([ctypes.POINTER(spk_slab16), _P, _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P], _I32),
     "plan_count": ([_I32], _I32),
     "plan_of_index": ([_I32, _I32, _I64, _PLAN_P, ctypes.POINTER(_I32)], _I32),
     "csr_features": ([_CSR_P, _P, _P, _SZ, _P], _I32),

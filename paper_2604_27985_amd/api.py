@@ -31,7 +31,7 @@ class Plan:
         return _lib.spk_plan(self.variant, self.lanes, self.chunk, self.flags)
 
     def name(self) -> str:
-        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4", VAR_SLAB: "slab", 4: "tile"}[self.variant]
+        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4", VAR_SLAB: "slab", 4: "tile", 5: "slab16"}[self.variant]
         s = f"{v}/l{self.lanes}"
         if self.chunk:
             s += f"/c{self.chunk}"
@@ -43,7 +43,7 @@ class Plan:
     def from_name(cls, name: str) -> "Plan":
         """Inverse of name(): "tile/l16/c64/f6" and the like."""
         parts = name.split("/")
-        v = {"rows": VAR_ROWS, "merge": VAR_MERGE, "bsr4": 2, "slab": VAR_SLAB, "tile": 4}[parts[0]]
+        v = {"rows": VAR_ROWS, "merge": VAR_MERGE, "bsr4": 2, "slab": VAR_SLAB, "tile": 4, "slab16": 5}[parts[0]]
         fields = {p[0]: int(p[1:]) for p in parts[1:]}
         return cls(v, fields.get("l", 16), fields.get("c", 0), fields.get("f", 0))
 
@@ -315,6 +315,93 @@ def spmm_bsr4(Ab: BSR4, B: torch.Tensor, out: torch.Tensor | None = None) -> tor
     _lib.check(lib.spmm_bsr4(ctypes.byref(cb), _ptr(B), B.stride(0), _DT[B.dtype], K, _ptr(C), C.stride(0),
                              _stream()), "spmm_bsr4")
     return C
+
+
+@dataclass
+class Slab16:
+    """Column-slab form with 16-bit slab-relative columns (device arrays).
+
+    seg[S m + 1] run starts (slab-major), apos[S m] A positions of the runs,
+    col16[nnz] column offsets (uint16 bits held in an int16 tensor)."""
+
+    seg: torch.Tensor
+    apos: torch.Tensor
+    col16: torch.Tensor
+    shape: tuple
+    nnz: int
+    width: int
+    nslabs: int
+
+    def c(self) -> _lib.spk_slab16:
+        return _lib.spk_slab16(int(self.shape[0]), int(self.shape[1]), self.nnz, self.width, self.nslabs,
+                               self.seg.data_ptr(), self.apos.data_ptr() if self.apos.numel() else None,
+                               self.col16.data_ptr() if self.nnz else None)
+
+    def nbytes(self) -> int:
+        """Bytes of the pattern form (values are A's own array)."""
+        return 4 * self.seg.numel() + 4 * self.apos.numel() + 2 * self.col16.numel()
+
+
+def csr_to_slab16(A: CSR, width: int) -> Slab16:
+    """Build the slab form of A's pattern on the GPU (once per pattern)."""
+    lib = _lib.load()
+    _require_device(A.row_ptr)
+    dev = A.row_ptr.device
+    S = max(1, -(-A.n // width)) if width > 0 else 0
+    seg = torch.empty(S * A.m + 1, dtype=torch.int32, device=dev)
+    apos = torch.empty(S * A.m, dtype=torch.int32, device=dev)
+    col16 = torch.empty(A.nnz, dtype=torch.int16, device=dev)
+    ca = A.c(use_vals=False)
+    nb = int(lib.slab16_workspace_bytes(ctypes.byref(ca), width))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    _lib.check(lib.csr_to_slab16(ctypes.byref(ca), width, _ptr(seg), _ptr(apos) if apos.numel() else None,
+                                 _ptr(col16) if A.nnz else None, _ptr(ws), nb, _stream()), "csr_to_slab16")
+    return Slab16(seg, apos, col16, A.shape, A.nnz, width, S)
+
+
+def _slab16_plan(plan: Plan | None):
+    if plan is not None and plan.variant != _lib.VAR_SLAB16:
+        raise ValueError("slab16 products take SLAB16 plans (variant 5) or None")
+    return plan.c() if plan is not None else None
+
+
+def spmm_slab16(F: Slab16, B: torch.Tensor, vals: torch.Tensor | None, plan: Plan | None = None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A B on the slab form; vals: A's values in A's storage order (None: pattern)."""
+    lib = _lib.load()
+    _require_device(F.seg, B)
+    _rowmajor(B, "B")
+    if B.shape[0] != F.shape[1] or B.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("B must be [n, K] float32 or bfloat16")
+    if vals is not None and (vals.dtype != torch.float32 or not vals.is_contiguous() or vals.numel() != F.nnz):
+        raise ValueError("vals must be a contiguous float32 tensor with nnz entries")
+    K = int(B.shape[1])
+    C = out if out is not None else torch.empty((F.shape[0], K), dtype=torch.float32, device=B.device)
+    _rowmajor(C, "C")
+    cf, cp = F.c(), _slab16_plan(plan)
+    _lib.check(lib.spmm_slab16(ctypes.byref(cf), _ptr(vals), _ptr(B), B.stride(0), _DT[B.dtype], K, _ptr(C),
+                               C.stride(0), ctypes.byref(cp) if cp else None, _stream()), "spmm_slab16")
+    return C
+
+
+def sddmm_slab16(F: Slab16, U: torch.Tensor, V: torch.Tensor, vals: torch.Tensor | None, plan: Plan | None = None,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """S[p] = a_p <U[row p], V[col p]> on the slab form, in A's storage order (vals None: a_p = 1)."""
+    lib = _lib.load()
+    _require_device(F.seg, U, V)
+    _rowmajor(U, "U")
+    _rowmajor(V, "V")
+    if U.shape[0] != F.shape[0] or V.shape[0] != F.shape[1] or U.shape[1] != V.shape[1] or U.dtype != V.dtype:
+        raise ValueError("U must be [m, K] and V [n, K] of one dtype")
+    if vals is not None and (vals.dtype != torch.float32 or not vals.is_contiguous() or vals.numel() != F.nnz):
+        raise ValueError("vals must be a contiguous float32 tensor with nnz entries")
+    K = int(U.shape[1])
+    S = out if out is not None else torch.empty(F.nnz, dtype=torch.float32, device=U.device)
+    cf, cp = F.c(), _slab16_plan(plan)
+    _lib.check(lib.sddmm_slab16(ctypes.byref(cf), _ptr(vals), _ptr(U), U.stride(0), _ptr(V), V.stride(0),
+                                _DT[U.dtype], K, _ptr(S), ctypes.byref(cp) if cp else None, _stream()),
+               "sddmm_slab16")
+    return S
 
 
 def validate_rules(A: CSR) -> int:

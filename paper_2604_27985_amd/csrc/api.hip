@@ -439,6 +439,100 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
     return SPK_OK;
 }
 
+// ---------------------------------------------------------------- slab16
+}  // extern "C"
+
+namespace {
+
+int64_t slab16_slabs(int64_t n, int64_t width) { return n > 0 ? (n + width - 1) / width : 1; }
+
+int32_t check_slab16(const spk_slab16 *F) {
+    if (!F) return SPK_ERR_NULL;
+    if (F->m < 0 || F->n < 0 || F->nnz < 0 || F->m > kMaxIndex || F->n > kMaxIndex || F->nnz > kMaxIndex)
+        return SPK_ERR_SIZE;
+    if (F->width < 1 || F->width > 65536 || F->nslabs != slab16_slabs(F->n, F->width)) return SPK_ERR_SIZE;
+    if (F->nslabs * F->m >= kMaxIndex) return SPK_ERR_SIZE;
+    if (F->m > 0 && (!F->seg || !F->apos)) return SPK_ERR_NULL;
+    if (F->nnz > 0 && !F->col16) return SPK_ERR_NULL;
+    return SPK_OK;
+}
+
+// A plan for the row-split code path of the slab form (lanes and flags).
+int32_t slab16_plan(const spk_plan *plan, spk_plan &out) {
+    if (plan && plan->variant != SPK_VAR_SLAB16) return SPK_ERR_PLAN;
+    out = plan ? spk_plan{SPK_VAR_ROWS, plan->lanes, 0, plan->flags} : spk_plan{SPK_VAR_ROWS, 0, 0, 0};
+    return SPK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t slab16_workspace_bytes(const spk_csr *A, int64_t width) {
+    if (check_csr(A) != SPK_OK || width < 1 || width > 65536) return 0;
+    const int64_t S = slab16_slabs(A->n, width);
+    if (S * A->m >= kMaxIndex) return 0;
+    return slab16_ws_bytes(A->m, S);
+}
+
+int32_t csr_to_slab16(const spk_csr *A, int64_t width, int32_t *seg, int32_t *apos, uint16_t *col16, void *ws,
+                      size_t ws_bytes, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (width < 1 || width > 65536) return SPK_ERR_SIZE;
+    const int64_t S = slab16_slabs(A->n, width);
+    if (S * A->m >= kMaxIndex) return SPK_ERR_SIZE;
+    if (!seg || (A->m > 0 && !apos) || (A->nnz > 0 && !col16)) return SPK_ERR_NULL;
+    if ((st = check_ws(slab16_ws_bytes(A->m, S), ws, ws_bytes))) return st;
+    return hip_status(slab16_build_launch(A->m, A->nnz, A->row_ptr, A->col_idx, width, S, seg, apos, col16, ws,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+int32_t spmm_slab16(const spk_slab16 *F, const void *vals, const void *B, int64_t ldb, int32_t b_dtype, int64_t K,
+                    void *C, int64_t ldc, const spk_plan *plan, void *stream) {
+    int32_t st = check_slab16(F);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (b_dtype != SPK_F32 && b_dtype != SPK_BF16) return SPK_ERR_DTYPE;
+    if (F->m == 0 || K == 0) return SPK_OK;
+    if (!C || (F->nnz > 0 && !B)) return SPK_ERR_NULL;
+    if (ldc < K || (F->nnz > 0 && ldb < K)) return SPK_ERR_LD;
+    spk_plan p;
+    if ((st = slab16_plan(plan, p))) return st;
+    if (!plan) p.lanes = default_spmm_lanes(K);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (F->nnz == 0) return hip_status(zero_fill(C, F->m, K, ldc, SPK_F32, s));
+    Resolved r;
+    if ((st = resolve_spmm(&p, K, b_dtype, B, ldb, C, ldc, r))) return st;
+    SpmmArgs a{F->m, F->n, F->nnz, K, nullptr, nullptr, vals, nullptr, B, ldb, b_dtype, C, ldc,
+               SPK_VAR_SLAB16, r.lanes, r.vec, F->width, nullptr};
+    a.s16 = Slab16View{F->seg, F->apos, F->col16, F->width, F->nslabs};
+    return hip_status(spmm_launch(a, s));
+}
+
+int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64_t ldu, const void *V, int64_t ldv,
+                     int32_t uv_dtype, int64_t K, void *S, const spk_plan *plan, void *stream) {
+    int32_t st = check_slab16(F);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (uv_dtype != SPK_F32 && uv_dtype != SPK_BF16) return SPK_ERR_DTYPE;
+    if (F->nnz == 0) return SPK_OK;
+    if (!S || !U || !V) return SPK_ERR_NULL;
+    if (K > 0 && (ldu < K || ldv < K)) return SPK_ERR_LD;
+    spk_plan p;
+    if ((st = slab16_plan(plan, p))) return st;
+    if (!plan) {  // the default SDDMM group: 8 lanes, widened until K fits 8 register slices of 4 columns
+        p.lanes = 8;
+        while (p.lanes < 64 && (K + p.lanes * 4 - 1) / (p.lanes * 4) > 8) p.lanes <<= 1;
+    }
+    Resolved r;
+    if ((st = resolve_sddmm(&p, K, uv_dtype, U, ldu, V, ldv, r))) return st;
+    SddmmArgs a{F->m, F->n, F->nnz, K, nullptr, nullptr, vals, U, ldu, V, ldv, uv_dtype, S,
+                SPK_VAR_SLAB16, r.lanes, r.vec, F->width, nullptr};
+    a.s16 = Slab16View{F->seg, F->apos, F->col16, F->width, F->nslabs};
+    return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
+}
+
 // ---------------------------------------------------------------- selector
 static constexpr int kMaxDevices = 64;
 static int32_t g_loaded[kMaxDevices][2];

@@ -12,6 +12,13 @@ namespace spk {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// The column-slab form with 16-bit slab-relative columns (slab16.hip).
+struct Slab16View {
+    const int32_t *seg = nullptr, *apos = nullptr;
+    const uint16_t *col16 = nullptr;
+    int64_t width = 0, nslabs = 0;
+};
+
 struct SpmmArgs {
     int64_t m, n, nnz, K;
     const int32_t *rp, *ci;
@@ -27,6 +34,7 @@ struct SpmmArgs {
     void *ws;
     int32_t rows_per_group = 4;  // TILE: rows each lane group owns (4 or 8)
     int32_t quad_split = 0;      // TILE: one entry per 4-lane quad, 16-lane groups
+    Slab16View s16{};            // SLAB16: the column-slab form (ci unused)
 };
 
 struct SddmmArgs {
@@ -44,6 +52,7 @@ struct SddmmArgs {
     void *ws;
     int32_t rows_per_group = 4;  // TILE: rows each lane group owns (4 or 8)
     int32_t quad_split = 0;      // TILE: one entry per 4-lane quad, 16-lane groups
+    Slab16View s16{};            // SLAB16: the column-slab form (ci unused)
 };
 
 // Column slabs of the SLAB variants: nslabs slabs of `width` columns; the
@@ -128,6 +137,12 @@ hipError_t exclusive_scan_i32(int32_t *data, int64_t count, void *ws, hipStream_
 size_t transpose_ws_bytes(int64_t m, int64_t n, int64_t nnz);
 hipError_t transpose_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                             int32_t *trp, int32_t *tci, int32_t *perm, void *ws, hipStream_t s);
+
+// Column-slab form with 16-bit columns (slab16.hip): runs of S slabs of W
+// columns over m rows; the workspace serves the scan of S m + 1 run starts.
+size_t slab16_ws_bytes(int64_t m, int64_t S);
+hipError_t slab16_build_launch(int64_t m, int64_t nnz, const int32_t *rp, const int32_t *ci, int64_t W, int64_t S,
+                               int32_t *seg, int32_t *apos, uint16_t *col16, void *ws, hipStream_t s);
 
 // Structural validation (transpose.hip): writes 0 to *flag_dev when A is
 // canonical, a positive code otherwise.

@@ -137,12 +137,15 @@ struct Step {
     int cnt;
     A vrow[R][NS][VW];
 
-    __device__ __forceinline__ void load(int64_t pb_, int cnt_, const int32_t *__restrict__ ci,
-                                         const TUV *__restrict__ V, int64_t ldv, int K, int gbase, int lig) {
+    // Column of entry p: cbase + ci[p] (CT = uint16_t: the slab form's offsets).
+    template <typename CT>
+    __device__ __forceinline__ void load(int64_t pb_, int cnt_, const CT *__restrict__ ci,
+                                         const TUV *__restrict__ V, int64_t ldv, int K, int gbase, int lig,
+                                         int32_t cbase = 0) {
         pb = pb_;
         cnt = cnt_;
         const int mine = lig < cnt ? lig : cnt - 1;
-        const int c_mine = __builtin_nontemporal_load(ci + pb + mine);
+        const int c_mine = cbase + static_cast<int>(__builtin_nontemporal_load(ci + pb + mine));
         int cc[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) cc[q] = lane_read(c_mine, gbase + q);
@@ -271,6 +274,47 @@ __global__ __launch_bounds__(kBlock) void sddmm_rows_kernel(int64_t m, int K, co
         const bool more = pb < b;
         if (more) st.load(pb, static_cast<int>(b - pb < R ? b - pb : R), ci, V, ldv, K, gbase, lig);
         finish<R, LANES>(pb_cur, cnt_cur, part, vals, S, lig, lane);
+        if (!more) break;
+    }
+}
+
+// SLAB16: group g takes run (s, g) of the column-slab form (slab16.hip): its
+// entries are positions [seg[s m + g], seg[s m + g + 1]) of col16 (columns
+// s W + col16), and entry k sits at A position apos[s m + g] + k, where its
+// value is read and its output written (the runs of a row cover its entries
+// once, so every output is written by one group).
+template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
+__global__ __launch_bounds__(kBlock) void sddmm_s16_kernel(int64_t m, int K, const int32_t *__restrict__ seg,
+                                                           const int32_t *__restrict__ apos,
+                                                           const uint16_t *__restrict__ col16, int s, int32_t cbase,
+                                                           const TV *__restrict__ vals, const TUV *__restrict__ U,
+                                                           int64_t ldu, const TUV *__restrict__ V, int64_t ldv,
+                                                           typename acc_of<TUV>::type *__restrict__ S) {
+    constexpr int GPB = kBlock / LANES;
+    constexpr int R = LANES < 8 ? LANES : 8;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row = blk * GPB + threadIdx.x / LANES;
+    if (row >= m) return;
+    const int64_t run = static_cast<int64_t>(s) * m + row;
+    const int64_t a = seg[run], b = seg[run + 1];
+    if (a >= b) return;
+    const int64_t voff = static_cast<int64_t>(apos[run]) - a;
+    URow<TUV, VW, LANES, NS> ur;
+    ur.load(U, row, ldu, K, lig);
+    Step<TUV, VW, LANES, NS, R, OFF32> st;
+    st.load(a, static_cast<int>(b - a < R ? b - a : R), col16, V, ldv, K, gbase, lig, cbase);
+    while (true) {
+        typename acc_of<TUV>::type part[R];
+        st.dots(ur, part);
+        const int64_t pb_cur = st.pb;
+        const int cnt_cur = st.cnt;
+        const int64_t pb = pb_cur + cnt_cur;
+        const bool more = pb < b;
+        if (more) st.load(pb, static_cast<int>(b - pb < R ? b - pb : R), col16, V, ldv, K, gbase, lig, cbase);
+        finish<R, LANES>(pb_cur + voff, cnt_cur, part, vals, S, lig, lane);
         if (!more) break;
     }
 }
@@ -661,6 +705,20 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
                            static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
                            static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S), a.chunk, ngroups);
         return hipGetLastError();
+    }
+    if (a.variant == SPK_VAR_SLAB16) {
+        const int64_t nb = (a.m + GPB - 1) / GPB;
+        if (nb > 0x7FFFFFFF || a.s16.nslabs < 1) return hipErrorInvalidValue;
+        for (int64_t sl = 0; sl < a.s16.nslabs; ++sl) {
+            hipLaunchKernelGGL((sddmm_s16_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
+                               dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.s16.seg, a.s16.apos, a.s16.col16,
+                               static_cast<int>(sl), static_cast<int32_t>(sl * a.s16.width),
+                               static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
+                               static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S));
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
     int nslabs = 1;
     int64_t width = a.n > 0 ? a.n : 1;

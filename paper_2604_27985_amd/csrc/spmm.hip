@@ -46,13 +46,16 @@ __device__ __forceinline__ const T *elem(const T *base, int32_t row, int64_t ld,
 
 // acc += sum_{p in [a, b)} val(p) * B[col(p), koff .. koff+VW).
 // a, b are uniform over the LANES-lane group; koff is clamped to a valid
-// column for lanes beyond K (their results are never stored).
-template <typename TB, typename TV, int VW, int LANES, bool OFF32>
-__device__ __forceinline__ void accumulate_entries(int64_t a, int64_t b, const int32_t *__restrict__ ci,
+// column for lanes beyond K (their results are never stored).  The column of
+// entry p is cbase + ci[p] (CT = uint16_t: the slab form's 16-bit offsets)
+// and its value vals[p + voff] (or vals[vperm[p]]).
+template <typename TB, typename TV, int VW, int LANES, bool OFF32, typename CT = int32_t>
+__device__ __forceinline__ void accumulate_entries(int64_t a, int64_t b, const CT *__restrict__ ci,
                                                    const TV *__restrict__ vals,
                                                    const int32_t *__restrict__ vperm,
                                                    const TB *__restrict__ B, int64_t ldb, int koff, int gbase,
-                                                   int lig, typename acc_of<TB>::type *acc) {
+                                                   int lig, typename acc_of<TB>::type *acc, int32_t cbase = 0,
+                                                   int64_t voff = 0) {
     using A = typename acc_of<TB>::type;
     constexpr int U = LANES < 8 ? LANES : 8;
     for (int64_t p0 = a; p0 < b; p0 += LANES) {
@@ -60,9 +63,9 @@ __device__ __forceinline__ void accumulate_entries(int64_t a, int64_t b, const i
         int c = 0;
         A v = A(0);
         if (p < b) {
-            c = __builtin_nontemporal_load(ci + p);
+            c = cbase + static_cast<int>(__builtin_nontemporal_load(ci + p));
             if (vals) {
-                const int64_t pv = vperm ? static_cast<int64_t>(__builtin_nontemporal_load(vperm + p)) : p;
+                const int64_t pv = vperm ? static_cast<int64_t>(__builtin_nontemporal_load(vperm + p)) : p + voff;
                 v = static_cast<A>(vals[pv]);
             } else {
                 v = A(1);
@@ -145,6 +148,47 @@ __global__ __launch_bounds__(kBlock) void spmm_slab_kernel(int64_t m, int K, con
     A acc[VW];
     zero<A, VW>(acc);
     accumulate_entries<TB, TV, VW, LANES, OFF32>(a, b, ci, vals, vperm, B, ldb, kvalid ? k0 : 0, gbase, lig, acc);
+    if (kvalid) {
+        A *out = C + row * ldc + k0;
+        if (s > 0) {
+            A prev[VW];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) prev[e] = out[e];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] = prev[e] + acc[e];
+        }
+        vec_store<A, VW>::run(out, acc);
+    }
+}
+
+// Slab s of the column-slab form (slab16.hip): group g takes run (s, g), whose
+// entries are positions [seg[s m + g], seg[s m + g + 1]) of col16 (columns
+// s W + col16) with values at A positions apos[s m + g] onward.  Slab 0 writes
+// C; a later slab adds its run to C, and a row with an empty run there is
+// left alone (no read or write of C).
+template <typename TB, typename TV, int VW, int LANES, bool OFF32>
+__global__ __launch_bounds__(kBlock) void spmm_s16_kernel(int64_t m, int K, const int32_t *__restrict__ seg,
+                                                          const int32_t *__restrict__ apos,
+                                                          const uint16_t *__restrict__ col16, int s, int32_t cbase,
+                                                          const TV *__restrict__ vals, const TB *__restrict__ B,
+                                                          int64_t ldb, typename acc_of<TB>::type *__restrict__ C,
+                                                          int64_t ldc) {
+    using A = typename acc_of<TB>::type;
+    constexpr int GPB = kBlock / LANES;
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = (threadIdx.x & (kWave - 1)) & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t row = blk * GPB + threadIdx.x / LANES;
+    if (row >= m) return;
+    const int64_t run = static_cast<int64_t>(s) * m + row;
+    const int64_t a = seg[run], b = seg[run + 1];
+    if (s > 0 && a == b) return;  // group-uniform
+    const int k0 = blockIdx.y * (LANES * VW) + lig * VW;
+    const bool kvalid = k0 < K;
+    A acc[VW];
+    zero<A, VW>(acc);
+    accumulate_entries<TB, TV, VW, LANES, OFF32, uint16_t>(a, b, col16, vals, nullptr, B, ldb, kvalid ? k0 : 0, gbase,
+                                                           lig, acc, cbase, static_cast<int64_t>(apos[run]) - a);
     if (kvalid) {
         A *out = C + row * ldc + k0;
         if (s > 0) {
@@ -700,6 +744,24 @@ static hipError_t launch_slab(const SpmmArgs &a, hipStream_t s) {
 }
 
 template <typename TB, typename TV, int VW, int LANES, bool OFF32>
+static hipError_t launch_s16(const SpmmArgs &a, hipStream_t s) {
+    constexpr int GPB = kBlock / LANES;
+    const int64_t nb = (a.m + GPB - 1) / GPB;
+    const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
+    if (nb > 0x7FFFFFFF || ktiles > 65535 || a.s16.nslabs < 1) return hipErrorInvalidValue;
+    for (int64_t sl = 0; sl < a.s16.nslabs; ++sl) {
+        hipLaunchKernelGGL((spmm_s16_kernel<TB, TV, VW, LANES, OFF32>),
+                           dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)), dim3(kBlock), 0, s, a.m,
+                           static_cast<int>(a.K), a.s16.seg, a.s16.apos, a.s16.col16, static_cast<int>(sl),
+                           static_cast<int32_t>(sl * a.s16.width), static_cast<const TV *>(a.vals),
+                           static_cast<const TB *>(a.B), a.ldb, static_cast<typename acc_of<TB>::type *>(a.C), a.ldc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename TB, typename TV, int VW, int LANES, bool OFF32>
 static hipError_t launch_merge(const SpmmArgs &a, hipStream_t s) {
     using A = typename acc_of<TB>::type;
     constexpr int GPB = kBlock / LANES;
@@ -788,6 +850,7 @@ static hipError_t dispatch_lanes(const SpmmArgs &a, hipStream_t s) {
         if (a.variant == SPK_VAR_MERGE) return launch_merge<TB, TV, VW, L, OFF32>(a, s); \
         if (a.variant == SPK_VAR_SLAB) return launch_slab<TB, TV, VW, L, OFF32>(a, s);   \
         if (a.variant == SPK_VAR_TILE) return launch_tile<TB, TV, VW, L>(a, s);          \
+        if (a.variant == SPK_VAR_SLAB16) return launch_s16<TB, TV, VW, L, OFF32>(a, s);  \
         return launch_rows<TB, TV, VW, L, OFF32>(a, s);
         SPK_CASE(4)
         SPK_CASE(8)
