@@ -69,6 +69,8 @@ def _load():
     lib.oracle_selector_inputs.restype = None
     lib.oracle_csr_to_slab16.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp]
     lib.oracle_csr_to_slab16.restype = i64
+    lib.oracle_sddmm_softmax_spmm.argtypes = [i64, i64, i64, vp, vp, vp, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, vp]
+    lib.oracle_sddmm_softmax_spmm.restype = None
     lib.oracle_csr_canonical.argtypes = [i64, i64, i64, vp, vp]
     lib.oracle_csr_canonical.restype = ctypes.c_int32
     _lib = lib
@@ -148,6 +150,24 @@ def spmm_backward(row_ptr, col_idx, vals, B, G, n: int):
     dB, dBM = spmm_t(row_ptr, col_idx, vals, G, n)
     dv, dvM = sddmm(row_ptr, col_idx, None, G, B)
     return dB, dBM, dv, dvM
+
+
+def sddmm_softmax_spmm(row_ptr, col_idx, vals, U, V, B):
+    """Attention on A's pattern in FP64: O = softmax_rows(A (.) U V^T) B.
+    Returns (O, bound, escale, lse); see oracle.c."""
+    lib = _load()
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    m = rp.shape[0] - 1
+    U64, V64, B64 = _f64(U), _f64(V), _f64(B)
+    K1, K2 = U64.shape[1], B64.shape[1]
+    O = np.empty((m, K2), np.float64)
+    M = np.empty((m, K2), np.float64)
+    E = np.empty(m, np.float64)
+    L = np.empty(m, np.float64)
+    v64 = _f64(vals)
+    lib.oracle_sddmm_softmax_spmm(m, K1, K2, _p(rp), _p(ci), _p(v64), _p(U64), K1, _p(V64), K1, _p(B64), K2,
+                                  _p(O), K2, _p(M), _p(E), _p(L))
+    return O, M, E, L
 
 
 def csr_to_slab16(row_ptr, col_idx, n: int, width: int):

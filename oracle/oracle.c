@@ -178,6 +178,63 @@ int64_t oracle_csr_to_slab16(int64_t m, int64_t n, int64_t W, const int32_t *row
 }
 
 /* ---------------------------------------------------------------------- */
+/* Back-to-back products with the intermediate kept (the paper's future     */
+/* work on consecutive operations whose result stays resident, Section V):  */
+/* attention on A's pattern, written as its three steps.                    */
+/*   1. S = A (.) (U V^T) on A's pattern (Eq. 2):                           */
+/*        S_p = a_p <U[i,:], V[c_p,:]>         (a_p = 1 when vals == NULL)  */
+/*   2. P = softmax of each row's stored scores:                            */
+/*        P_p = exp(S_p - mx_i) / sum_q exp(S_q - mx_i), mx_i = max of row i */
+/*   3. O = P B (Eq. 1 with P as the values):                               */
+/*        O[i,k] = sum_p P_p B[c_p, k]                                      */
+/* A row with no stored entry has O[i,:] = 0 and lse_i = -inf.              */
+/* Optional outputs:                                                        */
+/*   bound[i,k] = sum_p P_p |B[c_p,k]|          (the scale of O's error)     */
+/*   escale[i]  = max_p |a_p| sum_k |U[i,k]| |V[c_p,k]|  (the scores' scale) */
+/*   lse[i]     = mx_i + log sum_q exp(S_q - mx_i)  (log of the normaliser)  */
+/* ---------------------------------------------------------------------- */
+void oracle_sddmm_softmax_spmm(int64_t m, int64_t K1, int64_t K2, const int32_t *row_ptr,
+                               const int32_t *col_idx, const double *vals, const double *U,
+                               int64_t ldu, const double *V, int64_t ldv, const double *B,
+                               int64_t ldb, double *O, int64_t ldo, double *bound, double *escale,
+                               double *lse) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t a = row_ptr[i], b = row_ptr[i + 1];
+        double *S = (double *)malloc(sizeof(double) * (size_t)(b > a ? b - a : 1));
+        double mx = -INFINITY, emax = 0.0;
+        for (int64_t p = a; p < b; ++p) { /* step 1 */
+            int64_t j = col_idx[p];
+            double dot = 0.0, mag = 0.0;
+            for (int64_t k = 0; k < K1; ++k) {
+                dot += U[i * ldu + k] * V[j * ldv + k];
+                mag += fabs(U[i * ldu + k]) * fabs(V[j * ldv + k]);
+            }
+            double v = vals ? vals[p] : 1.0;
+            S[p - a] = v * dot;
+            if (fabs(v) * mag > emax) emax = fabs(v) * mag;
+            if (S[p - a] > mx) mx = S[p - a];
+        }
+        double sum = 0.0; /* step 2 */
+        for (int64_t p = a; p < b; ++p) sum += exp(S[p - a] - mx);
+        for (int64_t p = a; p < b; ++p) S[p - a] = exp(S[p - a] - mx) / sum;
+        for (int64_t k = 0; k < K2; ++k) { /* step 3 */
+            double acc = 0.0, mag = 0.0;
+            for (int64_t p = a; p < b; ++p) {
+                double bb = B[(int64_t)col_idx[p] * ldb + k];
+                acc += S[p - a] * bb;
+                mag += S[p - a] * fabs(bb);
+            }
+            O[i * ldo + k] = acc;
+            if (bound) bound[i * ldo + k] = mag;
+        }
+        if (escale) escale[i] = emax;
+        if (lse) lse[i] = b > a ? mx + log(sum) : -INFINITY;
+        free(S);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Canonical CSR, the input form every product assumes (the paper sends    */
 /* CSR with 32-bit column indices, Section III-A, and is silent on order   */
 /* and duplicates; the reading taken here is the usual canonical form).    */

@@ -416,3 +416,68 @@ def test_slab16_reconstructs_csr(kind, m, n, W):
         lo, hi = A.row_ptr[i], A.row_ptr[i + 1]
         assert rows[i] == A.col_idx[lo:hi].tolist()
         assert positions[i] == list(range(lo, hi))
+
+
+# ---------------------------------------------------------------- attention chain
+def _dense_attention(A, v, U, V, B):
+    """Masked dense attention with scipy's softmax: scores U V^T times A's
+    values where A stores an entry, -inf elsewhere; empty rows give zeros."""
+    from scipy.special import logsumexp, softmax
+
+    D = dense_of(A.row_ptr, A.col_idx, v, A.m, A.n)
+    mask = dense_of(A.row_ptr, A.col_idx, None, A.m, A.n) > 0
+    scores = np.where(mask, D * (U.astype(np.float64) @ V.astype(np.float64).T), -np.inf)
+    O = np.zeros((A.m, B.shape[1]))
+    lse = np.full(A.m, -np.inf)
+    rows = mask.any(1)
+    if rows.any():
+        O[rows] = softmax(scores[rows], axis=1) @ B.astype(np.float64)
+        lse[rows] = logsumexp(scores[rows], axis=1)
+    return O, lse
+
+
+@pytest.mark.parametrize("m,n,d,K1,K2,seed", [(30, 40, 0.2, 8, 5, 0), (25, 25, 1.0, 4, 4, 1), (40, 17, 0.05, 3, 9, 2),
+                                              (1, 1, 1.0, 2, 2, 3)])
+def test_attention_chain_matches_dense_softmax(m, n, d, K1, K2, seed):
+    A = synth.bernoulli(m, n, d, seed)
+    v = synth.normal(A.nnz, seed, synth.S_VALS)
+    U = synth.normal((m, K1), seed, synth.S_U)
+    V = synth.normal((n, K1), seed, synth.S_V)
+    B = synth.normal((n, K2), seed, synth.S_B)
+    O, M, E, L = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, v, U, V, B)
+    Od, Ld = _dense_attention(A, v, U, V, B)
+    assert np.allclose(O, Od, rtol=1e-12, atol=1e-12)
+    assert np.array_equal(np.isinf(L), np.isinf(Ld)) and np.allclose(L[np.isfinite(L)], Ld[np.isfinite(Ld)], rtol=1e-12)
+    # pattern mode equals values of one
+    O1, _, _, _ = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, None, U, V, B)
+    O1d, _ = _dense_attention(A, np.ones(A.nnz), U, V, B)
+    assert np.allclose(O1, O1d, rtol=1e-12, atol=1e-12)
+    # bound and score scale: brute force from their definitions' pieces
+    S, SM = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
+    for i in range(m):
+        a, b = A.row_ptr[i], A.row_ptr[i + 1]
+        assert E[i] == (SM[a:b].max() if b > a else 0.0)
+
+
+def test_attention_chain_closed_forms():
+    """B of ones gives rows of one (probabilities sum to 1); a one-entry row
+    copies its B row; a zero row of U gives the mean of the row's B rows."""
+    A = synth.bernoulli(50, 60, 0.1, 4)
+    U = synth.normal((50, 6), 4, synth.S_U)
+    V = synth.normal((60, 6), 4, synth.S_V)
+    B = synth.normal((60, 7), 4, synth.S_B)
+    lens = np.diff(A.row_ptr)
+    O, M, _, _ = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, None, U, V, np.ones((60, 3)))
+    assert np.allclose(O[lens > 0], 1.0, rtol=0, atol=1e-14) and not O[lens == 0].any()
+    U0 = U.copy()
+    U0[::2] = 0.0
+    O, M, _, _ = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, None, U0, V, B)
+    for i in range(0, 50, 2):
+        cols = A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]
+        want = B[cols].astype(np.float64).mean(0) if len(cols) else np.zeros(7)
+        assert np.allclose(O[i], want, rtol=1e-13, atol=1e-14)
+    one = synth.HostCSR(2, 60, np.array([0, 1, 1], np.int32), np.array([17], np.int32))
+    O, _, _, L = oracle.sddmm_softmax_spmm(one.row_ptr, one.col_idx, None, U[:2], V, B)
+    assert np.array_equal(O[0], B[17].astype(np.float64)) and not O[1].any()
+    assert np.isclose(L[0], float(U[0].astype(np.float64) @ V[17].astype(np.float64)), rtol=1e-14, atol=0)
+    assert np.isneginf(L[1])
