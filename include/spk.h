@@ -303,6 +303,37 @@ int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64
                      int64_t ldv, int32_t uv_dtype, int64_t K, void *S, const spk_plan *plan, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Back-to-back products with the intermediate kept on chip (the paper's
+ * future work on consecutive operations whose result stays resident,
+ * Section V): attention on A's pattern,
+ *   S = A (.) (U V^T)      scores on A's stored entries (Eq. 2)
+ *   P = softmax of each row's stored scores
+ *   O = P B                (Eq. 1 with the probabilities as values)
+ * ------------------------------------------------------------------------ */
+
+/* The whole chain in one pass: P is never written.  A's values scale the
+ * scores (NULL: pattern, every a_p = 1; F32 only).  U [m x K1], V [n x K1]
+ * and B [n x K2] device, all of dtype (SPK_F32 or SPK_BF16), row-major with
+ * leading dimensions ldu, ldv >= K1 and ldb >= K2 (required whenever K1 or K2
+ * is positive, even when nnz = 0).  O device [m x K2] F32, ldo >= K2, fully
+ * written; a row without stored entries gets zeros.  lse device [m] F32,
+ * nullable: log of each row's normaliser, max + log(sum exp(S - max))
+ * (-inf for an empty row).  plan NULL or SPK_VAR_ROWS with lanes 4..64 per
+ * row and flags bit 0 (scalar loads); at most 8 register slices of lanes * 4
+ * columns of max(K1, K2).  The row's entries are taken in storage order with
+ * an online (rescaled) softmax: deterministic.  Rows of very different
+ * lengths are not balanced (one group per row). */
+int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv,
+                           int64_t K1, const void *B, int64_t ldb, int64_t K2, int32_t dtype, float *O,
+                           int64_t ldo, float *lse, const spk_plan *plan, void *stream);
+
+/* The middle step alone, for the unfused chain (sddmm_csr, this, spmm_csr
+ * with S as values): S (device [nnz] F32, A's storage order) holds scores on
+ * entry and each row's softmax probabilities on return; lse as above
+ * (nullable). */
+int32_t csr_row_softmax(const spk_csr *A, float *S, float *lse, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned plan selection.  Not in the paper: the paper's kernels expose
  * compile-time tile parameters (rows buffered per chunk, columns per worker
  * row, Section III-A and IV-C) chosen by sweeping; here a small network maps

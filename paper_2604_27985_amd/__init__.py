@@ -12,7 +12,7 @@ __all__ = [
     "CSR", "Plan", "spmm", "sddmm", "csr_transpose", "spmm_backward", "spmm_autograd", "validate",
     "validate_rules", "backward_workspace_bytes", "workspace_bytes", "SpkError", "F32", "BF16", "F64", "OP_SPMM", "OP_SDDMM", "OP_BACKWARD", "OP_TRANSPOSE",
     "VAR_ROWS", "VAR_MERGE", "VAR_BSR4", "VAR_SLAB", "VAR_TILE", "VAR_SLAB16", "Slab16", "csr_to_slab16",
-    "spmm_slab16", "sddmm_slab16",
+    "spmm_slab16", "sddmm_slab16", "attention", "attention_unfused", "csr_row_softmax",
 ]
 
 
@@ -21,7 +21,7 @@ def __getattr__(name):
     # can be used without touching torch or the HIP library.
     if name in ("CSR", "Plan", "spmm", "sddmm", "csr_transpose", "spmm_backward", "spmm_autograd", "validate",
                 "validate_rules", "backward_workspace_bytes", "workspace_bytes", "SpMMFunction", "BSR4", "csr_to_bsr4", "spmm_bsr4", "Slab16", "csr_to_slab16", "spmm_slab16",
-                "sddmm_slab16"):
+                "sddmm_slab16", "attention", "attention_unfused", "csr_row_softmax"):
         from . import api
 
         return getattr(api, name)

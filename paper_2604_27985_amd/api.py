@@ -122,6 +122,16 @@ class CSR:
             self._transpose = csr_transpose(self)
         return self._transpose
 
+    def slab16_form(self, width: int) -> "Slab16":
+        """Column-slab form with 16-bit columns at this slab width, built on the
+        GPU once per pattern and width and cached (values are not part of it)."""
+        cache = getattr(self, "_slab16", None)
+        if cache is None:
+            cache = self._slab16 = {}
+        if width not in cache:
+            cache[width] = csr_to_slab16(self, width)
+        return cache[width]
+
     def block_form(self, vals: torch.Tensor | None = None) -> "BSR4":
         """4x4 block form for these values, built on the GPU once and cached.
 
@@ -171,6 +181,11 @@ def spmm(A: CSR, B: torch.Tensor, plan: Plan | None = None, out: torch.Tensor | 
     if plan is not None and plan.variant == _lib.VAR_BSR4:
         # the block form is per-pattern (and per-values) preprocessing, cached on A
         return spmm_bsr4(A.block_form(vals), B, out=C)
+    if plan is not None and plan.variant == _lib.VAR_SLAB16:
+        # the slab form is per-pattern preprocessing, cached on A; values stay A's
+        F = A.slab16_form(slab16_width(plan, K, B.dtype))
+        v = A.vals if vals is None else vals
+        return spmm_slab16(F, B, v, plan=Plan(plan.variant, plan.lanes, 0, plan.flags), out=C)
     ca = A.c(vals)
     cp = plan.c() if plan is not None else None
     ws, nb = (workspace, workspace.numel()) if workspace is not None else _workspace(OP_SPMM, A, K, plan, B.device)
@@ -193,6 +208,10 @@ def sddmm(A: CSR, U: torch.Tensor, V: torch.Tensor, plan: Plan | None = None, ou
     K = int(U.shape[1])
     odt = torch.float64 if U.dtype == torch.float64 else torch.float32
     S = out if out is not None else torch.empty(A.nnz, dtype=odt, device=U.device)
+    if plan is not None and plan.variant == _lib.VAR_SLAB16:
+        F = A.slab16_form(slab16_width(plan, K, U.dtype))
+        v = None if pattern else (A.vals if vals is None else vals)
+        return sddmm_slab16(F, U, V, v, plan=Plan(plan.variant, plan.lanes, 0, plan.flags), out=S)
     ca = A.c(vals, use_vals=not pattern)
     cp = plan.c() if plan is not None else None
     ws, nb = (workspace, workspace.numel()) if workspace is not None else _workspace(OP_SDDMM, A, K, plan, U.device)
@@ -359,6 +378,18 @@ def csr_to_slab16(A: CSR, width: int) -> Slab16:
     return Slab16(seg, apos, col16, A.shape, A.nnz, width, S)
 
 
+def slab16_width(plan: Plan, K: int, dtype: torch.dtype) -> int:
+    """Slab width of a SLAB16 plan: its chunk, else the power of two (>= 256)
+    whose slab of the dense operand takes at most 2 MiB, capped at 65536."""
+    if plan.chunk > 0:
+        return int(plan.chunk)
+    row = max(K, 1) * (2 if dtype == torch.bfloat16 else 4)
+    w = 256
+    while w * 2 * row <= (2 << 20) and w < 65536:
+        w *= 2
+    return w
+
+
 def _slab16_plan(plan: Plan | None):
     if plan is not None and plan.variant != _lib.VAR_SLAB16:
         raise ValueError("slab16 products take SLAB16 plans (variant 5) or None")
@@ -402,6 +433,53 @@ def sddmm_slab16(F: Slab16, U: torch.Tensor, V: torch.Tensor, vals: torch.Tensor
                                 _DT[U.dtype], K, _ptr(S), ctypes.byref(cp) if cp else None, _stream()),
                "sddmm_slab16")
     return S
+
+
+def attention(A: CSR, U: torch.Tensor, V: torch.Tensor, B: torch.Tensor, plan: Plan | None = None,
+              vals: torch.Tensor | None = None, pattern: bool = False, out: torch.Tensor | None = None,
+              with_lse: bool = False):
+    """O = softmax_rows(A (.) U V^T) B in one pass (the probabilities stay on
+    chip).  Returns O, or (O, lse) with with_lse."""
+    lib = _lib.load()
+    _require_device(A.row_ptr, U, V, B)
+    for t, nm in ((U, "U"), (V, "V"), (B, "B")):
+        _rowmajor(t, nm)
+    if U.shape[0] != A.m or V.shape[0] != A.n or B.shape[0] != A.n or U.shape[1] != V.shape[1]:
+        raise ValueError("U must be [m, K1], V [n, K1] and B [n, K2]")
+    if not (U.dtype == V.dtype == B.dtype) or U.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("U, V and B must share dtype float32 or bfloat16")
+    K1, K2 = int(U.shape[1]), int(B.shape[1])
+    O = out if out is not None else torch.empty((A.m, K2), dtype=torch.float32, device=B.device)
+    _rowmajor(O, "O")
+    lse = torch.empty(A.m, dtype=torch.float32, device=B.device) if with_lse else None
+    ca = A.c(vals, use_vals=not pattern)
+    cp = plan.c() if plan is not None else None
+    _lib.check(lib.sddmm_softmax_spmm(ctypes.byref(ca), _ptr(U), U.stride(0), _ptr(V), V.stride(0), K1, _ptr(B),
+                                      B.stride(0), K2, _DT[U.dtype], _ptr(O), O.stride(0), _ptr(lse),
+                                      ctypes.byref(cp) if cp else None, _stream()), "sddmm_softmax_spmm")
+    return (O, lse) if with_lse else O
+
+
+def csr_row_softmax(A: CSR, S: torch.Tensor, with_lse: bool = False):
+    """Row softmax of stored scores S (nnz, A's order) in place; returns S (and lse)."""
+    lib = _lib.load()
+    _require_device(A.row_ptr, S)
+    if S.dtype != torch.float32 or not S.is_contiguous() or S.numel() != A.nnz:
+        raise ValueError("S must be a contiguous float32 tensor with nnz entries")
+    lse = torch.empty(A.m, dtype=torch.float32, device=S.device) if with_lse else None
+    ca = A.c(use_vals=False)
+    _lib.check(lib.csr_row_softmax(ctypes.byref(ca), _ptr(S), _ptr(lse), _stream()), "csr_row_softmax")
+    return (S, lse) if with_lse else S
+
+
+def attention_unfused(A: CSR, U: torch.Tensor, V: torch.Tensor, B: torch.Tensor, sddmm_plan: Plan | None = None,
+                      spmm_plan: Plan | None = None, vals: torch.Tensor | None = None, pattern: bool = False,
+                      S: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The same chain as three launches: sddmm_csr, csr_row_softmax, spmm_csr
+    with the probabilities as values (S is written to and read from HBM)."""
+    S = sddmm(A, U, V, plan=sddmm_plan, vals=vals, pattern=pattern, out=S)
+    csr_row_softmax(A, S)
+    return spmm(A, B, plan=spmm_plan, vals=S, out=out)
 
 
 def validate_rules(A: CSR) -> int:

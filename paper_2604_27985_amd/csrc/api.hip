@@ -533,6 +533,43 @@ int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64
     return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
 }
 
+// ---------------------------------------------------------------- attention chain
+int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv, int64_t K1,
+                           const void *B, int64_t ldb, int64_t K2, int32_t dtype, float *O, int64_t ldo, float *lse,
+                           const spk_plan *plan, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (K1 < 0 || K2 < 0 || K1 > kMaxIndex || K2 > kMaxIndex) return SPK_ERR_SIZE;
+    if (dtype != SPK_F32 && dtype != SPK_BF16) return SPK_ERR_DTYPE;
+    if (A->vals && A->vals_dtype != SPK_F32) return SPK_ERR_DTYPE;
+    if (A->m == 0 || (K2 == 0 && !lse)) return SPK_OK;
+    if ((K2 > 0 && (!O || !B)) || (K1 > 0 && (!U || !V))) return SPK_ERR_NULL;
+    if ((K2 > 0 && (ldo < K2 || ldb < K2)) || (K1 > 0 && (ldu < K1 || ldv < K1))) return SPK_ERR_LD;
+    if (plan && (plan->variant != SPK_VAR_ROWS || !valid_lanes(plan->lanes) || (plan->flags & ~1) || plan->chunk < 0))
+        return SPK_ERR_PLAN;
+    const int64_t kmax = K1 > K2 ? K1 : K2;
+    int32_t lanes = 8;
+    if (plan) lanes = plan->lanes;
+    else
+        while (lanes < 64 && (kmax + lanes * 4 - 1) / (lanes * 4) > 8) lanes <<= 1;
+    const size_t es = elem_size(dtype);
+    const bool v4 = !(plan && (plan->flags & 1)) && K1 % 4 == 0 && K2 % 4 == 0 && ldu % 4 == 0 && ldv % 4 == 0 &&
+                    ldb % 4 == 0 && ldo % 4 == 0 && aligned(U, es * 4) && aligned(V, es * 4) && aligned(B, es * 4) &&
+                    aligned(O, 16);
+    const int32_t vec = v4 ? 4 : 1;
+    if ((kmax + lanes * vec - 1) / (lanes * vec) > 8) return SPK_ERR_PLAN;
+    AttnArgs a{A->m, A->n, A->nnz, K1, K2, A->row_ptr, A->col_idx, static_cast<const float *>(A->vals), U, ldu, V, ldv,
+               B, ldb, dtype, O, ldo, lse, lanes, vec};
+    return hip_status(attn_launch(a, static_cast<hipStream_t>(stream)));
+}
+
+int32_t csr_row_softmax(const spk_csr *A, float *S, float *lse, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (A->nnz > 0 && !S) return SPK_ERR_NULL;
+    return hip_status(row_softmax_launch(A->m, A->row_ptr, S, lse, static_cast<hipStream_t>(stream)));
+}
+
 // ---------------------------------------------------------------- selector
 static constexpr int kMaxDevices = 64;
 static int32_t g_loaded[kMaxDevices][2];

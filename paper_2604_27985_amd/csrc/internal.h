@@ -144,6 +144,27 @@ size_t slab16_ws_bytes(int64_t m, int64_t S);
 hipError_t slab16_build_launch(int64_t m, int64_t nnz, const int32_t *rp, const int32_t *ci, int64_t W, int64_t S,
                                int32_t *seg, int32_t *apos, uint16_t *col16, void *ws, hipStream_t s);
 
+// Attention on A's pattern in one pass (attn.hip): O = softmax_rows(A (.) U V^T) B.
+struct AttnArgs {
+    int64_t m, n, nnz, K1, K2;
+    const int32_t *rp, *ci;
+    const float *vals;  // nullable: every entry 1
+    const void *U;
+    int64_t ldu;
+    const void *V;
+    int64_t ldv;
+    const void *B;
+    int64_t ldb;
+    int32_t dtype;  // of U, V and B: SPK_F32 or SPK_BF16
+    float *O;
+    int64_t ldo;
+    float *lse;  // nullable
+    int32_t lanes, vec;
+};
+hipError_t attn_launch(const AttnArgs &a, hipStream_t s);
+// Row softmax of stored scores in place (the unfused middle step).
+hipError_t row_softmax_launch(int64_t m, const int32_t *rp, float *S, float *lse, hipStream_t s);
+
 // Structural validation (transpose.hip): writes 0 to *flag_dev when A is
 // canonical, a positive code otherwise.
 hipError_t validate_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
