@@ -60,6 +60,7 @@ WORKLOADS = {
     "uniform-n16384-s99.9-K64": (16384, 0.001, 64, "uniform"),
     "uniform-n16384-s99.9-K128": (16384, 0.001, 128, "uniform"),
     "uniform-n1024-s90-K64": (1024, 0.1, 64, "uniform"),
+    "attention-powerlaw-n262144-mean16-K64": (262144, 16, 64, "attention"),
 }
 DEFAULT_WORKLOAD = "uniform-n65536-s90-K128"
 SWEEP = [w for w, v in WORKLOADS.items() if v[3] == "uniform" and v[0] >= 16384]
@@ -94,7 +95,9 @@ PROFILES = os.path.join(ROOT, "profiles")
 # kernels of each part of a step (rocprofv3 names), for attributing counter readings
 PART_KERNELS = {"spmm": ("spmm_", "slab_bounds_kernel", "merge_partition_kernel", "merge_fixup_kernel",
                          "gather_vals_kernel"),
-                "sddmm": ("sddmm_",)}
+                "sddmm": ("sddmm_",),
+                "attention": ("attn_rows_kernel",),
+                "softmax": ("row_softmax_kernel",)}
 
 
 def kernel_source_digest():
@@ -210,11 +213,13 @@ def profile_summary(args):
     for short, part, n, f, w, sc in rows[:14]:
         out.append(f"| {short} | {part} | {n} | {f:.0f} | {w:.0f} | {'-' if sc is None else f'{sc:.4g}'} |")
     out += _counter_tables(d)
-    if line["config"]["ops"] == "spmm+sddmm":
+    if line["config"]["ops"] in ("spmm+sddmm", "attention"):
         out += ["", "Per step (scaled bytes of a part's kernels over the steps run), read by bench.py while the",
                 "kernel sources keep the digest above:", "", "```"]
         for part, b in sorted(part_bytes.items()):
-            plan = line["config"]["plans"].get(part, "?")
+            if part not in line["config"]["plans"]:
+                continue  # kernels of a comparison run, not of the step
+            plan = line["config"]["plans"][part]
             out.append(f"traffic {line['config']['workload']} {part} {plan} {b:.0f} {digest}")
         out += ["```", ""]
     else:  # the backward runs SpMM kernels too: kernel names do not separate the parts
@@ -652,6 +657,168 @@ def run_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def attention_bytes(m, n, nnz, K1, K2, s=4):
+    """Compulsory HBM bytes of the fused chain: row_ptr, (col, val) per entry,
+    U, V and B once, O once; the probabilities never leave the chip."""
+    return 4 * (m + 1) + nnz * 8 + m * K1 * s + n * K1 * s + n * K2 * s + m * K2 * 4
+
+
+def attention_problem(name, seed=0):
+    """GAT-like scores of unit scale: U, V ~ N(0,1) / K^(1/4), values U(0,1)."""
+    from paper_2604_27985_amd import synth
+
+    n, d, K, kind = WORKLOADS[name]
+    p = synth.powerlaw_problem(n, d, K, 2.1, seed)
+    s = float(K) ** -0.25
+    p.U = (p.U * s).astype("float32")
+    p.V = (p.V * s).astype("float32")
+    return p
+
+
+def run_attention(args):
+    """Attention on A's pattern: the fused one-pass kernel timed as the step,
+    the unfused chain (sddmm_csr, csr_row_softmax, spmm_csr) beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2604_27985_amd as spk
+    from paper_2604_27985_amd.api import Plan
+
+    name = args.workload
+    n, d, K, kind = WORKLOADS[name]
+    t0 = time.perf_counter()
+    p = attention_problem(name)
+    gen_s = time.perf_counter() - t0
+    dA = spk.CSR.from_host(p.A, p.vals)
+    U, V, B = (torch.from_numpy(x).cuda() for x in (p.U, p.V, p.B))
+    O = torch.empty((p.A.m, K), dtype=torch.float32, device="cuda")
+    plan = None
+    if args.plans:
+        plan = None if args.plans.split(",")[0] == "plain" else Plan.from_name(args.plans.split(",")[0])
+    elif args.plan != "plain":
+        best = None
+        # a short timed choice among entry-split runs and one group per row
+        cands = [Plan(1, lanes, chunk) for lanes in (8, 16, 32) for chunk in (256, 512)] + \
+                [Plan(0, lanes, 0) for lanes in (8, 16)]
+        for cand in cands:
+            for _ in range(2):
+                spk.attention(dA, U, V, B, plan=cand, out=O)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                spk.attention(dA, U, V, B, plan=cand, out=O)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 5
+            if best is None or t < best[1]:
+                best = (cand, t)
+        plan = best[0]
+
+    nbw = spk.attention_workspace_bytes(dA, K, plan)
+    ws_at = torch.empty(nbw, dtype=torch.uint8, device="cuda") if nbw else None
+
+    class _Step:
+        def first(self):
+            spk.attention(dA, U, V, B, plan=plan, out=O, workspace=ws_at)
+
+        def second(self):
+            pass
+
+    step = _Step()
+    if args.calib_copy:
+        src = torch.ones(args.calib_copy << 28, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
+    total_ms, wall, first_ms, _ = time_steps(step, args.steps, args.warmup)
+    nnz = p.A.nnz
+    ms = float(np.mean(first_ms))
+    flops = 2.0 * nnz * K * 2
+    byts = attention_bytes(p.A.m, p.A.n, nnz, K, K)
+    roof = roofline(byts, flops, ms * 1e-3)
+    roof["kernel"] = "attention"
+    roof["traffic"] = recorded_traffic(name, "attention", plan.name() if plan else "plain")
+    ms_step = total_ms / args.steps
+    out = {
+        "metric": "SpMM/SDDMM GFLOP/s + % HBM roofline; learned-tuned vs plain at 1e-5 rel err",
+        "value": round(flops / (ms_step * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "n": n, "nnz": nnz, "K": K, "pattern": "powerlaw", "mean_degree": d,
+                   "ops": "attention", "plan": "fixed" if args.plans else ("best of 8 timed" if plan else "plain"),
+                   "plans": {"attention": plan.name() if plan else "plain"}},
+        "roofline": roof,
+        "kernels": {"attention": {"ms": round(ms, 4), "ms_median": round(float(np.median(first_ms)), 4),
+                                  "gflops": round(flops / (ms * 1e-3) / 1e9, 1), "alg_bytes": int(byts),
+                                  "hbm_frac": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
+        "host_wall_s": round(wall, 3), "gen_s": round(gen_s, 2),
+    }
+    if not args.no_compare:
+        # the unfused chain: S written by the SDDMM, read and rewritten by the
+        # softmax, read again as the SpMM's values
+        S = torch.empty(nnz, dtype=torch.float32, device="cuda")
+        sp_sddmm, sp_spmm = Plan(1, 8, 256), Plan(1, 16, 0)
+        from paper_2604_27985_amd import _lib
+        import ctypes
+
+        nbs = int(_lib.load().row_softmax_workspace_bytes(ctypes.byref(dA.c(use_vals=False))))
+        ws_sm = torch.empty(max(nbs, 1), dtype=torch.uint8, device="cuda")
+        parts = (lambda: spk.sddmm(dA, U, V, plan=sp_sddmm, out=S),
+                 lambda: spk.csr_row_softmax(dA, S, workspace=ws_sm),
+                 lambda: spk.spmm(dA, B, plan=sp_spmm, vals=S, out=O))
+        for _ in range(args.warmup):
+            for f in parts:
+                f()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        for e in ev:
+            for i, f in enumerate(parts):
+                e[i].record()
+                f()
+            e[3].record()
+        torch.cuda.synchronize()
+        t = [[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in ev]
+        um = [float(np.mean([x[i] for x in t])) for i in range(3)]
+        ub = (sddmm_bytes(p.A.m, p.A.n, nnz, K) + 4 * (p.A.m + 1) + 8 * nnz
+              + spmm_bytes(p.A.m, p.A.n, nnz, K))
+        out["unfused"] = {"ms": round(sum(um), 4), "parts_ms": {"sddmm": round(um[0], 4), "softmax": round(um[1], 4),
+                                                                "spmm": round(um[2], 4)},
+                          "plans": {"sddmm": sp_sddmm.name(), "spmm": sp_spmm.name()}, "alg_bytes": int(ub)}
+        out["speedup_vs_unfused"] = round(sum(um) / ms, 3)
+        del S
+    if not args.no_cpu_baseline:
+        import oracle
+
+        rows = 64
+        while True:  # about args.cpu_budget seconds of the oracle on the first rows
+            t0 = time.perf_counter()
+            oracle.sddmm_softmax_spmm(p.A.row_ptr[:rows + 1], p.A.col_idx, p.vals, p.U, p.V, p.B)
+            dt = time.perf_counter() - t0
+            if dt >= 1.0 or rows >= p.A.m:
+                break
+            rows = min(p.A.m, rows * 4)
+        rows = int(min(p.A.m, max(rows, rows * args.cpu_budget / dt)))
+        t0 = time.perf_counter()
+        O64, M, E, _ = oracle.sddmm_softmax_spmm(p.A.row_ptr[:rows + 1], p.A.col_idx, p.vals, p.U, p.V, p.B)
+        dt = time.perf_counter() - t0
+        spk.attention(dA, U, V, B, plan=plan, out=O)
+        got = O[:rows].cpu().numpy().astype(np.float64)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            err = np.where(M > 0, np.abs(got - O64) / M, np.abs(got - O64))
+        nnz_s = int(p.A.row_ptr[rows])
+        out["cpu_baseline"] = {"value": round(2.0 * nnz_s * K * 2 / dt / 1e9, 3), "unit": "GFLOP/s",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": f"first {rows} of {p.A.m} rows ({nnz_s} entries): the three-step chain in "
+                                         f"FP64, {dt:.1f} s",
+                               "gpu_max_scaled_err": float(err.max(initial=0.0))}
+        gate = 1e-5 + 4 * K * 2.0 ** -24 * float(E.max(initial=0.0))
+        out["parity"] = {"max_scaled_err": float(err.max(initial=0.0)), "gate": gate,
+                         "ok": float(err.max(initial=0.0)) <= gate,
+                         "sample": out["cpu_baseline"]["sample"].split(":")[0]}
+    print(json.dumps(out), flush=True)
+
+
 def run_sweep(args):
     """One record per (workload, op, plan mode) of the n x sparsity x K grid."""
     import numpy as np
@@ -716,6 +883,8 @@ def main():
         sys.exit(1)
     if args.sweep:
         run_sweep(args)
+    elif WORKLOADS[args.workload][3] == "attention":
+        run_attention(args)
     else:
         run_workload(args)
 

@@ -318,20 +318,40 @@ int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64
  * is positive, even when nnz = 0).  O device [m x K2] F32, ldo >= K2, fully
  * written; a row without stored entries gets zeros.  lse device [m] F32,
  * nullable: log of each row's normaliser, max + log(sum exp(S - max))
- * (-inf for an empty row).  plan NULL or SPK_VAR_ROWS with lanes 4..64 per
- * row and flags bit 0 (scalar loads); at most 8 register slices of lanes * 4
- * columns of max(K1, K2).  The row's entries are taken in storage order with
- * an online (rescaled) softmax: deterministic.  Rows of very different
- * lengths are not balanced (one group per row). */
+ * (-inf for an empty row).
+ * plan  NULL or a plan with flags bit 0 (scalar loads) and lanes 4..64 per
+ *       group (at most 8 register slices of lanes * 4 columns of
+ *       max(K1, K2); NULL: 8 lanes, widened as needed):
+ *       SPK_VAR_MERGE (the NULL plan's) - each group takes a run of `chunk`
+ *         entries (0: 512) whatever the rows, so rows of very different
+ *         lengths cost no imbalance; a row cut by a run's ends leaves a
+ *         partial state (maximum, normaliser, K2 sums) that a fix-up
+ *         combines in run order;
+ *       SPK_VAR_ROWS - one group per row (no workspace).
+ *       Each row's entries are taken in storage order with an online
+ *       (rescaled) softmax and fixed reductions: deterministic.
+ * ws    attention_workspace_bytes(A, K2, plan) bytes (MERGE: per run two
+ *       partial states). */
 int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv,
                            int64_t K1, const void *B, int64_t ldb, int64_t K2, int32_t dtype, float *O,
-                           int64_t ldo, float *lse, const spk_plan *plan, void *stream);
+                           int64_t ldo, float *lse, const spk_plan *plan, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Workspace bytes of sddmm_softmax_spmm for A, K2 and plan (0 for ROWS plans
+ * and for bad arguments). */
+size_t attention_workspace_bytes(const spk_csr *A, int64_t K2, const spk_plan *plan);
 
 /* The middle step alone, for the unfused chain (sddmm_csr, this, spmm_csr
  * with S as values): S (device [nnz] F32, A's storage order) holds scores on
  * entry and each row's softmax probabilities on return; lse as above
- * (nullable). */
-int32_t csr_row_softmax(const spk_csr *A, float *S, float *lse, void *stream);
+ * (nullable).  Balanced over runs of entries like the MERGE attention, so a
+ * row of any length costs no imbalance.
+ * ws    row_softmax_workspace_bytes(A) bytes (each row's maximum and
+ *       normaliser, the runs' partial states). */
+int32_t csr_row_softmax(const spk_csr *A, float *S, float *lse, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of csr_row_softmax for A (0 for bad arguments). */
+size_t row_softmax_workspace_bytes(const spk_csr *A);
 
 /* ------------------------------------------------------------------------
  * Learned plan selection.  Not in the paper: the paper's kernels expose

@@ -21,7 +21,7 @@ def __getattr__(name):
     # can be used without touching torch or the HIP library.
     if name in ("CSR", "Plan", "spmm", "sddmm", "csr_transpose", "spmm_backward", "spmm_autograd", "validate",
                 "validate_rules", "backward_workspace_bytes", "workspace_bytes", "SpMMFunction", "BSR4", "csr_to_bsr4", "spmm_bsr4", "Slab16", "csr_to_slab16", "spmm_slab16",
-                "sddmm_slab16", "attention", "attention_unfused", "csr_row_softmax"):
+                "sddmm_slab16", "attention", "attention_unfused", "csr_row_softmax", "attention_workspace_bytes"):
         from . import api
 
         return getattr(api, name)

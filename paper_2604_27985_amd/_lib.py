@@ -80,9 +80,11 @@ SIGNATURES = {
     "csr_to_slab16": ([_CSR_P, _I64, _P, _P, _P, _P, _SZ, _P], _I32),
     "spmm_slab16": ([ctypes.POINTER(spk_slab16), _P, _P, _I64, _I32, _I64, _P, _I64, _PLAN_P, _P], _I32),
     "sddmm_slab16": ([ctypes.POINTER(spk_slab16), _P, _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P], _I32),
-    "sddmm_softmax_spmm": ([_CSR_P, _P, _I64, _P, _I64, _I64, _P, _I64, _I64, _I32, _P, _I64, _P, _PLAN_P, _P],
-                           _I32),
-    "csr_row_softmax": ([_CSR_P, _P, _P, _P], _I32),
+    "sddmm_softmax_spmm": ([_CSR_P, _P, _I64, _P, _I64, _I64, _P, _I64, _I64, _I32, _P, _I64, _P, _PLAN_P, _P, _SZ,
+                            _P], _I32),
+    "attention_workspace_bytes": ([_CSR_P, _I64, _PLAN_P], _SZ),
+    "csr_row_softmax": ([_CSR_P, _P, _P, _P, _SZ, _P], _I32),
+    "row_softmax_workspace_bytes": ([_CSR_P], _SZ),
     "plan_count": ([_I32], _I32),
     "plan_of_index": ([_I32, _I32, _I64, _PLAN_P, ctypes.POINTER(_I32)], _I32),
     "csr_features": ([_CSR_P, _P, _P, _SZ, _P], _I32),

@@ -435,9 +435,16 @@ def sddmm_slab16(F: Slab16, U: torch.Tensor, V: torch.Tensor, vals: torch.Tensor
     return S
 
 
+def attention_workspace_bytes(A: CSR, K2: int, plan: Plan | None = None) -> int:
+    lib = _lib.load()
+    ca = A.c(use_vals=False)
+    cp = plan.c() if plan is not None else None
+    return int(lib.attention_workspace_bytes(ctypes.byref(ca), K2, ctypes.byref(cp) if cp else None))
+
+
 def attention(A: CSR, U: torch.Tensor, V: torch.Tensor, B: torch.Tensor, plan: Plan | None = None,
               vals: torch.Tensor | None = None, pattern: bool = False, out: torch.Tensor | None = None,
-              with_lse: bool = False):
+              with_lse: bool = False, workspace: torch.Tensor | None = None):
     """O = softmax_rows(A (.) U V^T) B in one pass (the probabilities stay on
     chip).  Returns O, or (O, lse) with with_lse."""
     lib = _lib.load()
@@ -454,13 +461,19 @@ def attention(A: CSR, U: torch.Tensor, V: torch.Tensor, B: torch.Tensor, plan: P
     lse = torch.empty(A.m, dtype=torch.float32, device=B.device) if with_lse else None
     ca = A.c(vals, use_vals=not pattern)
     cp = plan.c() if plan is not None else None
+    if workspace is not None:
+        ws, nb = workspace, workspace.numel()
+    else:
+        nb = int(lib.attention_workspace_bytes(ctypes.byref(ca), K2, ctypes.byref(cp) if cp else None))
+        ws = torch.empty(nb, dtype=torch.uint8, device=B.device) if nb else None
     _lib.check(lib.sddmm_softmax_spmm(ctypes.byref(ca), _ptr(U), U.stride(0), _ptr(V), V.stride(0), K1, _ptr(B),
                                       B.stride(0), K2, _DT[U.dtype], _ptr(O), O.stride(0), _ptr(lse),
-                                      ctypes.byref(cp) if cp else None, _stream()), "sddmm_softmax_spmm")
+                                      ctypes.byref(cp) if cp else None, _ptr(ws), nb, _stream()),
+               "sddmm_softmax_spmm")
     return (O, lse) if with_lse else O
 
 
-def csr_row_softmax(A: CSR, S: torch.Tensor, with_lse: bool = False):
+def csr_row_softmax(A: CSR, S: torch.Tensor, with_lse: bool = False, workspace: torch.Tensor | None = None):
     """Row softmax of stored scores S (nnz, A's order) in place; returns S (and lse)."""
     lib = _lib.load()
     _require_device(A.row_ptr, S)
@@ -468,7 +481,12 @@ def csr_row_softmax(A: CSR, S: torch.Tensor, with_lse: bool = False):
         raise ValueError("S must be a contiguous float32 tensor with nnz entries")
     lse = torch.empty(A.m, dtype=torch.float32, device=S.device) if with_lse else None
     ca = A.c(use_vals=False)
-    _lib.check(lib.csr_row_softmax(ctypes.byref(ca), _ptr(S), _ptr(lse), _stream()), "csr_row_softmax")
+    if workspace is not None:
+        ws, nb = workspace, workspace.numel()
+    else:
+        nb = int(lib.row_softmax_workspace_bytes(ctypes.byref(ca)))
+        ws = torch.empty(nb, dtype=torch.uint8, device=S.device) if nb else None
+    _lib.check(lib.csr_row_softmax(ctypes.byref(ca), _ptr(S), _ptr(lse), _ptr(ws), nb, _stream()), "csr_row_softmax")
     return (S, lse) if with_lse else S
 
 

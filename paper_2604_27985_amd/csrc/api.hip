@@ -534,19 +534,45 @@ int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64
 }
 
 // ---------------------------------------------------------------- attention chain
+}  // extern "C"
+
+namespace {
+
+constexpr int64_t kAttnItems = 512;  // entries per run of the entry-split attention
+
+int32_t resolve_attn(const spk_plan *plan, int32_t &variant, int64_t &items) {
+    variant = plan ? plan->variant : SPK_VAR_MERGE;
+    if (variant != SPK_VAR_ROWS && variant != SPK_VAR_MERGE) return SPK_ERR_PLAN;
+    if (plan && (!valid_lanes(plan->lanes) || (plan->flags & ~1) || plan->chunk < 0)) return SPK_ERR_PLAN;
+    items = plan && plan->chunk > 0 ? plan->chunk : kAttnItems;
+    return SPK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t attention_workspace_bytes(const spk_csr *A, int64_t K2, const spk_plan *plan) {
+    int32_t variant;
+    int64_t items;
+    if (check_csr(A) != SPK_OK || K2 < 0 || resolve_attn(plan, variant, items) != SPK_OK) return 0;
+    return variant == SPK_VAR_MERGE ? attn_layout(A->nnz, K2, items).total : 0;
+}
+
 int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv, int64_t K1,
                            const void *B, int64_t ldb, int64_t K2, int32_t dtype, float *O, int64_t ldo, float *lse,
-                           const spk_plan *plan, void *stream) {
+                           const spk_plan *plan, void *ws, size_t ws_bytes, void *stream) {
     int32_t st = check_csr(A);
     if (st) return st;
     if (K1 < 0 || K2 < 0 || K1 > kMaxIndex || K2 > kMaxIndex) return SPK_ERR_SIZE;
     if (dtype != SPK_F32 && dtype != SPK_BF16) return SPK_ERR_DTYPE;
     if (A->vals && A->vals_dtype != SPK_F32) return SPK_ERR_DTYPE;
+    int32_t variant;
+    int64_t items;
+    if ((st = resolve_attn(plan, variant, items))) return st;
     if (A->m == 0 || (K2 == 0 && !lse)) return SPK_OK;
     if ((K2 > 0 && (!O || !B)) || (K1 > 0 && (!U || !V))) return SPK_ERR_NULL;
     if ((K2 > 0 && (ldo < K2 || ldb < K2)) || (K1 > 0 && (ldu < K1 || ldv < K1))) return SPK_ERR_LD;
-    if (plan && (plan->variant != SPK_VAR_ROWS || !valid_lanes(plan->lanes) || (plan->flags & ~1) || plan->chunk < 0))
-        return SPK_ERR_PLAN;
     const int64_t kmax = K1 > K2 ? K1 : K2;
     int32_t lanes = 8;
     if (plan) lanes = plan->lanes;
@@ -558,16 +584,24 @@ int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const v
                     aligned(O, 16);
     const int32_t vec = v4 ? 4 : 1;
     if ((kmax + lanes * vec - 1) / (lanes * vec) > 8) return SPK_ERR_PLAN;
+    if (variant == SPK_VAR_MERGE && (st = check_ws(attn_layout(A->nnz, K2, items).total, ws, ws_bytes))) return st;
     AttnArgs a{A->m, A->n, A->nnz, K1, K2, A->row_ptr, A->col_idx, static_cast<const float *>(A->vals), U, ldu, V, ldv,
-               B, ldb, dtype, O, ldo, lse, lanes, vec};
+               B, ldb, dtype, O, ldo, lse, lanes, vec, variant, items, ws};
     return hip_status(attn_launch(a, static_cast<hipStream_t>(stream)));
 }
 
-int32_t csr_row_softmax(const spk_csr *A, float *S, float *lse, void *stream) {
+size_t row_softmax_workspace_bytes(const spk_csr *A) {
+    if (check_csr(A) != SPK_OK) return 0;
+    return row_softmax_ws_bytes(A->m, A->nnz);
+}
+
+int32_t csr_row_softmax(const spk_csr *A, float *S, float *lse, void *ws, size_t ws_bytes, void *stream) {
     int32_t st = check_csr(A);
     if (st) return st;
     if (A->nnz > 0 && !S) return SPK_ERR_NULL;
-    return hip_status(row_softmax_launch(A->m, A->row_ptr, S, lse, static_cast<hipStream_t>(stream)));
+    if (A->m == 0) return SPK_OK;
+    if ((st = check_ws(row_softmax_ws_bytes(A->m, A->nnz), ws, ws_bytes))) return st;
+    return hip_status(row_softmax_launch(A->m, A->nnz, A->row_ptr, S, lse, ws, static_cast<hipStream_t>(stream)));
 }
 
 // ---------------------------------------------------------------- selector

@@ -44,6 +44,131 @@ __device__ __forceinline__ float allsum(float v, int lane) {
     return v;
 }
 
+// Running softmax state of a run of one row's entries: maximum score mx, sum
+// of exp(score - mx) l, and acc = sum of exp(score - mx) B[col] (this lane's
+// slices of K2 columns).
+template <int NS, int VW>
+struct SoftState {
+    float mx, l;
+    float acc[NS][VW];
+
+    __device__ __forceinline__ void clear() {
+        mx = -INFINITY;
+        l = 0.f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[s][e] = 0.f;
+    }
+};
+
+// The lane's slices of U's row and the clamped column offsets of its slices
+// (lanes past K read column 0, whose products are never used).
+template <typename T, int VW, int LANES, int NS>
+struct RowCtx {
+    float u[NS][VW];
+    int k1[NS], k2[NS];
+
+    __device__ __forceinline__ void load(const T *__restrict__ U, int64_t row, int64_t ldu, int K1, int K2, int lig) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k = s * LANES * VW + lig * VW;
+            if (k < K1) vec_load<T, VW>::run(U + row * ldu + k, u[s]);
+            else
+#pragma unroll
+                for (int e = 0; e < VW; ++e) u[s][e] = 0.f;
+            k1[s] = k < K1 ? k : 0;
+            k2[s] = k < K2 ? k : 0;
+        }
+    }
+};
+
+// Adds entries [pa, pb) of one row to st, R at a time: R rows of V are
+// gathered and dotted with U's row, the dots summed over the group, the
+// state rescaled to the new maximum and R weighted rows of B added.
+template <typename T, int VW, int LANES, int NS>
+__device__ __forceinline__ void soft_run(int64_t pa, int64_t pb, const int32_t *__restrict__ ci,
+                                         const float *__restrict__ vals, const T *__restrict__ V, int64_t ldv,
+                                         const T *__restrict__ B, int64_t ldb, const RowCtx<T, VW, LANES, NS> &rc,
+                                         SoftState<NS, VW> &st, int lig, int gbase, int lane) {
+    constexpr int R = LANES < 8 ? LANES : 8;
+    for (int64_t p0 = pa; p0 < pb; p0 += R) {
+        const int cnt = static_cast<int>(pb - p0 < R ? pb - p0 : R);
+        const int mine = lig < cnt ? lig : cnt - 1;
+        const int c_mine = ci[p0 + mine];
+        const float v_mine = vals ? vals[p0 + mine] : 1.f;
+        int cq[R];
+        float sc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) cq[q] = lane_read(c_mine, gbase + q);
+        // every gather of the step (R rows of V, then R rows of B) is issued
+        // before any of them is used: the B rows are in flight while the
+        // scores are formed
+        float vr[R][NS][VW], br[R][NS][VW];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) vec_load<T, VW>::run(V + static_cast<int64_t>(cq[q]) * ldv + rc.k1[s], vr[q][s]);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) vec_load<T, VW>::run(B + static_cast<int64_t>(cq[q]) * ldb + rc.k2[s], br[q][s]);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float part = 0.f;
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int e = 0; e < VW; ++e) part = fma(rc.u[s][e], vr[q][s][e], part);
+            sc[q] = allsum<LANES>(part, lane) * lane_read(v_mine, gbase + q);
+        }
+        float mstep = sc[0];
+#pragma unroll
+        for (int q = 1; q < R; ++q)
+            if (q < cnt) mstep = fmaxf(mstep, sc[q]);
+        const float mnew = fmaxf(st.mx, mstep);
+        const float scale = __expf(st.mx - mnew);  // 0 while the state is empty (mx = -inf)
+        float w[R];
+        float wsum = 0.f;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            w[q] = q < cnt ? __expf(sc[q] - mnew) : 0.f;
+            wsum += w[q];
+        }
+        st.l = st.l * scale + wsum;
+        st.mx = mnew;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) st.acc[s][e] *= scale;
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int e = 0; e < VW; ++e) st.acc[s][e] = fma(w[q], br[q][s][e], st.acc[s][e]);
+    }
+}
+
+// O's row (acc / l; zeros for a row without entries) and lse.
+template <int VW, int LANES, int NS>
+__device__ __forceinline__ void soft_store(const SoftState<NS, VW> &st, bool any, int64_t row, float *__restrict__ O,
+                                           int64_t ldo, float *__restrict__ lse, int K2, int lig) {
+    const float inv = any ? 1.f / st.l : 0.f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = s * LANES * VW + lig * VW;
+        if (k < K2) {
+            float o[VW];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) o[e] = st.acc[s][e] * inv;
+            vec_store<float, VW>::run(O + row * ldo + k, o);
+        }
+    }
+    if (lse && lig == 0) lse[row] = any ? st.mx + logf(st.l) : -INFINITY;
+}
+
+// ROWS: one group per row.
 template <typename T, int VW, int LANES, int NS>
 __global__ __launch_bounds__(kBlock) void attn_rows_kernel(int64_t m, int K1, int K2, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
@@ -53,104 +178,195 @@ __global__ __launch_bounds__(kBlock) void attn_rows_kernel(int64_t m, int K1, in
                                                            float *__restrict__ O, int64_t ldo,
                                                            float *__restrict__ lse) {
     constexpr int GPB = kBlock / LANES;
-    constexpr int R = LANES < 8 ? LANES : 8;
     const int lane = threadIdx.x & (kWave - 1);
     const int lig = threadIdx.x & (LANES - 1);
     const int gbase = lane & ~(LANES - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t row = blk * GPB + threadIdx.x / LANES;
     if (row >= m) return;
-    // slice s of this lane: columns s * LANES * VW + lig * VW .. + VW
-    float u[NS][VW], acc[NS][VW];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int k = s * LANES * VW + lig * VW;
-        if (k < K1) vec_load<T, VW>::run(U + row * ldu + k, u[s]);
-        else
-#pragma unroll
-            for (int e = 0; e < VW; ++e) u[s][e] = 0.f;
-#pragma unroll
-        for (int e = 0; e < VW; ++e) acc[s][e] = 0.f;
-    }
-    int k1[NS], k2[NS];  // clamped column offsets: lanes past K read column 0 (never used)
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int k = s * LANES * VW + lig * VW;
-        k1[s] = k < K1 ? k : 0;
-        k2[s] = k < K2 ? k : 0;
-    }
-    float mrun = -INFINITY, lrun = 0.f;
+    RowCtx<T, VW, LANES, NS> rc;
+    rc.load(U, row, ldu, K1, K2, lig);
+    SoftState<NS, VW> st;
+    st.clear();
     const int64_t a = rp[row], b = rp[row + 1];
-    for (int64_t pb = a; pb < b; pb += R) {
-        const int cnt = static_cast<int>(b - pb < R ? b - pb : R);
-        const int mine = lig < cnt ? lig : cnt - 1;
-        const int c_mine = ci[pb + mine];
-        const float v_mine = vals ? vals[pb + mine] : 1.f;
-        int cq[R];
-        float sc[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) cq[q] = lane_read(c_mine, gbase + q);
-        // scores: R gathered rows of V against the row of U
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            float part = 0.f;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                float vr[VW];
-                vec_load<T, VW>::run(V + static_cast<int64_t>(cq[q]) * ldv + k1[s], vr);
-#pragma unroll
-                for (int e = 0; e < VW; ++e) part = fma(u[s][e], vr[e], part);
-            }
-            sc[q] = allsum<LANES>(part, lane) * lane_read(v_mine, gbase + q);
+    soft_run<T, VW, LANES, NS>(a, b, ci, vals, V, ldv, B, ldb, rc, st, lig, gbase, lane);
+    soft_store<VW, LANES, NS>(st, b > a, row, O, ldo, lse, K2, lig);
+}
+
+// MERGE: group g takes entries [g*items, (g+1)*items).  A row lying wholly
+// inside the run is finished here.  A row cut by the run's ends leaves a
+// partial state: its first piece in slot 1 of the group, every later piece
+// (the last one, and middle pieces when the row spans several runs) in
+// slot 0.  Slot rows are -1 when unused.  attn_fixup_kernel combines the
+// pieces of every cut row in run order.
+template <typename T, int VW, int LANES, int NS>
+__global__ __launch_bounds__(kBlock) void attn_split_kernel(int64_t m, int64_t nnz, int K1, int K2,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const float *__restrict__ vals, const T *__restrict__ U,
+                                                            int64_t ldu, const T *__restrict__ V, int64_t ldv,
+                                                            const T *__restrict__ B, int64_t ldb,
+                                                            float *__restrict__ O, int64_t ldo,
+                                                            float *__restrict__ lse, int64_t items, int64_t ngroups,
+                                                            int32_t *__restrict__ slot_row,
+                                                            float *__restrict__ slot_ml,
+                                                            float *__restrict__ slot_acc) {
+    constexpr int GPB = kBlock / LANES;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t g = blk * GPB + threadIdx.x / LANES;
+    if (g >= ngroups) return;
+    const int64_t p0 = g * items;
+    const int64_t p1 = p0 + items < nnz ? p0 + items : nnz;
+    int32_t used0 = -1, used1 = -1;
+    // row holding entry p0: largest r with row_ptr[r] <= p0
+    int64_t r = last_at_most(0, m - 1, p0, [&](int64_t i) { return static_cast<int64_t>(rp[i]); });
+    for (; r < m; ++r) {
+        const int64_t ra = rp[r], rb = rp[r + 1];
+        if (ra >= p1) break;
+        const int64_t a = ra > p0 ? ra : p0, b = rb < p1 ? rb : p1;
+        if (a >= b) continue;  // empty row (written by attn_empty_kernel)
+        RowCtx<T, VW, LANES, NS> rc;
+        rc.load(U, r, ldu, K1, K2, lig);
+        SoftState<NS, VW> st;
+        st.clear();
+        soft_run<T, VW, LANES, NS>(a, b, ci, vals, V, ldv, B, ldb, rc, st, lig, gbase, lane);
+        if (ra >= p0 && rb <= p1) {
+            soft_store<VW, LANES, NS>(st, true, r, O, ldo, lse, K2, lig);
+            continue;
         }
-        // online softmax: the accumulated row is rescaled to the new maximum
-        float mstep = sc[0];
-#pragma unroll
-        for (int q = 1; q < R; ++q)
-            if (q < cnt) mstep = fmaxf(mstep, sc[q]);
-        const float mnew = fmaxf(mrun, mstep);
-        const float scale = __expf(mrun - mnew);  // 0 on the first step (mrun = -inf)
-        float w[R];
-        float wsum = 0.f;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            w[q] = q < cnt ? __expf(sc[q] - mnew) : 0.f;
-            wsum += w[q];
+        const int64_t slot = 2 * g + (ra >= p0 ? 1 : 0);  // first piece: slot 1; later pieces: slot 0
+        if (ra >= p0) used1 = static_cast<int32_t>(r);
+        else used0 = static_cast<int32_t>(r);
+        if (lig == 0) {
+            slot_ml[2 * slot] = st.mx;
+            slot_ml[2 * slot + 1] = st.l;
         }
-        lrun = lrun * scale + wsum;
-        mrun = mnew;
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
-#pragma unroll
-            for (int e = 0; e < VW; ++e) acc[s][e] *= scale;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                float br[VW];
-                vec_load<T, VW>::run(B + static_cast<int64_t>(cq[q]) * ldb + k2[s], br);
-#pragma unroll
-                for (int e = 0; e < VW; ++e) acc[s][e] = fma(w[q], br[e], acc[s][e]);
-            }
-        }
-    }
-    const float inv = b > a ? 1.f / lrun : 0.f;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int k = s * LANES * VW + lig * VW;
-        if (k < K2) {
-            float o[VW];
-#pragma unroll
-            for (int e = 0; e < VW; ++e) o[e] = acc[s][e] * inv;
-            vec_store<float, VW>::run(O + row * ldo + k, o);
+        for (int s = 0; s < NS; ++s) {
+            const int k = s * LANES * VW + lig * VW;
+            if (k < K2) vec_store<float, VW>::run(slot_acc + slot * K2 + k, st.acc[s]);
         }
     }
-    if (lse && lig == 0) lse[row] = b > a ? mrun + logf(lrun) : -INFINITY;
+    if (lig == 0) {
+        slot_row[2 * g] = used0;
+        slot_row[2 * g + 1] = used1;
+    }
+}
+
+// One wave per run: a run whose slot 1 holds a row's first piece combines it
+// with the slot-0 pieces of the following runs that carry the same row, in
+// run order (pieces are loaded 8 at a time), and writes the row of O and lse.
+__global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int K2,
+                                                            const int32_t *__restrict__ slot_row,
+                                                            const float *__restrict__ slot_ml,
+                                                            const float *__restrict__ slot_acc,
+                                                            float *__restrict__ O, int64_t ldo,
+                                                            float *__restrict__ lse) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (g >= ngroups) return;
+    const int32_t r = slot_row[2 * g + 1];
+    if (r < 0) return;
+    // the end of the row's run of pieces, 64 runs per probe
+    int64_t h_end = g + 1;
+    for (;;) {
+        const int64_t h = h_end + lane;
+        const uint64_t other = __ballot(!(h < ngroups && slot_row[2 * h] == r));
+        if (other) {
+            h_end += __ffsll(static_cast<long long>(other)) - 1;
+            break;
+        }
+        h_end += kWave;
+    }
+    // Maximum and normaliser over the pieces: piece 0 is slot 1 of run g,
+    // piece t > 0 slot 0 of run g + t.  Lane j combines pieces j, j + 64, ...
+    // in order, then the 64 lane states are combined by a butterfly whose
+    // two partners compute the same (commutative) expression, so every lane
+    // ends with the same bits.
+    const int64_t npieces = h_end - g;
+    float mx = -INFINITY, l = 0.f;
+    for (int64_t t = lane; t < npieces; t += kWave) {
+        const int64_t sl = t == 0 ? 2 * g + 1 : 2 * (g + t);
+        const float m2 = slot_ml[2 * sl], l2 = slot_ml[2 * sl + 1];
+        const float mn = fmaxf(mx, m2);
+        l = l * __expf(mx - mn) + l2 * __expf(m2 - mn);
+        mx = mn;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const float m2 = lane_read(mx, lane ^ d), l2 = lane_read(l, lane ^ d);
+        const float mn = fmaxf(mx, m2);
+        // an empty lane state (mx = -inf, l = 0) adds nothing
+        const float ea = mx == -INFINITY ? 0.f : l * __expf(mx - mn);
+        const float eb = m2 == -INFINITY ? 0.f : l2 * __expf(m2 - mn);
+        l = ea + eb;
+        mx = mn;
+    }
+    const float inv = 1.f / l;
+    constexpr int D = 8;
+    for (int k = lane; k < K2; k += kWave) {
+        float a = slot_acc[(2 * g + 1) * K2 + k] * __expf(slot_ml[2 * (2 * g + 1)] - mx);
+        for (int64_t h = g + 1; h < h_end; h += D) {
+            float v[D], w[D];
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const bool in = h + u < h_end;
+                v[u] = in ? slot_acc[(2 * (h + u)) * K2 + k] : 0.f;
+                w[u] = in ? __expf(slot_ml[2 * (2 * (h + u))] - mx) : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < D; ++u)
+                if (h + u < h_end) a = fma(v[u], w[u], a);  // wave-uniform condition
+        }
+        O[static_cast<int64_t>(r) * ldo + k] = a * inv;
+    }
+    if (lse && lane == 0) lse[r] = mx + logf(l);
+}
+
+// Rows without stored entries: zeros and -inf (the entry-split kernel never
+// visits them).
+__global__ void attn_empty_kernel(int64_t m, int K2, const int32_t *__restrict__ rp, float *__restrict__ O, int64_t ldo,
+                                  float *__restrict__ lse) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= m) return;
+    if (rp[idx] != rp[idx + 1]) return;
+    for (int k = 0; k < K2; ++k) O[idx * ldo + k] = 0.f;
+    if (lse) lse[idx] = -INFINITY;
 }
 
 template <typename T, int VW, int LANES, int NS>
 static hipError_t launch_attn(const AttnArgs &a, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
+    if (a.variant == SPK_VAR_MERGE) {
+        const AttnLayout L = attn_layout(a.nnz, a.K2, a.items);
+        char *ws = static_cast<char *>(a.ws);
+        int32_t *slot_row = reinterpret_cast<int32_t *>(ws + L.row_off);
+        float *slot_ml = reinterpret_cast<float *>(ws + L.ml_off);
+        float *slot_acc = reinterpret_cast<float *>(ws + L.acc_off);
+        if (a.m > 0) {
+            hipLaunchKernelGGL(attn_empty_kernel, dim3(static_cast<unsigned>((a.m + kBlock - 1) / kBlock)), dim3(kBlock),
+                               0, s, a.m, static_cast<int>(a.K2), a.rp, a.O, a.ldo, a.lse);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (L.ngroups == 0) return hipSuccess;
+        const int64_t nb = (L.ngroups + GPB - 1) / GPB;
+        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((attn_split_kernel<T, VW, LANES, NS>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s,
+                           a.m, a.nnz, static_cast<int>(a.K1), static_cast<int>(a.K2), a.rp, a.ci, a.vals,
+                           static_cast<const T *>(a.U), a.ldu, static_cast<const T *>(a.V), a.ldv,
+                           static_cast<const T *>(a.B), a.ldb, a.O, a.ldo, a.lse, L.items, L.ngroups, slot_row,
+                           slot_ml, slot_acc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        constexpr int wpb = kBlock / kWave;
+        hipLaunchKernelGGL(attn_fixup_kernel, dim3(static_cast<unsigned>((L.ngroups + wpb - 1) / wpb)), dim3(kBlock), 0,
+                           s, L.ngroups, static_cast<int>(a.K2), slot_row, slot_ml, slot_acc, a.O, a.ldo, a.lse);
+        return hipGetLastError();
+    }
     const int64_t nb = (a.m + GPB - 1) / GPB;
     if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
     hipLaunchKernelGGL((attn_rows_kernel<T, VW, LANES, NS>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, a.m,
@@ -189,32 +405,163 @@ hipError_t attn_launch(const AttnArgs &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-// Row softmax of stored scores in place: a wave per row, three passes
-// (maximum, sum of exponentials, normalisation), fixed reduction order.
-__global__ __launch_bounds__(kBlock) void row_softmax_kernel(int64_t m, const int32_t *__restrict__ rp,
-                                                             float *__restrict__ S, float *__restrict__ lse) {
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (row >= m) return;
-    const int64_t a = rp[row], b = rp[row + 1];
-    float mx = -INFINITY;
-    for (int64_t p = a + lane; p < b; p += kWave) mx = fmaxf(mx, S[p]);
+// Row softmax of stored scores in place, balanced over entries: one wave per
+// run of `items` entries (the same runs and piece slots as the entry-split
+// attention).  Pass 1 finds each row piece's maximum and sum of exponentials
+// (a row wholly inside the run is finished into rowml), pass 2 combines the
+// pieces of cut rows in run order, pass 3 rewrites every score as its
+// probability.  Reductions use fixed butterflies: deterministic.
+__device__ __forceinline__ float wave_max(float v, int lane) {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) mx = fmaxf(mx, lane_read(mx, lane ^ d));
-    float sum = 0.f;
-    for (int64_t p = a + lane; p < b; p += kWave) sum += __expf(S[p] - mx);
+    for (int d = 1; d < kWave; d <<= 1) v = fmaxf(v, lane_read(v, lane ^ d));
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v, int lane) {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) sum += lane_read(sum, lane ^ d);
-    const float inv = 1.f / sum;
-    for (int64_t p = a + lane; p < b; p += kWave) S[p] = __expf(S[p] - mx) * inv;
-    if (lse && lane == 0) lse[row] = b > a ? mx + logf(sum) : -INFINITY;
+    for (int d = 1; d < kWave; d <<= 1) v += lane_read(v, lane ^ d);
+    return v;
 }
 
-hipError_t row_softmax_launch(int64_t m, const int32_t *rp, float *S, float *lse, hipStream_t s) {
+__global__ __launch_bounds__(kBlock) void softmax_stats_kernel(int64_t m, int64_t nnz, const int32_t *__restrict__ rp,
+                                                               const float *__restrict__ S, int64_t items,
+                                                               int64_t ngroups, float *__restrict__ rowml,
+                                                               int32_t *__restrict__ slot_row,
+                                                               float *__restrict__ slot_ml) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (g >= ngroups) return;
+    const int64_t p0 = g * items;
+    const int64_t p1 = p0 + items < nnz ? p0 + items : nnz;
+    int32_t used0 = -1, used1 = -1;
+    int64_t r = last_at_most(0, m - 1, p0, [&](int64_t i) { return static_cast<int64_t>(rp[i]); });
+    for (; r < m; ++r) {
+        const int64_t ra = rp[r], rb = rp[r + 1];
+        if (ra >= p1) break;
+        const int64_t a = ra > p0 ? ra : p0, b = rb < p1 ? rb : p1;
+        if (a >= b) continue;
+        float mx = -INFINITY;
+        for (int64_t p = a + lane; p < b; p += kWave) mx = fmaxf(mx, S[p]);
+        mx = wave_max(mx, lane);
+        float l = 0.f;
+        for (int64_t p = a + lane; p < b; p += kWave) l += __expf(S[p] - mx);
+        l = wave_sum(l, lane);
+        if (ra >= p0 && rb <= p1) {
+            if (lane == 0) {
+                rowml[2 * r] = mx;
+                rowml[2 * r + 1] = l;
+            }
+            continue;
+        }
+        const int64_t slot = 2 * g + (ra >= p0 ? 1 : 0);
+        if (ra >= p0) used1 = static_cast<int32_t>(r);
+        else used0 = static_cast<int32_t>(r);
+        if (lane == 0) {
+            slot_ml[2 * slot] = mx;
+            slot_ml[2 * slot + 1] = l;
+        }
+    }
+    if (lane == 0) {
+        slot_row[2 * g] = used0;
+        slot_row[2 * g + 1] = used1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void softmax_fixup_kernel(int64_t ngroups, const int32_t *__restrict__ slot_row,
+                                                               const float *__restrict__ slot_ml,
+                                                               float *__restrict__ rowml) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (g >= ngroups) return;
+    const int32_t r = slot_row[2 * g + 1];
+    if (r < 0) return;
+    int64_t h_end = g + 1;
+    for (;;) {
+        const int64_t h = h_end + lane;
+        const uint64_t other = __ballot(!(h < ngroups && slot_row[2 * h] == r));
+        if (other) {
+            h_end += __ffsll(static_cast<long long>(other)) - 1;
+            break;
+        }
+        h_end += kWave;
+    }
+    const int64_t npieces = h_end - g;
+    float mx = -INFINITY, l = 0.f;
+    for (int64_t t = lane; t < npieces; t += kWave) {
+        const int64_t sl = t == 0 ? 2 * g + 1 : 2 * (g + t);
+        const float m2 = slot_ml[2 * sl], l2 = slot_ml[2 * sl + 1];
+        const float mn = fmaxf(mx, m2);
+        l = l * __expf(mx - mn) + l2 * __expf(m2 - mn);
+        mx = mn;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const float m2 = lane_read(mx, lane ^ d), l2 = lane_read(l, lane ^ d);
+        const float mn = fmaxf(mx, m2);
+        const float ea = mx == -INFINITY ? 0.f : l * __expf(mx - mn);
+        const float eb = m2 == -INFINITY ? 0.f : l2 * __expf(m2 - mn);
+        l = ea + eb;
+        mx = mn;
+    }
+    if (lane == 0) {
+        rowml[2 * r] = mx;
+        rowml[2 * r + 1] = l;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void softmax_apply_kernel(int64_t m, int64_t nnz, const int32_t *__restrict__ rp,
+                                                               float *__restrict__ S, int64_t items, int64_t ngroups,
+                                                               const float *__restrict__ rowml,
+                                                               float *__restrict__ lse) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (g >= ngroups) return;
+    const int64_t p0 = g * items;
+    const int64_t p1 = p0 + items < nnz ? p0 + items : nnz;
+    int64_t r = last_at_most(0, m - 1, p0, [&](int64_t i) { return static_cast<int64_t>(rp[i]); });
+    for (; r < m; ++r) {
+        const int64_t ra = rp[r], rb = rp[r + 1];
+        if (ra >= p1) break;
+        const int64_t a = ra > p0 ? ra : p0, b = rb < p1 ? rb : p1;
+        if (a >= b) continue;
+        const float mx = rowml[2 * r], inv = 1.f / rowml[2 * r + 1];
+        for (int64_t p = a + lane; p < b; p += kWave) S[p] = __expf(S[p] - mx) * inv;
+        if (lse && lane == 0 && ra >= p0) lse[r] = mx + logf(rowml[2 * r + 1]);
+    }
+}
+
+__global__ void softmax_empty_kernel(int64_t m, const int32_t *__restrict__ rp, float *__restrict__ lse) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx < m && rp[idx] == rp[idx + 1]) lse[idx] = -INFINITY;
+}
+
+size_t row_softmax_ws_bytes(int64_t m, int64_t nnz) {
+    const AttnLayout L = attn_layout(nnz, 0, kSoftmaxItems);
+    return align_up(sizeof(float) * 2 * static_cast<size_t>(m)) + L.total;
+}
+
+hipError_t row_softmax_launch(int64_t m, int64_t nnz, const int32_t *rp, float *S, float *lse, void *ws_, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    constexpr int rows_per_block = kBlock / kWave;
-    hipLaunchKernelGGL(row_softmax_kernel, dim3(static_cast<unsigned>((m + rows_per_block - 1) / rows_per_block)),
-                       dim3(kBlock), 0, s, m, rp, S, lse);
+    hipError_t e;
+    if (lse) {
+        hipLaunchKernelGGL(softmax_empty_kernel, dim3(static_cast<unsigned>((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           m, rp, lse);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const AttnLayout L = attn_layout(nnz, 0, kSoftmaxItems);
+    if (L.ngroups == 0) return hipSuccess;
+    char *ws = static_cast<char *>(ws_);
+    float *rowml = reinterpret_cast<float *>(ws);
+    char *slots = ws + align_up(sizeof(float) * 2 * static_cast<size_t>(m));
+    int32_t *slot_row = reinterpret_cast<int32_t *>(slots + L.row_off);
+    float *slot_ml = reinterpret_cast<float *>(slots + L.ml_off);
+    constexpr int wpb = kBlock / kWave;
+    const unsigned nb = static_cast<unsigned>((L.ngroups + wpb - 1) / wpb);
+    hipLaunchKernelGGL(softmax_stats_kernel, dim3(nb), dim3(kBlock), 0, s, m, nnz, rp, S, L.items, L.ngroups, rowml,
+                       slot_row, slot_ml);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(softmax_fixup_kernel, dim3(nb), dim3(kBlock), 0, s, L.ngroups, slot_row, slot_ml, rowml);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(softmax_apply_kernel, dim3(nb), dim3(kBlock), 0, s, m, nnz, rp, S, L.items, L.ngroups, rowml, lse);
     return hipGetLastError();
 }
 

@@ -160,10 +160,35 @@ struct AttnArgs {
     int64_t ldo;
     float *lse;  // nullable
     int32_t lanes, vec;
+    int32_t variant = SPK_VAR_ROWS;  // ROWS: a group per row; MERGE: equal runs of entries
+    int64_t items = 0;               // MERGE: entries per run
+    void *ws = nullptr;              // MERGE: the runs' partial states
 };
+
+// Workspace of the entry-split attention: per run two slots (a row id, the
+// running maximum and normaliser, K2 accumulated values).
+struct AttnLayout {
+    int64_t items, ngroups;
+    size_t row_off, ml_off, acc_off, total;
+};
+
+inline AttnLayout attn_layout(int64_t nnz, int64_t K2, int64_t items) {
+    AttnLayout L;
+    L.items = items > 0 ? items : 1;
+    L.ngroups = nnz > 0 ? (nnz + L.items - 1) / L.items : 0;
+    L.row_off = 0;
+    L.ml_off = align_up(sizeof(int32_t) * 2 * static_cast<size_t>(L.ngroups));
+    L.acc_off = L.ml_off + align_up(sizeof(float) * 4 * static_cast<size_t>(L.ngroups));
+    L.total = L.acc_off + align_up(sizeof(float) * 2 * static_cast<size_t>(L.ngroups) * static_cast<size_t>(K2));
+    return L;
+}
 hipError_t attn_launch(const AttnArgs &a, hipStream_t s);
-// Row softmax of stored scores in place (the unfused middle step).
-hipError_t row_softmax_launch(int64_t m, const int32_t *rp, float *S, float *lse, hipStream_t s);
+// Row softmax of stored scores in place (the unfused middle step), balanced
+// over runs of kSoftmaxItems entries; the workspace holds each row's maximum
+// and normaliser and the runs' partial states.
+constexpr int64_t kSoftmaxItems = 1024;
+size_t row_softmax_ws_bytes(int64_t m, int64_t nnz);
+hipError_t row_softmax_launch(int64_t m, int64_t nnz, const int32_t *rp, float *S, float *lse, void *ws, hipStream_t s);
 
 // Structural validation (transpose.hip): writes 0 to *flag_dev when A is
 // canonical, a positive code otherwise.

@@ -72,7 +72,9 @@ def test_attention_matches_oracle(spk, kind, m, n, d, K1, K2):
     ref = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, v, U, V, B)
     dA = spk.CSR.from_host(A, v)
     Ud, Vd, Bd = dev(U), dev(V), dev(B)
-    plans = [None, spk.Plan(0, 4, 0), spk.Plan(0, 16, 0), spk.Plan(0, 64, 0), spk.Plan(0, 8, 0, 1)]
+    # NULL = runs of 512 entries; small runs cut most rows into pieces
+    plans = [None, spk.Plan(0, 4, 0), spk.Plan(0, 16, 0), spk.Plan(0, 64, 0), spk.Plan(0, 8, 0, 1),
+             spk.Plan(1, 8, 7), spk.Plan(1, 16, 64), spk.Plan(1, 4, 1000), spk.Plan(1, 32, 3, 1)]
     for plan in plans:
         try:
             O, lse = spk.attention(dA, Ud, Vd, Bd, plan=plan, with_lse=True)
@@ -100,9 +102,11 @@ def test_attention_bf16_empty_rows_and_strides(spk):
     Vd = dev(pad(Vr)).to(torch.bfloat16)[:, :K1]
     Bd = dev(pad(Br)).to(torch.bfloat16)[:, :K2]
     O = torch.full((7, ld), 9.0, device="cuda")[:, :K2]
-    _, lse = spk.attention(spk.CSR.from_host(A, v), Ud, Vd, Bd, out=O, with_lse=True)
-    check(O.cpu().numpy(), lse.cpu().numpy(), ref, K1, "bf16 strided")
-    assert not O[0].any() and not O[3].any()
+    for plan in (None, spk.Plan(1, 8, 2), spk.Plan(0, 8, 0)):
+        O.fill_(9.0)
+        _, lse = spk.attention(spk.CSR.from_host(A, v), Ud, Vd, Bd, out=O, with_lse=True, plan=plan)
+        check(O.cpu().numpy(), lse.cpu().numpy(), ref, K1, f"bf16 strided {plan}")
+        assert not O[0].any() and not O[3].any()
     # no stored entries at all
     E = synth.HostCSR(5, 9, np.zeros(6, np.int32), np.zeros(0, np.int32))
     O, lse = spk.attention(spk.CSR.from_host(E, np.zeros(0, np.float32)), dev(U[:5]), dev(V[:9]), dev(B[:9]),
@@ -117,8 +121,11 @@ def test_row_softmax_matches_oracle(spk):
     dA = spk.CSR.from_host(A, v)
     S = spk.sddmm(dA, dev(U), dev(V))
     P, lse = spk.csr_row_softmax(dA, S, with_lse=True)
-    P = P.cpu().numpy().astype(np.float64)
     _, _, E, L = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, v, U, V, B)
+    fin = np.isfinite(L)
+    assert np.array_equal(np.isneginf(lse.cpu().numpy()), ~fin)
+    assert np.all(np.abs(lse.cpu().numpy()[fin] - L[fin]) <= 4 * 16 * U_ROUND * E[fin] + 8 * U_ROUND * np.abs(L[fin]) + 1e-6)
+    P = P.cpu().numpy().astype(np.float64)
     for i in np.concatenate([np.arange(50), np.argsort(A.row_lengths())[-5:]]):
         a, b = A.row_ptr[i], A.row_ptr[i + 1]
         if b == a:
@@ -140,7 +147,7 @@ def test_attention_full_size_sampled(spk):
     srp, sci, idx = sub_rows(A, rows)
     ref = oracle.sddmm_softmax_spmm(srp, sci, v[idx], U[rows], V, B)
     r = torch.from_numpy(rows).cuda()
-    for plan in (None, spk.Plan(0, 16, 0)):
+    for plan in (None, spk.Plan(1, 8, 128), spk.Plan(0, 16, 0)):
         O, lse = spk.attention(dA, Ud, Vd, Bd, plan=plan, with_lse=True)
         check(O[r].cpu().numpy(), lse[r].cpu().numpy(), ref, K, f"full-size fused {plan}")
     O = spk.attention_unfused(dA, Ud, Vd, Bd)
