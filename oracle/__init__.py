@@ -71,6 +71,10 @@ def _load():
     lib.oracle_csr_to_slab16.restype = i64
     lib.oracle_sddmm_softmax_spmm.argtypes = [i64, i64, i64, vp, vp, vp, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, vp]
     lib.oracle_sddmm_softmax_spmm.restype = None
+    lib.oracle_nonempty_order.argtypes = [i64, vp, vp]
+    lib.oracle_nonempty_order.restype = i64
+    lib.oracle_row_index.argtypes = [i64, vp, vp]
+    lib.oracle_row_index.restype = None
     lib.oracle_csr_canonical.argtypes = [i64, i64, i64, vp, vp]
     lib.oracle_csr_canonical.restype = ctypes.c_int32
     _lib = lib
@@ -168,6 +172,26 @@ def sddmm_softmax_spmm(row_ptr, col_idx, vals, U, V, B):
     lib.oracle_sddmm_softmax_spmm(m, K1, K2, _p(rp), _p(ci), _p(v64), _p(U64), K1, _p(V64), K1, _p(B64), K2,
                                   _p(O), K2, _p(M), _p(E), _p(L))
     return O, M, E, L
+
+
+def nonempty_order(row_ptr):
+    """(order[m], nr): non-empty rows ascending, then empty rows ascending."""
+    lib = _load()
+    rp = _i32(row_ptr)
+    m = rp.shape[0] - 1
+    order = np.empty(m, np.int32)
+    nr = int(lib.oracle_nonempty_order(m, _p(rp), _p(order)))
+    return order, nr
+
+
+def row_index(row_ptr):
+    """COO row index of every stored entry."""
+    lib = _load()
+    rp = _i32(row_ptr)
+    m = rp.shape[0] - 1
+    out = np.empty(int(rp[m]), np.int32)
+    lib.oracle_row_index(m, _p(rp), _p(out))
+    return out
 
 
 def csr_to_slab16(row_ptr, col_idx, n: int, width: int):

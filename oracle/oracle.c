@@ -235,6 +235,31 @@ void oracle_sddmm_softmax_spmm(int64_t m, int64_t K1, int64_t K2, const int32_t 
 }
 
 /* ---------------------------------------------------------------------- */
+/* Hyper-sparse forms (the paper's weak region above 99% sparsity,         */
+/* Sections I and IV-C, and its first future-work item, Section V).        */
+/* Row order of the doubly compressed form: the rows holding an entry in   */
+/* increasing order, then the empty rows in increasing order; returns the  */
+/* number of non-empty rows.  A product then visits only order[0 .. nr).   */
+/* ---------------------------------------------------------------------- */
+int64_t oracle_nonempty_order(int64_t m, const int32_t *row_ptr, int32_t *order) {
+    int64_t nr = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (row_ptr[i + 1] > row_ptr[i]) order[nr++] = (int32_t)i;
+    int64_t k = nr;
+    for (int64_t i = 0; i < m; ++i)
+        if (row_ptr[i + 1] == row_ptr[i]) order[k++] = (int32_t)i;
+    return nr;
+}
+
+/* Coordinate (COO) row index of every stored entry: rowidx[p] = the row    */
+/* whose range holds p (the paper's workers keep row, column and value of   */
+/* each nonzero, Section III-B).                                            */
+void oracle_row_index(int64_t m, const int32_t *row_ptr, int32_t *rowidx) {
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) rowidx[p] = (int32_t)i;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Canonical CSR, the input form every product assumes (the paper sends    */
 /* CSR with 32-bit column indices, Section III-A, and is silent on order   */
 /* and duplicates; the reading taken here is the usual canonical form).    */

@@ -481,3 +481,26 @@ def test_attention_chain_closed_forms():
     assert np.array_equal(O[0], B[17].astype(np.float64)) and not O[1].any()
     assert np.isclose(L[0], float(U[0].astype(np.float64) @ V[17].astype(np.float64)), rtol=1e-14, atol=0)
     assert np.isneginf(L[1])
+
+
+# ---------------------------------------------------------------- hyper-sparse forms
+def test_hypersparse_hand_examples(golden):
+    for c in golden["hypersparse"]["cases"]:
+        order, nr = oracle.nonempty_order(c["row_ptr"])
+        assert order.tolist() == c["order"] and nr == c["nr"]
+        assert oracle.row_index(c["row_ptr"]).tolist() == c["rowidx"]
+
+
+@pytest.mark.parametrize("m,n,d,seed", [(5000, 3000, 1e-4, 0), (300, 300, 0.01, 1), (1000, 10, 0.0, 2)])
+def test_hypersparse_forms_properties(m, n, d, seed):
+    """order is a permutation listing exactly the non-empty rows first, each
+    part ascending; rowidx repeats each row number its length, in order
+    (numpy's repeat of the row lengths)."""
+    A = synth.bernoulli(m, n, d, seed)
+    order, nr = oracle.nonempty_order(A.row_ptr)
+    lens = np.diff(A.row_ptr)
+    assert sorted(order.tolist()) == list(range(m))
+    assert nr == int((lens > 0).sum())
+    assert np.all(lens[order[:nr]] > 0) and np.all(lens[order[nr:]] == 0)
+    assert np.all(np.diff(order[:nr]) > 0) and np.all(np.diff(order[nr:]) > 0)
+    assert np.array_equal(oracle.row_index(A.row_ptr), np.repeat(np.arange(m, dtype=np.int32), lens))
