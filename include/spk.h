@@ -114,9 +114,13 @@ enum spk_variant {
                           (the lanes field is then not used; rows of 512
                           bytes keep 4 rows per group); other shapes run the
                           split above. */
-    SPK_VAR_SLAB16 = 5 /* the column-slab form with 16-bit columns
-                          (spmm_slab16 / sddmm_slab16 only): row-split over
-                          the slabs of the form, one launch per slab */
+    SPK_VAR_SLAB16 = 5, /* the column-slab form with 16-bit columns
+                           (spmm_slab16 / sddmm_slab16 only): row-split over
+                           the slabs of the form, one launch per slab */
+    SPK_VAR_DCSR = 6,   /* doubly compressed rows (spmm_dcsr / sddmm_dcsr
+                           only): row-split over the non-empty rows */
+    SPK_VAR_COO = 7     /* COO entries (sddmm_coo only): flat runs of
+                           `chunk` entries whatever their rows */
 };
 
 /* An execution plan: plain data, owned by the caller.
@@ -301,6 +305,58 @@ int32_t spmm_slab16(const spk_slab16 *F, const void *vals, const void *B, int64_
  * slices of lanes * 4 columns). */
 int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64_t ldu, const void *V,
                      int64_t ldv, int32_t uv_dtype, int64_t K, void *S, const spk_plan *plan, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Hyper-sparse forms, for the region above 99% sparsity where the paper's
+ * design falls back towards the CPU (Sections I and IV-C; first future-work
+ * item, Section V).  Both are per-pattern preprocessing built on the GPU.
+ * ------------------------------------------------------------------------ */
+
+/* Doubly compressed rows: A's CSR arrays plus a row order whose first nrows
+ * entries are the rows holding an entry (ascending) and the rest the empty
+ * rows (ascending).  Products launch groups for the non-empty rows only and
+ * write the empty rows' zeros with plain stores. */
+typedef struct spk_dcsr {
+    int64_t m, n, nnz;
+    int64_t nrows;           /* rows holding an entry */
+    const int32_t *row_ptr;  /* device, m+1 (A's) */
+    const int32_t *col_idx;  /* device, nnz (A's) */
+    const void *vals;        /* device, nnz F32 (A's); NULL = pattern */
+    const int32_t *order;    /* device, m (from csr_nonempty_order) */
+} spk_dcsr;
+
+/* Scratch bytes of csr_nonempty_order for A (0 for bad arguments). */
+size_t nonempty_order_workspace_bytes(const spk_csr *A);
+
+/* The row order (device, m) and the number of non-empty rows (*nrows, host).
+ * The result is unique.  Synchronises `stream` to return the count. */
+int32_t csr_nonempty_order(const spk_csr *A, int32_t *order, int64_t *nrows, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* SpMM (Eq. 1) on the doubly compressed form: C = A B, C fully written (F32),
+ * B F32 or BF16 as in spmm_csr.  plan NULL or SPK_VAR_DCSR with lanes 4..64
+ * and flags bit 0 (scalar loads). */
+int32_t spmm_dcsr(const spk_dcsr *D, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C,
+                  int64_t ldc, const spk_plan *plan, void *stream);
+
+/* SDDMM (Eq. 2) on the doubly compressed form (S device [nnz] F32, A's
+ * order); plan as for spmm_dcsr, at most 8 register slices of lanes * 4
+ * columns. */
+int32_t sddmm_dcsr(const spk_dcsr *D, const void *U, int64_t ldu, const void *V, int64_t ldv, int32_t uv_dtype,
+                   int64_t K, void *S, const spk_plan *plan, void *stream);
+
+/* COO row index of A's entries: rowidx device [nnz], rowidx[p] = the row
+ * holding entry p. */
+int32_t csr_row_index(const spk_csr *A, int32_t *rowidx, void *stream);
+
+/* SDDMM (Eq. 2) over COO entries: flat runs of `chunk` entries (0: 64)
+ * whatever their rows, each entry's row of U gathered like its row of V, so
+ * the work splits evenly however the entries fall into rows.  A's col_idx
+ * and vals (F32 or NULL), rowidx from csr_row_index.  plan NULL or
+ * SPK_VAR_COO with lanes 4..64 (NULL: 8, widened until K fits 8 register
+ * slices) and flags bit 0. */
+int32_t sddmm_coo(const spk_csr *A, const int32_t *rowidx, const void *U, int64_t ldu, const void *V,
+                  int64_t ldv, int32_t uv_dtype, int64_t K, void *S, const spk_plan *plan, void *stream);
 
 /* ------------------------------------------------------------------------
  * Back-to-back products with the intermediate kept on chip (the paper's

@@ -16,7 +16,7 @@ F32, BF16, F64 = 0, 1, 2
 # enum spk_op
 OP_SPMM, OP_SDDMM, OP_BACKWARD, OP_TRANSPOSE, OP_BSR4, OP_SELECT = 0, 1, 2, 3, 4, 5
 # enum spk_variant
-VAR_ROWS, VAR_MERGE, VAR_BSR4, VAR_SLAB, VAR_TILE, VAR_SLAB16 = 0, 1, 2, 3, 4, 5
+VAR_ROWS, VAR_MERGE, VAR_BSR4, VAR_SLAB, VAR_TILE, VAR_SLAB16, VAR_DCSR, VAR_COO = 0, 1, 2, 3, 4, 5, 6, 7
 
 STATUS = {
     0: "SPK_OK", -1: "SPK_ERR_NULL", -2: "SPK_ERR_SIZE", -3: "SPK_ERR_DTYPE", -4: "SPK_ERR_LD",
@@ -48,6 +48,12 @@ class spk_slab16(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("width", ctypes.c_int64),
                 ("nslabs", ctypes.c_int64), ("seg", ctypes.c_void_p), ("apos", ctypes.c_void_p),
                 ("col16", ctypes.c_void_p)]
+
+
+class spk_dcsr(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("nrows", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("order", ctypes.c_void_p)]
 
 
 class SpkError(RuntimeError):
@@ -85,6 +91,12 @@ SIGNATURES = {
     "attention_workspace_bytes": ([_CSR_P, _I64, _PLAN_P], _SZ),
     "csr_row_softmax": ([_CSR_P, _P, _P, _P, _SZ, _P], _I32),
     "row_softmax_workspace_bytes": ([_CSR_P], _SZ),
+    "nonempty_order_workspace_bytes": ([_CSR_P], _SZ),
+    "csr_nonempty_order": ([_CSR_P, _P, ctypes.POINTER(ctypes.c_int64), _P, _SZ, _P], _I32),
+    "spmm_dcsr": ([ctypes.POINTER(spk_dcsr), _P, _I64, _I32, _I64, _P, _I64, _PLAN_P, _P], _I32),
+    "sddmm_dcsr": ([ctypes.POINTER(spk_dcsr), _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P], _I32),
+    "csr_row_index": ([_CSR_P, _P, _P], _I32),
+    "sddmm_coo": ([_CSR_P, _P, _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P], _I32),
     "plan_count": ([_I32], _I32),
     "plan_of_index": ([_I32, _I32, _I64, _PLAN_P, ctypes.POINTER(_I32)], _I32),
     "csr_features": ([_CSR_P, _P, _P, _SZ, _P], _I32),

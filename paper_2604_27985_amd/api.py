@@ -31,7 +31,8 @@ class Plan:
         return _lib.spk_plan(self.variant, self.lanes, self.chunk, self.flags)
 
     def name(self) -> str:
-        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4", VAR_SLAB: "slab", 4: "tile", 5: "slab16"}[self.variant]
+        v = {VAR_ROWS: "rows", VAR_MERGE: "merge", 2: "bsr4", VAR_SLAB: "slab", 4: "tile", 5: "slab16", 6: "dcsr",
+             7: "coo"}[self.variant]
         s = f"{v}/l{self.lanes}"
         if self.chunk:
             s += f"/c{self.chunk}"
@@ -43,7 +44,8 @@ class Plan:
     def from_name(cls, name: str) -> "Plan":
         """Inverse of name(): "tile/l16/c64/f6" and the like."""
         parts = name.split("/")
-        v = {"rows": VAR_ROWS, "merge": VAR_MERGE, "bsr4": 2, "slab": VAR_SLAB, "tile": 4, "slab16": 5}[parts[0]]
+        v = {"rows": VAR_ROWS, "merge": VAR_MERGE, "bsr4": 2, "slab": VAR_SLAB, "tile": 4, "slab16": 5, "dcsr": 6,
+             "coo": 7}[parts[0]]
         fields = {p[0]: int(p[1:]) for p in parts[1:]}
         return cls(v, fields.get("l", 16), fields.get("c", 0), fields.get("f", 0))
 
@@ -122,6 +124,27 @@ class CSR:
             self._transpose = csr_transpose(self)
         return self._transpose
 
+    def nonempty_order(self):
+        """(order [m] int32, nrows): non-empty rows first, built on the GPU once
+        per pattern and cached."""
+        if getattr(self, "_order", None) is None:
+            self._order = csr_nonempty_order(self)
+        return self._order
+
+    def row_index(self) -> torch.Tensor:
+        """COO row index of the entries, built on the GPU once per pattern."""
+        if getattr(self, "_rowidx", None) is None:
+            self._rowidx = csr_row_index(self)
+        return self._rowidx
+
+    def dcsr(self, vals: torch.Tensor | None = None, use_vals: bool = True) -> "_lib.spk_dcsr":
+        order, nr = self.nonempty_order()
+        ca = self.c(vals, use_vals=use_vals)
+        if ca.vals is not None and ca.vals_dtype != F32:
+            raise ValueError("the hyper-sparse products take float32 values")
+        return _lib.spk_dcsr(self.m, self.n, self.nnz, nr, ca.row_ptr, ca.col_idx, ca.vals,
+                             order.data_ptr() if order.numel() else None)
+
     def slab16_form(self, width: int) -> "Slab16":
         """Column-slab form with 16-bit columns at this slab width, built on the
         GPU once per pattern and width and cached (values are not part of it)."""
@@ -181,6 +204,12 @@ def spmm(A: CSR, B: torch.Tensor, plan: Plan | None = None, out: torch.Tensor | 
     if plan is not None and plan.variant == _lib.VAR_BSR4:
         # the block form is per-pattern (and per-values) preprocessing, cached on A
         return spmm_bsr4(A.block_form(vals), B, out=C)
+    if plan is not None and plan.variant == _lib.VAR_DCSR:
+        cd, cp = A.dcsr(vals), plan.c()
+        st = lib.spmm_dcsr(ctypes.byref(cd), _ptr(B), B.stride(0), _DT[B.dtype], K, _ptr(C), C.stride(0),
+                           ctypes.byref(cp), _stream())
+        _lib.check(st, "spmm_dcsr")
+        return C
     if plan is not None and plan.variant == _lib.VAR_SLAB16:
         # the slab form is per-pattern preprocessing, cached on A; values stay A's
         F = A.slab16_form(slab16_width(plan, K, B.dtype))
@@ -208,6 +237,18 @@ def sddmm(A: CSR, U: torch.Tensor, V: torch.Tensor, plan: Plan | None = None, ou
     K = int(U.shape[1])
     odt = torch.float64 if U.dtype == torch.float64 else torch.float32
     S = out if out is not None else torch.empty(A.nnz, dtype=odt, device=U.device)
+    if plan is not None and plan.variant in (_lib.VAR_DCSR, _lib.VAR_COO):
+        cp = plan.c()
+        if plan.variant == _lib.VAR_DCSR:
+            cd = A.dcsr(vals, use_vals=not pattern)
+            st = lib.sddmm_dcsr(ctypes.byref(cd), _ptr(U), U.stride(0), _ptr(V), V.stride(0), _DT[U.dtype], K,
+                                _ptr(S), ctypes.byref(cp), _stream())
+        else:
+            ca = A.c(vals, use_vals=not pattern)
+            st = lib.sddmm_coo(ctypes.byref(ca), _ptr(A.row_index()), _ptr(U), U.stride(0), _ptr(V), V.stride(0),
+                               _DT[U.dtype], K, _ptr(S), ctypes.byref(cp), _stream())
+        _lib.check(st, "sddmm_dcsr" if plan.variant == _lib.VAR_DCSR else "sddmm_coo")
+        return S
     if plan is not None and plan.variant == _lib.VAR_SLAB16:
         F = A.slab16_form(slab16_width(plan, K, U.dtype))
         v = None if pattern else (A.vals if vals is None else vals)
@@ -498,6 +539,31 @@ def attention_unfused(A: CSR, U: torch.Tensor, V: torch.Tensor, B: torch.Tensor,
     S = sddmm(A, U, V, plan=sddmm_plan, vals=vals, pattern=pattern, out=S)
     csr_row_softmax(A, S)
     return spmm(A, B, plan=spmm_plan, vals=S, out=out)
+
+
+def csr_nonempty_order(A: CSR):
+    """(order [m] int32, nrows): rows holding an entry first, then empty rows."""
+    lib = _lib.load()
+    _require_device(A.row_ptr)
+    dev = A.row_ptr.device
+    order = torch.empty(A.m, dtype=torch.int32, device=dev)
+    ca = A.c(use_vals=False)
+    nb = int(lib.nonempty_order_workspace_bytes(ctypes.byref(ca)))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    nr = ctypes.c_int64(0)
+    _lib.check(lib.csr_nonempty_order(ctypes.byref(ca), _ptr(order) if A.m else None, ctypes.byref(nr), _ptr(ws), nb,
+                                      _stream()), "csr_nonempty_order")
+    return order, int(nr.value)
+
+
+def csr_row_index(A: CSR) -> torch.Tensor:
+    """COO row index of A's entries."""
+    lib = _lib.load()
+    _require_device(A.row_ptr)
+    rowidx = torch.empty(A.nnz, dtype=torch.int32, device=A.row_ptr.device)
+    ca = A.c(use_vals=False)
+    _lib.check(lib.csr_row_index(ctypes.byref(ca), _ptr(rowidx) if A.nnz else None, _stream()), "csr_row_index")
+    return rowidx
 
 
 def validate_rules(A: CSR) -> int:

@@ -533,6 +533,140 @@ int32_t sddmm_slab16(const spk_slab16 *F, const void *vals, const void *U, int64
     return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
 }
 
+// ---------------------------------------------------------------- hyper-sparse
+}  // extern "C"
+
+namespace {
+
+int32_t check_dcsr(const spk_dcsr *D) {
+    if (!D) return SPK_ERR_NULL;
+    if (D->m < 0 || D->n < 0 || D->nnz < 0 || D->m > kMaxIndex || D->n > kMaxIndex || D->nnz > kMaxIndex)
+        return SPK_ERR_SIZE;
+    if (D->nrows < 0 || D->nrows > D->m) return SPK_ERR_SIZE;
+    if (D->m > 0 && (!D->row_ptr || !D->order)) return SPK_ERR_NULL;
+    if (D->nnz > 0 && !D->col_idx) return SPK_ERR_NULL;
+    return SPK_OK;
+}
+
+// Lanes and flags of a hyper-sparse plan (variant `want`), as a ROWS plan.
+int32_t hyper_plan(const spk_plan *plan, int32_t want, spk_plan &out) {
+    if (plan && plan->variant != want) return SPK_ERR_PLAN;
+    out = plan ? spk_plan{SPK_VAR_ROWS, plan->lanes, 0, plan->flags} : spk_plan{SPK_VAR_ROWS, 0, 0, 0};
+    return SPK_OK;
+}
+
+int32_t default_sddmm_lanes(int64_t K) {
+    int32_t lanes = 8;
+    while (lanes < 64 && (K + lanes * 4 - 1) / (lanes * 4) > 8) lanes <<= 1;
+    return lanes;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nonempty_order_workspace_bytes(const spk_csr *A) {
+    if (check_csr(A) != SPK_OK) return 0;
+    return align_up(sizeof(int32_t)) + nonempty_order_ws_bytes(A->m);
+}
+
+int32_t csr_nonempty_order(const spk_csr *A, int32_t *order, int64_t *nrows, void *ws, size_t ws_bytes,
+                           void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (!nrows || (A->m > 0 && !order)) return SPK_ERR_NULL;
+    if (A->m == 0) {
+        *nrows = 0;
+        return SPK_OK;
+    }
+    if ((st = check_ws(align_up(sizeof(int32_t)) + nonempty_order_ws_bytes(A->m), ws, ws_bytes))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t *count = static_cast<int32_t *>(ws);
+    if ((st = hip_status(nonempty_order_launch(A->m, A->row_ptr, order, count,
+                                               static_cast<char *>(ws) + align_up(sizeof(int32_t)), s))))
+        return st;
+    int32_t host = 0;
+    if (hipMemcpyAsync(&host, count, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return SPK_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPK_ERR_HIP;
+    *nrows = host;
+    return SPK_OK;
+}
+
+int32_t spmm_dcsr(const spk_dcsr *D, const void *B, int64_t ldb, int32_t b_dtype, int64_t K, void *C, int64_t ldc,
+                  const spk_plan *plan, void *stream) {
+    int32_t st = check_dcsr(D);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (b_dtype != SPK_F32 && b_dtype != SPK_BF16) return SPK_ERR_DTYPE;
+    if (D->m == 0 || K == 0) return SPK_OK;
+    if (!C || (D->nnz > 0 && !B)) return SPK_ERR_NULL;
+    if (ldc < K || (D->nnz > 0 && ldb < K)) return SPK_ERR_LD;
+    spk_plan p;
+    if ((st = hyper_plan(plan, SPK_VAR_DCSR, p))) return st;
+    if (!plan) p.lanes = default_spmm_lanes(K);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (D->nnz == 0) return hip_status(zero_fill(C, D->m, K, ldc, SPK_F32, s));
+    Resolved r;
+    if ((st = resolve_spmm(&p, K, b_dtype, B, ldb, C, ldc, r))) return st;
+    SpmmArgs a{D->m, D->n, D->nnz, K, D->row_ptr, D->col_idx, D->vals, nullptr, B, ldb, b_dtype, C, ldc,
+               SPK_VAR_DCSR, r.lanes, r.vec, 0, nullptr};
+    a.hv.order = D->order;
+    a.hv.nrows = D->nrows;
+    return hip_status(spmm_launch(a, s));
+}
+
+int32_t sddmm_dcsr(const spk_dcsr *D, const void *U, int64_t ldu, const void *V, int64_t ldv, int32_t uv_dtype,
+                   int64_t K, void *S, const spk_plan *plan, void *stream) {
+    int32_t st = check_dcsr(D);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (uv_dtype != SPK_F32 && uv_dtype != SPK_BF16) return SPK_ERR_DTYPE;
+    if (D->nnz == 0) return SPK_OK;
+    if (!S || !U || !V) return SPK_ERR_NULL;
+    if (K > 0 && (ldu < K || ldv < K)) return SPK_ERR_LD;
+    spk_plan p;
+    if ((st = hyper_plan(plan, SPK_VAR_DCSR, p))) return st;
+    if (!plan) p.lanes = default_sddmm_lanes(K);
+    Resolved r;
+    if ((st = resolve_sddmm(&p, K, uv_dtype, U, ldu, V, ldv, r))) return st;
+    SddmmArgs a{D->m, D->n, D->nnz, K, D->row_ptr, D->col_idx, D->vals, U, ldu, V, ldv, uv_dtype, S,
+                SPK_VAR_DCSR, r.lanes, r.vec, 0, nullptr};
+    a.hv.order = D->order;
+    a.hv.nrows = D->nrows;
+    return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
+}
+
+int32_t csr_row_index(const spk_csr *A, int32_t *rowidx, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (A->nnz > 0 && !rowidx) return SPK_ERR_NULL;
+    if (A->nnz == 0) return SPK_OK;
+    return hip_status(row_index_launch(A->m, A->row_ptr, rowidx, static_cast<hipStream_t>(stream)));
+}
+
+int32_t sddmm_coo(const spk_csr *A, const int32_t *rowidx, const void *U, int64_t ldu, const void *V, int64_t ldv,
+                  int32_t uv_dtype, int64_t K, void *S, const spk_plan *plan, void *stream) {
+    int32_t st = check_csr(A);
+    if (st) return st;
+    if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
+    if (uv_dtype != SPK_F32 && uv_dtype != SPK_BF16) return SPK_ERR_DTYPE;
+    if (A->vals && A->vals_dtype != SPK_F32) return SPK_ERR_DTYPE;
+    if (A->nnz == 0) return SPK_OK;
+    if (!S || !U || !V || !rowidx) return SPK_ERR_NULL;
+    if (K > 0 && (ldu < K || ldv < K)) return SPK_ERR_LD;
+    if (plan && plan->chunk < 0) return SPK_ERR_PLAN;
+    spk_plan p;
+    if ((st = hyper_plan(plan, SPK_VAR_COO, p))) return st;
+    if (!plan) p.lanes = default_sddmm_lanes(K);
+    Resolved r;
+    if ((st = resolve_sddmm(&p, K, uv_dtype, U, ldu, V, ldv, r))) return st;
+    const int64_t chunk = plan && plan->chunk > 0 ? plan->chunk : 64;
+    SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, U, ldu, V, ldv, uv_dtype, S,
+                SPK_VAR_COO, r.lanes, r.vec, chunk, nullptr};
+    a.hv.rowidx = rowidx;
+    return hip_status(sddmm_launch(a, static_cast<hipStream_t>(stream)));
+}
+
 // ---------------------------------------------------------------- attention chain
 }  // extern "C"
 

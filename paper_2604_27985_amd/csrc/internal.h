@@ -19,6 +19,14 @@ struct Slab16View {
     int64_t width = 0, nslabs = 0;
 };
 
+// Hyper-sparse forms (hyper.hip): the row order of the doubly compressed
+// form (non-empty rows first) and the COO row index of every entry.
+struct HyperView {
+    const int32_t *order = nullptr;   // DCSR: m rows, the first nrows non-empty
+    int64_t nrows = 0;
+    const int32_t *rowidx = nullptr;  // COO: row of every entry
+};
+
 struct SpmmArgs {
     int64_t m, n, nnz, K;
     const int32_t *rp, *ci;
@@ -35,6 +43,7 @@ struct SpmmArgs {
     int32_t rows_per_group = 4;  // TILE: rows each lane group owns (4 or 8)
     int32_t quad_split = 0;      // TILE: one entry per 4-lane quad, 16-lane groups
     Slab16View s16{};            // SLAB16: the column-slab form (ci unused)
+    HyperView hv{};              // DCSR
 };
 
 struct SddmmArgs {
@@ -53,6 +62,7 @@ struct SddmmArgs {
     int32_t rows_per_group = 4;  // TILE: rows each lane group owns (4 or 8)
     int32_t quad_split = 0;      // TILE: one entry per 4-lane quad, 16-lane groups
     Slab16View s16{};            // SLAB16: the column-slab form (ci unused)
+    HyperView hv{};              // DCSR, COO
 };
 
 // Column slabs of the SLAB variants: nslabs slabs of `width` columns; the
@@ -189,6 +199,12 @@ hipError_t attn_launch(const AttnArgs &a, hipStream_t s);
 constexpr int64_t kSoftmaxItems = 1024;
 size_t row_softmax_ws_bytes(int64_t m, int64_t nnz);
 hipError_t row_softmax_launch(int64_t m, int64_t nnz, const int32_t *rp, float *S, float *lse, void *ws, hipStream_t s);
+
+// Hyper-sparse preprocessing (hyper.hip).
+size_t nonempty_order_ws_bytes(int64_t m);
+hipError_t nonempty_order_launch(int64_t m, const int32_t *rp, int32_t *order, int32_t *count_dev, void *ws,
+                                 hipStream_t s);
+hipError_t row_index_launch(int64_t m, const int32_t *rp, int32_t *rowidx, hipStream_t s);
 
 // Structural validation (transpose.hip): writes 0 to *flag_dev when A is
 // canonical, a positive code otherwise.

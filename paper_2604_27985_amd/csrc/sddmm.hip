@@ -278,6 +278,91 @@ __global__ __launch_bounds__(kBlock) void sddmm_rows_kernel(int64_t m, int K, co
     }
 }
 
+// DCSR: group g takes row order[g] of the non-empty rows (g < nrows).
+template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
+__global__ __launch_bounds__(kBlock) void sddmm_dcsr_kernel(int64_t nrows, int K, const int32_t *__restrict__ order,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const TV *__restrict__ vals,
+                                                            const TUV *__restrict__ U, int64_t ldu,
+                                                            const TUV *__restrict__ V, int64_t ldv,
+                                                            typename acc_of<TUV>::type *__restrict__ S) {
+    constexpr int GPB = kBlock / LANES;
+    constexpr int R = LANES < 8 ? LANES : 8;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t g = blk * GPB + threadIdx.x / LANES;
+    if (g >= nrows) return;
+    const int64_t row = order[g];
+    const int64_t a = rp[row], b = rp[row + 1];
+    URow<TUV, VW, LANES, NS> ur;
+    ur.load(U, row, ldu, K, lig);
+    Step<TUV, VW, LANES, NS, R, OFF32> st;
+    st.load(a, static_cast<int>(b - a < R ? b - a : R), ci, V, ldv, K, gbase, lig);
+    while (true) {
+        typename acc_of<TUV>::type part[R];
+        st.dots(ur, part);
+        const int64_t pb_cur = st.pb;
+        const int cnt_cur = st.cnt;
+        const int64_t pb = pb_cur + cnt_cur;
+        const bool more = pb < b;
+        if (more) st.load(pb, static_cast<int>(b - pb < R ? b - pb : R), ci, V, ldv, K, gbase, lig);
+        finish<R, LANES>(pb_cur, cnt_cur, part, vals, S, lig, lane);
+        if (!more) break;
+    }
+}
+
+// COO: group g takes entries [g*chunk, (g+1)*chunk), R at a time, whatever
+// their rows: each entry's row comes from rowidx and its slice of U is
+// gathered like V's (consecutive entries of a row hit the same cached row).
+template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
+__global__ __launch_bounds__(kBlock) void sddmm_coo_kernel(int64_t nnz, int K, const int32_t *__restrict__ rowidx,
+                                                           const int32_t *__restrict__ ci,
+                                                           const TV *__restrict__ vals,
+                                                           const TUV *__restrict__ U, int64_t ldu,
+                                                           const TUV *__restrict__ V, int64_t ldv,
+                                                           typename acc_of<TUV>::type *__restrict__ S, int64_t chunk,
+                                                           int64_t ngroups) {
+    using A = typename acc_of<TUV>::type;
+    constexpr int GPB = kBlock / LANES;
+    constexpr int R = LANES < 8 ? LANES : 8;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = lane & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t g = blk * GPB + threadIdx.x / LANES;
+    if (g >= ngroups) return;
+    const int64_t p0 = g * chunk;
+    const int64_t p1 = p0 + chunk < nnz ? p0 + chunk : nnz;
+    for (int64_t pb = p0; pb < p1; pb += R) {
+        const int cnt = static_cast<int>(p1 - pb < R ? p1 - pb : R);
+        const int mine = lig < cnt ? lig : cnt - 1;
+        const int r_mine = __builtin_nontemporal_load(rowidx + pb + mine);
+        const int c_mine = __builtin_nontemporal_load(ci + pb + mine);
+        A part[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int rq = lane_read(r_mine, gbase + q), cq = lane_read(c_mine, gbase + q);
+            A acc = A(0);
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) {
+                const int k = sl * LANES * VW + lig * VW;
+                const int kk = k < K ? k : 0;
+                A uu[VW], vv[VW];
+                vec_load<TUV, VW>::run(U + static_cast<int64_t>(rq) * ldu + kk, uu);
+                vec_load<TUV, VW>::run(row_elem<OFF32>(V, cq, ldv, kk), vv);
+                if (k < K)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) acc = fma(uu[e], vv[e], acc);
+            }
+            part[q] = acc;
+        }
+        finish<R, LANES>(pb, cnt, part, vals, S, lig, lane);
+    }
+}
+
 // SLAB16: group g takes run (s, g) of the column-slab form (slab16.hip): its
 // entries are positions [seg[s m + g], seg[s m + g + 1]) of col16 (columns
 // s W + col16), and entry k sits at A position apos[s m + g] + k, where its
@@ -702,6 +787,26 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
         if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
         hipLaunchKernelGGL((sddmm_split_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
                            dim3(kBlock), 0, s, a.m, a.nnz, static_cast<int>(a.K), a.rp, a.ci,
+                           static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
+                           static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S), a.chunk, ngroups);
+        return hipGetLastError();
+    }
+    if (a.variant == SPK_VAR_DCSR) {
+        if (a.hv.nrows <= 0) return hipSuccess;
+        const int64_t nb = (a.hv.nrows + GPB - 1) / GPB;
+        if (nb > 0x7FFFFFFF || a.hv.nrows > a.m) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((sddmm_dcsr_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
+                           dim3(kBlock), 0, s, a.hv.nrows, static_cast<int>(a.K), a.hv.order, a.rp, a.ci,
+                           static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
+                           static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S));
+        return hipGetLastError();
+    }
+    if (a.variant == SPK_VAR_COO) {
+        const int64_t ngroups = (a.nnz + a.chunk - 1) / a.chunk;
+        const int64_t nb = (ngroups + GPB - 1) / GPB;
+        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((sddmm_coo_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
+                           dim3(kBlock), 0, s, a.nnz, static_cast<int>(a.K), a.hv.rowidx, a.ci,
                            static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
                            static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S), a.chunk, ngroups);
         return hipGetLastError();

@@ -161,6 +161,46 @@ __global__ __launch_bounds__(kBlock) void spmm_slab_kernel(int64_t m, int K, con
     }
 }
 
+// DCSR: group g takes row order[g] of the non-empty rows (g < nrows).
+template <typename TB, typename TV, int VW, int LANES, bool OFF32>
+__global__ __launch_bounds__(kBlock) void spmm_dcsr_kernel(int64_t nrows, int K, const int32_t *__restrict__ order,
+                                                           const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const TV *__restrict__ vals, const TB *__restrict__ B,
+                                                           int64_t ldb, typename acc_of<TB>::type *__restrict__ C,
+                                                           int64_t ldc) {
+    using A = typename acc_of<TB>::type;
+    constexpr int GPB = kBlock / LANES;
+    const int lig = threadIdx.x & (LANES - 1);
+    const int gbase = (threadIdx.x & (kWave - 1)) & ~(LANES - 1);
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t g = blk * GPB + threadIdx.x / LANES;
+    if (g >= nrows) return;
+    const int64_t row = order[g];
+    const int k0 = blockIdx.y * (LANES * VW) + lig * VW;
+    const bool kvalid = k0 < K;
+    A acc[VW];
+    zero<A, VW>(acc);
+    accumulate_entries<TB, TV, VW, LANES, OFF32>(rp[row], rp[row + 1], ci, vals, nullptr, B, ldb, kvalid ? k0 : 0,
+                                                 gbase, lig, acc);
+    if (kvalid) vec_store<A, VW>::run(C + row * ldc + k0, acc);
+}
+
+// Zeros for rows order[0 .. count) (the empty rows of a DCSR order): one
+// thread per VW-wide piece of a row, so consecutive threads fill a row with
+// vector stores and a wave covers several rows.
+template <typename A, int VW>
+__global__ void zero_rows_kernel(int64_t count, int64_t pieces, const int32_t *__restrict__ order, A *__restrict__ C,
+                                 int64_t ldc) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= count * pieces) return;
+    const int64_t g = idx / pieces, k = (idx - g * pieces) * VW;
+    A z[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) z[e] = A(0);
+    vec_store<A, VW>::run(C + static_cast<int64_t>(order[g]) * ldc + k, z);
+}
+
 // Slab s of the column-slab form (slab16.hip): group g takes run (s, g), whose
 // entries are positions [seg[s m + g], seg[s m + g + 1]) of col16 (columns
 // s W + col16) with values at A positions apos[s m + g] onward.  Slab 0 writes
@@ -762,6 +802,43 @@ static hipError_t launch_s16(const SpmmArgs &a, hipStream_t s) {
 }
 
 template <typename TB, typename TV, int VW, int LANES, bool OFF32>
+static hipError_t launch_dcsr(const SpmmArgs &a, hipStream_t s) {
+    using A = typename acc_of<TB>::type;
+    constexpr int GPB = kBlock / LANES;
+    const int64_t nr = a.hv.nrows;
+    const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
+    if (ktiles > 65535 || nr < 0 || nr > a.m) return hipErrorInvalidValue;
+    if (nr > 0) {
+        const int64_t nb = (nr + GPB - 1) / GPB;
+        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((spmm_dcsr_kernel<TB, TV, VW, LANES, OFF32>),
+                           dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)), dim3(kBlock), 0, s, nr,
+                           static_cast<int>(a.K), a.hv.order, a.rp, a.ci, static_cast<const TV *>(a.vals),
+                           static_cast<const TB *>(a.B), a.ldb, static_cast<A *>(a.C), a.ldc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t empty = a.m - nr;
+    if (empty > 0) {
+        // 16-byte stores when rows of C are 16-byte aligned pieces
+        const bool v4 = sizeof(A) == 4 && a.K % 4 == 0 && a.ldc % 4 == 0 &&
+                        reinterpret_cast<uintptr_t>(a.C) % 16 == 0;
+        const int64_t pieces = v4 ? a.K / 4 : a.K;
+        const int64_t total = empty * pieces;
+        const int64_t nb = (total + kBlock - 1) / kBlock;
+        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        if (v4)
+            hipLaunchKernelGGL((zero_rows_kernel<A, 4>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, empty,
+                               pieces, a.hv.order + nr, static_cast<A *>(a.C), a.ldc);
+        else
+            hipLaunchKernelGGL((zero_rows_kernel<A, 1>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, empty,
+                               pieces, a.hv.order + nr, static_cast<A *>(a.C), a.ldc);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <typename TB, typename TV, int VW, int LANES, bool OFF32>
 static hipError_t launch_merge(const SpmmArgs &a, hipStream_t s) {
     using A = typename acc_of<TB>::type;
     constexpr int GPB = kBlock / LANES;
@@ -851,6 +928,7 @@ static hipError_t dispatch_lanes(const SpmmArgs &a, hipStream_t s) {
         if (a.variant == SPK_VAR_SLAB) return launch_slab<TB, TV, VW, L, OFF32>(a, s);   \
         if (a.variant == SPK_VAR_TILE) return launch_tile<TB, TV, VW, L>(a, s);          \
         if (a.variant == SPK_VAR_SLAB16) return launch_s16<TB, TV, VW, L, OFF32>(a, s);  \
+        if (a.variant == SPK_VAR_DCSR) return launch_dcsr<TB, TV, VW, L, OFF32>(a, s);   \
         return launch_rows<TB, TV, VW, L, OFF32>(a, s);
         SPK_CASE(4)
         SPK_CASE(8)
