@@ -142,7 +142,12 @@ enum spk_variant {
  *          only): 8 rows per lane group instead of 4 (quad splits of 512-byte
  *          rows and SpMM quad splits of BF16 rows of 128 elements keep 4).
  *          bit 2 (TILE only): one entry per 4-lane quad where the rows fit
- *          (see SPK_VAR_TILE).  Other bits must be 0.
+ *          (see SPK_VAR_TILE).  bit 3 (TILE with bit 2, where the quad
+ *          split applies): wide workgroups - slabs up to 32 KiB run in
+ *          512-thread workgroups with 2 rows per group, larger slabs (up to
+ *          64 KiB, two buffers in 128 KiB of LDS) and all 512-byte rows in
+ *          1024-thread workgroups with 1 row per group; more waves per SIMD
+ *          than the 256-thread form.  Other bits must be 0.
  * Vector loads are used when K and the leading dimensions are multiples of
  * the vector width and the base pointers are aligned to it; otherwise the
  * call falls back to scalar loads by itself.

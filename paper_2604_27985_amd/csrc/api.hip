@@ -50,6 +50,14 @@ struct Resolved {
     int32_t quad_split = 0;
 };
 
+// LDS for the two slab buffers of a TILE plan: 64 KiB, or 128 KiB for the
+// wide quad plans (flags bit 3), whose slabs above 32 KiB run in 1024-thread
+// workgroups, one per CU.
+int64_t tile_lds_budget(const Resolved &r, int64_t) {
+    return r.quad_split && r.rows_per_group == 2 ? 2 * static_cast<int64_t>(kTileLds)
+                                                 : static_cast<int64_t>(kTileLds);
+}
+
 int32_t default_spmm_lanes(int64_t K) {
     int32_t l = 4;
     while (l < 64 && l * 4 < K) l <<= 1;
@@ -77,7 +85,7 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
         // one K-tile of 16-byte (F32) or 8-byte (BF16) lanes; the slab fits kTileLds
         const size_t es = elem_size(b_dtype);
         const int64_t sv = 16 / static_cast<int64_t>(es);
-        if (b_dtype == SPK_F64 || (plan && (plan->flags & ~6)) || (plan && plan->chunk < 0)) return SPK_ERR_PLAN;
+        if (b_dtype == SPK_F64 || (plan && (plan->flags & ~14)) || (plan && plan->chunk < 0)) return SPK_ERR_PLAN;
         r.rows_per_group = plan && (plan->flags & 2) ? 8 : 4;
         const int64_t row_bytes = K * static_cast<int64_t>(es);
         // one entry per quad where a row of B is 128 or 256 bytes (16-lane
@@ -87,10 +95,11 @@ int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const voi
                            ? 1
                            : 0;
         if (r.quad_split) r.lanes = 16;
+        if (r.quad_split && (plan->flags & 8)) r.rows_per_group = 2;  // 512-thread workgroups
         if ((!r.quad_split && K > 4 * r.lanes) || K % sv != 0 || ldb % sv != 0 || !aligned(B, 16) || ldc % 4 != 0 ||
             !aligned(C, 16))
             return SPK_ERR_PLAN;
-        const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * row_bytes);  // two buffers
+        const int64_t wmax = tile_lds_budget(r, row_bytes) / (2 * row_bytes);  // two buffers
         int64_t w = 16;  // default: the largest power of two whose slab fits 16 KiB
         while (w * 2 * row_bytes <= 16384) w *= 2;
         r.chunk = plan && plan->chunk > 0 ? plan->chunk : w;
@@ -129,7 +138,7 @@ int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U
         // groups of 16, 32 or 64 lanes, one 4-wide slice of U and V per lane,
         // slabs of V rows in 16-byte pieces, two slab buffers in kTileLds
         const int64_t sv = 16 / static_cast<int64_t>(es);
-        if (dt == SPK_F64 || (plan->flags & ~6) || plan->chunk < 0) return SPK_ERR_PLAN;
+        if (dt == SPK_F64 || (plan->flags & ~14) || plan->chunk < 0) return SPK_ERR_PLAN;
         r.lanes = plan->lanes;
         r.rows_per_group = (plan->flags & 2) ? 8 : 4;
         const int64_t row_bytes = K * static_cast<int64_t>(es);
@@ -142,11 +151,12 @@ int32_t resolve_sddmm(const spk_plan *plan, int64_t K, int32_t dt, const void *U
                            ? 1
                            : 0;
         if (r.quad_split) r.lanes = 16;
+        if (r.quad_split && (plan->flags & 8)) r.rows_per_group = 2;  // 512-thread workgroups
         if (r.lanes != 16 && r.lanes != 32 && r.lanes != 64) return SPK_ERR_PLAN;
         if ((!r.quad_split && K > 4 * r.lanes) || K % sv != 0 || ldv % sv != 0 || !aligned(V, 16) ||
             ldu % 4 != 0 || !aligned(U, 4 * es))
             return SPK_ERR_PLAN;
-        const int64_t wmax = static_cast<int64_t>(kTileLds) / (2 * row_bytes);
+        const int64_t wmax = tile_lds_budget(r, row_bytes) / (2 * row_bytes);
         int64_t w = 16;  // default: the largest power of two whose slab fits 16 KiB
         while (w * 2 * row_bytes <= 16384) w *= 2;
         r.chunk = plan->chunk > 0 ? plan->chunk : w;

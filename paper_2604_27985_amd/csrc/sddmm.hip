@@ -639,8 +639,8 @@ __device__ __forceinline__ int sddmm_tileq_pass(const unsigned char *__restrict_
     return cnt;
 }
 
-template <typename TUV, typename TV, int NP, int RPG, int NPT>
-__global__ __launch_bounds__(kBlock) void sddmm_tileq_kernel(int64_t m, int64_t n, int64_t nnz,
+template <typename TUV, typename TV, int NP, int RPG, int NPT, int BS>
+__global__ __launch_bounds__(BS, BS > kBlock ? 4 : 1) void sddmm_tileq_kernel(int64_t m, int64_t n, int64_t nnz,
                                                              const int32_t *__restrict__ rp,
                                                              const int32_t *__restrict__ ci,
                                                              const TV *__restrict__ vals,
@@ -649,9 +649,9 @@ __global__ __launch_bounds__(kBlock) void sddmm_tileq_kernel(int64_t m, int64_t 
                                                              float *__restrict__ S, int W) {
     constexpr int SV = kTileSV<TUV>;
     constexpr int per_row = 4 * NP;  // 16-byte pieces in a row of U or V
-    constexpr int buf_bytes = NPT * kTilePiece;
+    constexpr int buf_bytes = NPT * BS * 16;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int GPB = kBlock / 16;
+    constexpr int GPB = BS / 16;
     const int lane = threadIdx.x & (kWave - 1);
     const int lig = threadIdx.x & 15;
     const int q = lig >> 2, j = lig & 3;
@@ -677,10 +677,10 @@ __global__ __launch_bounds__(kBlock) void sddmm_tileq_kernel(int64_t m, int64_t 
             u[r][i] = row < m ? *reinterpret_cast<const u32x4 *>(U + row * ldu + (pb[i] / 16) * SV) : u32x4{0, 0, 0, 0};
     }
     u32x4 stg[NPT];
-    TileCopy<TUV, NPT> copy;
+    TileCopy<TUV, NPT, BS> copy;
     copy.layout(static_cast<int>(n < W ? n : W), per_row, ldv);
     copy.load(V, ldv, 0, stg);
-    tile_store<TUV, NPT>(reinterpret_cast<TUV *>(smem), stg);
+    tile_store<TUV, NPT, BS>(reinterpret_cast<TUV *>(smem), stg);
     int pc[RPG];
     TV pv[RPG];
 #pragma unroll
@@ -702,38 +702,57 @@ __global__ __launch_bounds__(kBlock) void sddmm_tileq_kernel(int64_t m, int64_t 
                 }
             }
         }
-        tile_store<TUV, NPT>(reinterpret_cast<TUV *>(smem + ((sl + 1) & 1) * buf_bytes), stg);
+        tile_store<TUV, NPT, BS>(reinterpret_cast<TUV *>(smem + ((sl + 1) & 1) * buf_bytes), stg);
     }
 }
 
-template <typename TUV, typename TV, int NP, int RPG, int NPT>
+template <typename TUV, typename TV, int NP, int RPG, int NPT, int BS>
 static hipError_t launch_tileq_npt(const SddmmArgs &a, hipStream_t s) {
-    constexpr int GPB = kBlock / 16;
+    constexpr int GPB = BS / 16;
     const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
-    const size_t lds = 2 * static_cast<size_t>(NPT) * kTilePiece;  // two slab buffers
-    hipLaunchKernelGGL((sddmm_tileq_kernel<TUV, TV, NP, RPG, NPT>), dim3(static_cast<unsigned>(nb)), dim3(kBlock),
+    const size_t lds = 2 * static_cast<size_t>(NPT) * BS * 16;  // two slab buffers
+    if (lds > 65536) {  // beyond the default dynamic LDS limit (gfx950 has 160 KiB per CU)
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&sddmm_tileq_kernel<TUV, TV, NP, RPG, NPT, BS>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((sddmm_tileq_kernel<TUV, TV, NP, RPG, NPT, BS>), dim3(static_cast<unsigned>(nb)), dim3(BS),
                        lds, s, a.m, a.n, a.nnz, a.rp, a.ci, static_cast<const TV *>(a.vals),
                        static_cast<const TUV *>(a.U), a.ldu, static_cast<const TUV *>(a.V), a.ldv,
                        static_cast<float *>(a.S), static_cast<int>(a.chunk));
     return hipGetLastError();
 }
 
-template <typename TUV, typename TV, int NP, int RPG>
+template <typename TUV, typename TV, int NP, int RPG, int BS = kBlock>
 static hipError_t launch_tileq_rpg(const SddmmArgs &a, hipStream_t s) {
-    constexpr int GPB = kBlock / 16;
+    constexpr int GPB = BS / 16;
+    constexpr int64_t round = BS * 16;
     const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
     const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TUV));
     if (nb > 0x7FFFFFFF || a.K * static_cast<int64_t>(sizeof(TUV)) != 64 * NP || a.chunk < 1 ||
-        2 * slab_bytes > static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
+        2 * slab_bytes > (BS == 1024 ? 2 : 1) * static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
         return hipErrorInvalidValue;
-    if (slab_bytes <= 2 * kTilePiece) return launch_tileq_npt<TUV, TV, NP, RPG, 2>(a, s);
-    if (slab_bytes <= 4 * kTilePiece) return launch_tileq_npt<TUV, TV, NP, RPG, 4>(a, s);
-    return launch_tileq_npt<TUV, TV, NP, RPG, 8>(a, s);
+    if (slab_bytes <= 2 * round) return launch_tileq_npt<TUV, TV, NP, RPG, 2, BS>(a, s);
+    if (slab_bytes <= 4 * round) return launch_tileq_npt<TUV, TV, NP, RPG, 4, BS>(a, s);
+    if constexpr (BS == kBlock) return launch_tileq_npt<TUV, TV, NP, RPG, 8, BS>(a, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename TUV, typename TV>
 static hipError_t launch_tileq(const SddmmArgs &a, hipStream_t s) {
     const bool r8 = a.rows_per_group == 8;
+    if (a.rows_per_group == 2) {
+        // wide plans: 512 threads with two rows per group for slabs up to
+        // 32 KiB, else 1024 threads with one row per group
+        const bool big = a.chunk * a.K * static_cast<int64_t>(sizeof(TUV)) > kTileLds / 2;
+        switch (a.K * static_cast<int64_t>(sizeof(TUV))) {
+        case 128: return big ? launch_tileq_rpg<TUV, TV, 2, 1, 1024>(a, s) : launch_tileq_rpg<TUV, TV, 2, 2, 512>(a, s);
+        case 256: return big ? launch_tileq_rpg<TUV, TV, 4, 1, 1024>(a, s) : launch_tileq_rpg<TUV, TV, 4, 2, 512>(a, s);
+        case 512: return launch_tileq_rpg<TUV, TV, 8, 1, 1024>(a, s);  // 1024 threads, one row per group
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.K * static_cast<int64_t>(sizeof(TUV))) {
     case 128: return r8 ? launch_tileq_rpg<TUV, TV, 2, 8>(a, s) : launch_tileq_rpg<TUV, TV, 2, 4>(a, s);
     case 256: return r8 ? launch_tileq_rpg<TUV, TV, 4, 8>(a, s) : launch_tileq_rpg<TUV, TV, 4, 4>(a, s);

@@ -487,8 +487,8 @@ __device__ __forceinline__ float dpp_move(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-template <typename TB, typename TV, int NP, int RPG, int NPT>
-__global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n, int64_t nnz,
+template <typename TB, typename TV, int NP, int RPG, int NPT, int BS>
+__global__ __launch_bounds__(BS, BS > kBlock ? 4 : 1) void spmm_tileq_kernel(int64_t m, int64_t n, int64_t nnz,
                                                             const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ ci,
                                                             const TV *__restrict__ vals, const TB *__restrict__ B,
@@ -496,9 +496,9 @@ __global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n
     static_assert(sizeof(TV) == 4, "values are F32 on this path");
     constexpr int SV = kTileSV<TB>;
     constexpr int per_row = 4 * NP;
-    constexpr int buf_bytes = NPT * kTilePiece;
+    constexpr int buf_bytes = NPT * BS * 16;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int GPB = kBlock / 16;
+    constexpr int GPB = BS / 16;
     const int lane = threadIdx.x & (kWave - 1);
     const int lig = threadIdx.x & 15;
     const int q = lig >> 2, j = lig & 3;
@@ -520,10 +520,10 @@ __global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n
         end[r] = row < m ? rp[row + 1] : 0;
     }
     u32x4 stg[NPT];
-    TileCopy<TB, NPT> copy;
+    TileCopy<TB, NPT, BS> copy;
     copy.layout(static_cast<int>(n < W ? n : W), per_row, ldb);
     copy.load(B, ldb, 0, stg);
-    tile_store<TB, NPT>(reinterpret_cast<TB *>(smem), stg);
+    tile_store<TB, NPT, BS>(reinterpret_cast<TB *>(smem), stg);
     int pc[RPG];
     TV pv[RPG];
     float acc[RPG][NP][SV];
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n
                 }
             }
         }
-        tile_store<TB, NPT>(reinterpret_cast<TB *>(smem + ((sl + 1) & 1) * buf_bytes), stg);
+        tile_store<TB, NPT, BS>(reinterpret_cast<TB *>(smem + ((sl + 1) & 1) * buf_bytes), stg);
     }
     // lane (q, j) sums groups g = q + 4h of each row over the four quads and,
     // for g < NP, stores piece j of it: elements (4g + j) * SV .. + SV
@@ -575,28 +575,37 @@ __global__ __launch_bounds__(kBlock) void spmm_tileq_kernel(int64_t m, int64_t n
     }
 }
 
-template <typename TB, typename TV, int NP, int RPG, int NPT>
+template <typename TB, typename TV, int NP, int RPG, int NPT, int BS>
 static hipError_t launch_tileq_npt(const SpmmArgs &a, const TV *vals, hipStream_t s) {
-    constexpr int GPB = kBlock / 16;
+    constexpr int GPB = BS / 16;
     const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
-    const size_t lds = 2 * static_cast<size_t>(NPT) * kTilePiece;  // two slab buffers
-    hipLaunchKernelGGL((spmm_tileq_kernel<TB, TV, NP, RPG, NPT>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), lds,
+    const size_t lds = 2 * static_cast<size_t>(NPT) * BS * 16;  // two slab buffers
+    if (lds > 65536) {  // beyond the default dynamic LDS limit (gfx950 has 160 KiB per CU)
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&spmm_tileq_kernel<TB, TV, NP, RPG, NPT, BS>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((spmm_tileq_kernel<TB, TV, NP, RPG, NPT, BS>), dim3(static_cast<unsigned>(nb)), dim3(BS), lds,
                        s, a.m, a.n, a.nnz, a.rp, a.ci, vals, static_cast<const TB *>(a.B), a.ldb,
                        static_cast<float *>(a.C), a.ldc, static_cast<int>(a.chunk));
     return hipGetLastError();
 }
 
-template <typename TB, typename TV, int NP, int RPG>
+// BS threads per workgroup: a copy round moves BS * 16 bytes, so a slab of
+// up to 32 KiB takes 2, 4 or 8 rounds.
+template <typename TB, typename TV, int NP, int RPG, int BS = kBlock>
 static hipError_t launch_tileq_rpg(const SpmmArgs &a, const TV *vals, hipStream_t s) {
-    constexpr int GPB = kBlock / 16;
+    constexpr int GPB = BS / 16;
+    constexpr int64_t round = BS * 16;
     const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
     const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TB));
     if (nb > 0x7FFFFFFF || a.K * static_cast<int64_t>(sizeof(TB)) != 64 * NP || a.chunk < 1 ||
-        2 * slab_bytes > static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
+        2 * slab_bytes > (BS == 1024 ? 2 : 1) * static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
         return hipErrorInvalidValue;
-    if (slab_bytes <= 2 * kTilePiece) return launch_tileq_npt<TB, TV, NP, RPG, 2>(a, vals, s);
-    if (slab_bytes <= 4 * kTilePiece) return launch_tileq_npt<TB, TV, NP, RPG, 4>(a, vals, s);
-    return launch_tileq_npt<TB, TV, NP, RPG, 8>(a, vals, s);
+    if (slab_bytes <= 2 * round) return launch_tileq_npt<TB, TV, NP, RPG, 2, BS>(a, vals, s);
+    if (slab_bytes <= 4 * round) return launch_tileq_npt<TB, TV, NP, RPG, 4, BS>(a, vals, s);
+    if constexpr (BS == kBlock) return launch_tileq_npt<TB, TV, NP, RPG, 8, BS>(a, vals, s);
+    return hipErrorInvalidValue;
 }
 
 // Rows of 128 bytes (NP = 2), 256 bytes (NP = 4) or 512 bytes (NP = 8, F32
@@ -606,6 +615,19 @@ static hipError_t launch_tileq_rpg(const SpmmArgs &a, const TV *vals, hipStream_
 template <typename TB, typename TV>
 static hipError_t launch_tileq(const SpmmArgs &a, const TV *vals, hipStream_t s) {
     const bool r8 = a.rows_per_group == 8;
+    if (a.rows_per_group == 2) {
+        // wide plans: 512 threads with two rows per group for slabs up to
+        // 32 KiB, else 1024 threads with one row per group
+        const bool big = a.chunk * a.K * static_cast<int64_t>(sizeof(TB)) > kTileLds / 2;
+        switch (a.K * static_cast<int64_t>(sizeof(TB))) {
+        case 128: return big ? launch_tileq_rpg<TB, TV, 2, 1, 1024>(a, vals, s) : launch_tileq_rpg<TB, TV, 2, 2, 512>(a, vals, s);
+        case 256: return big ? launch_tileq_rpg<TB, TV, 4, 1, 1024>(a, vals, s) : launch_tileq_rpg<TB, TV, 4, 2, 512>(a, vals, s);
+        case 512:  // 32 accumulators per lane and row: 1024 threads, one row per group
+            if constexpr (sizeof(TB) == 4) return launch_tileq_rpg<TB, TV, 8, 1, 1024>(a, vals, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.K * static_cast<int64_t>(sizeof(TB))) {
     case 128: return r8 ? launch_tileq_rpg<TB, TV, 2, 8>(a, vals, s) : launch_tileq_rpg<TB, TV, 2, 4>(a, vals, s);
     case 256:

@@ -11,14 +11,14 @@ constexpr int kTilePiece = kBlock * 16;  // bytes one copy round of a workgroup 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Copy of a slab [c0, c0 + w) of B as [w][K] pieces of 16 bytes: thread t
-// moves pieces t + i * kBlock.  Indices past the slab are clamped to its last
+// of a BS-thread workgroup moves pieces t + i * BS.  Indices past the slab are clamped to its last
 // piece, so every thread always issues NPT loads; their copies land in the
 // buffer's tail beyond the slab (a buffer holds NPT * 4 KiB).  The pieces'
 // byte offsets from the slab's first row depend only on the slab width, so
 // they are computed once per width; they fit 32 bits (the API admits TILE
 // plans only when a slab spans less than 4 GiB of B), so every slab's loads
 // are the uniform slab base plus a 32-bit offset, with no address arithmetic.
-template <typename TB, int NPT>
+template <typename TB, int NPT, int BS = kBlock>
 struct TileCopy {
     uint32_t off[NPT];
 
@@ -26,7 +26,7 @@ struct TileCopy {
         const int items = w * per_row;
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
-            const int idx0 = static_cast<int>(threadIdx.x) + i * kBlock;
+            const int idx0 = static_cast<int>(threadIdx.x) + i * BS;
             const int idx = idx0 < items ? idx0 : items - 1;
             const int rr = idx / per_row;
             off[i] = static_cast<uint32_t>((rr * ldb + (idx - rr * per_row) * kTileSV<TB>) * sizeof(TB));
@@ -41,11 +41,11 @@ struct TileCopy {
     }
 };
 
-template <typename TB, int NPT>
+template <typename TB, int NPT, int BS = kBlock>
 __device__ __forceinline__ void tile_store(TB *dst, const u32x4 (&stg)[NPT]) {
 #pragma unroll
     for (int i = 0; i < NPT; ++i)
-        *reinterpret_cast<u32x4 *>(dst + (static_cast<int>(threadIdx.x) + i * kBlock) * kTileSV<TB>) = stg[i];
+        *reinterpret_cast<u32x4 *>(dst + (static_cast<int>(threadIdx.x) + i * BS) * kTileSV<TB>) = stg[i];
 }
 
 // Next chunk of one row: the lane reads entry p (its position in the chunk

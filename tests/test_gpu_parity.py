@@ -98,13 +98,34 @@ def test_spmm_tile_quad_split(spk, K, kind, m, n, d):
     """One entry per 4-lane quad (flags bit 2), 4 or 8 rows per group: default, odd and one-row slabs."""
     A, v, B, _ = problem(m, n, d, K, 13, kind)
     C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    # flags 12: 512-thread workgroups with two rows per group
     for chunk in (0, 7, 1, 31):
-        for flags in (4, 6):
+        for flags in (4, 6, 12):
             plan = spk.Plan(4, 16, chunk, flags)
             assert_within(run_spmm(spk, A, v, B, plan), C64, M, TOL_F32, f"quad spmm K={K} {plan.name()}")
     P64, PM = oracle.spmm(A.row_ptr, A.col_idx, None, B)
     assert_within(run_spmm(spk, A, v, B, spk.Plan(4, 16, 5, 4), pattern=True), P64, PM, TOL_F32,
                   "quad spmm pattern")
+
+
+@pytest.mark.parametrize("kind", ["uniform", "powerlaw"])
+def test_tile_quad_wide_slabs(spk, kind):
+    """Wide quad plans (flags 12): slabs above 32 KiB run in 1024-thread
+    workgroups (512-byte rows always), up to 64 KiB of B per slab (128 KiB of
+    LDS for the two buffers), also ragged last slabs; other plans keep the
+    64 KiB budget."""
+    for K, chunks in ((128, (128, 100, 64)), (64, (256, 200, 128)), (32, (512, 300))):
+        A, v, B, U = problem(3000, 2500, 0.05 if kind == "uniform" else 8, K, 16, kind)
+        C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+        S64, SM = oracle.sddmm(A.row_ptr, A.col_idx, v, U, B)
+        for chunk in chunks:
+            plan = spk.Plan(4, 16, chunk, 12)
+            assert_within(run_spmm(spk, A, v, B, plan), C64, M, TOL_F32, f"wide quad spmm K={K} {plan.name()}")
+            assert_within(run_sddmm(spk, A, v, U, B, plan), S64, SM, TOL_F32, f"wide quad sddmm K={K} {plan.name()}")
+        for plan in (spk.Plan(4, 16, chunks[0], 4), spk.Plan(4, 16, chunks[0] + 1, 12)):
+            with pytest.raises(spk.SpkError) as e:
+                run_spmm(spk, A, v, B, plan)
+            assert e.value.status == -6
 
 
 @pytest.mark.parametrize("K,lanes", [(48, 16), (256, 64), (16, 4), (8, 4)])
@@ -124,7 +145,7 @@ def test_spmm_tile_rejects_unfit_plans(spk):
     for plan in (spk.Plan(4, 8, 0),      # 8 lanes x 4 < K
                  spk.Plan(4, 16, 1 << 20),  # slab larger than the LDS budget
                  spk.Plan(4, 16, 129, 4),   # one entry per quad: 2 x 129 x 256 B > 64 KiB
-                 spk.Plan(4, 16, 0, 8)):    # unknown flag
+                 spk.Plan(4, 16, 0, 16)):   # unknown flag
         with pytest.raises(spk.SpkError) as e:
             run_spmm(spk, A, v, B, plan)
         assert e.value.status == -6
@@ -305,7 +326,7 @@ def test_sddmm_tile_quad_split(spk, K, kind, m, n, d):
     A, v, V, U = problem(m, n, d, K, 12, kind)
     S64, M = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
     for chunk in (0, 7, 1, 31):
-        for flags in (4, 6):
+        for flags in (4, 6, 12):
             plan = spk.Plan(4, 16, chunk, flags)
             assert_within(run_sddmm(spk, A, v, U, V, plan), S64, M, TOL_F32, f"quad sddmm K={K} {plan.name()}")
     # the quad split uses 16-lane groups whatever the plan's lanes
@@ -321,7 +342,7 @@ def test_sddmm_tile_rejects_unfit_plans(spk):
                  spk.Plan(4, 16, 1 << 20),  # slab beyond the LDS budget
                  spk.Plan(4, 16, 0, 1),     # scalar loads are not a TILE option
                  spk.Plan(4, 16, 129, 4),   # one entry per quad: 2 x 129 x 256 B > 64 KiB
-                 spk.Plan(4, 16, 0, 8)):    # unknown flag
+                 spk.Plan(4, 16, 0, 16)):   # unknown flag
         with pytest.raises(spk.SpkError) as e:
             run_sddmm(spk, A, v, U, V, plan)
         assert e.value.status == -6
