@@ -65,7 +65,7 @@ def _load():
     lib.oracle_mlp_loss_grad.restype = dbl
     lib.oracle_adam.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i64]
     lib.oracle_adam.restype = None
-    lib.oracle_selector_inputs.argtypes = [vp, i64, vp]
+    lib.oracle_selector_inputs.argtypes = [vp, i64, ctypes.c_int32, vp]
     lib.oracle_selector_inputs.restype = None
     lib.oracle_csr_to_slab16.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp]
     lib.oracle_csr_to_slab16.restype = i64
@@ -239,15 +239,16 @@ def features(row_ptr, col_idx, n: int) -> np.ndarray:
     return f
 
 
-NIN = 32
+NIN = 33
 
 
-def selector_inputs(f, K: int) -> np.ndarray:
-    """The 32 scaled selector inputs of integer features f and width K (see oracle.c)."""
+def selector_inputs(f, K: int, dtype: int = 0) -> np.ndarray:
+    """The 33 scaled selector inputs of integer features f, width K and the
+    dense operands' dtype (0 binary32, 1 bfloat16); see oracle.c."""
     lib = _load()
     f64 = np.ascontiguousarray(f, dtype=np.int64)
     x = np.empty(NIN, np.float64)
-    lib.oracle_selector_inputs(_p(f64), int(K), _p(x))
+    lib.oracle_selector_inputs(_p(f64), int(K), int(dtype), _p(x))
     return x
 
 

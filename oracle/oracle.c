@@ -375,21 +375,23 @@ void oracle_features(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t
 }
 
 /* ---------------------------------------------------------------------- */
-/* Selector inputs: 32 numbers derived from the integer features f and the  */
-/* dense width K, each scaled to roughly [0, 1]:                           */
+/* Selector inputs: 33 numbers derived from the integer features f, the   */
+/* dense width K and the dense dtype, each scaled to roughly [0, 1]:      */
 /*   x0 log2(1+m)/20, x1 log2(1+n)/20, x2 log2(1+nnz)/30,                  */
 /*   x3..x22 fraction of rows in each row-length bin,                      */
 /*   x23 log2(1+max len)/20, x24 log2(1+mean len)/20 (mean = nnz/m),       */
 /*   x25 log2(1+cv)/4, cv = sqrt(max(0, E[L^2] - mean^2)) / mean,          */
 /*   x26 log2(1+max |i-j|)/20, x27 mean |i-j| / n,                         */
 /*   x28 block fill nnz / (16 * blocks), x29 log2(K)/8,                    */
-/*   x30 1 + log10(nnz / (m n)) / 5, x31 = 1.                              */
+/*   x30 1 + log10(nnz / (m n)) / 5, x31 = 1, x32 = 1 for bfloat16 dense   */
+/*   operands and 0 for binary32.                                          */
 /* Empty denominators count as 1.                                          */
 /* ---------------------------------------------------------------------- */
-#define ORACLE_NIN 32
+#define ORACLE_NIN 33
 int oracle_input_count(void) { return ORACLE_NIN; }
 
-void oracle_selector_inputs(const int64_t *f, int64_t K, double *x) {
+/* dtype: the dense operands' element type, 0 binary32, 1 bfloat16 (x32). */
+void oracle_selector_inputs(const int64_t *f, int64_t K, int32_t dtype, double *x) {
     double m = (double)f[0], n = (double)f[1], nnz = (double)f[2];
     double md = m > 0 ? m : 1.0, nd = n > 0 ? n : 1.0, zd = nnz > 0 ? nnz : 1.0;
     x[0] = log2(1.0 + m) / 20.0;
@@ -409,6 +411,7 @@ void oracle_selector_inputs(const int64_t *f, int64_t K, double *x) {
     double dens = nnz / (md * nd);
     x[30] = 1.0 + log10(dens > 1e-12 ? dens : 1e-12) / 5.0;
     x[31] = 1.0;
+    x[32] = dtype == 1 ? 1.0 : 0.0;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -281,6 +281,10 @@ def test_selector_inputs_closed_forms(golden):
     assert x[26] == np.log2(4) / 20 and np.isclose(x[27], (5 / 5) / 4)
     assert np.isclose(x[28], 5 / 16) and x[29] == 6 / 8
     assert np.isclose(x[30], 1 + np.log10(5 / 12) / 5) and x[31] == 1.0
+    # the dtype input: 0 for binary32 operands, 1 for bfloat16, nothing else moves
+    assert x[32] == 0.0
+    xb = oracle.selector_inputs(f, 64, 1)
+    assert xb[32] == 1.0 and np.array_equal(xb[:32], x[:32])
     # an empty matrix gives finite inputs
     e = np.zeros(28, np.int64)
     e[0], e[1], e[3] = 10, 10, 10
