@@ -422,21 +422,32 @@ size_t row_softmax_workspace_bytes(const spk_csr *A);
  * the fallback and the judge.
  * ------------------------------------------------------------------------ */
 
-/* Number of plans in an op's plan list (SPK_OP_SPMM: 24, SPK_OP_SDDMM: 23),
+/* Number of plans in an op's plan list (SPK_OP_SPMM: 30, SPK_OP_SDDMM: 29),
  * or 0 for other ops. */
 int32_t plan_count(int32_t op);
 
-/* Plan `index` of an op's plan list: index = 5 v + l (< 15) picks variant v
- * (ROWS, MERGE, SLAB) and lanes 4 << l; SpMM index 15 is SPK_VAR_BSR4 (lanes
- * 64); SpMM indices 16..23 are SPK_VAR_TILE with the plain lanes for K and a
- * slab of 16 KiB (16, 18, 20, 21) or 32 KiB (17, 19, 22, 23) of F32 rows,
- * 8 rows per group for the odd indices, one entry per quad (flags bit 2) for
- * 20..23; SDDMM indices 15..22 are the same eight SPK_VAR_TILE plans (at
- * least 16 lanes).  SDDMM MERGE plans use 256 entries per group.  *valid is 1
- * when the plan suits dense width K (lanes not wider than twice K rounded up
- * to a power of two, at least 16; SDDMM: at most 8 register slices; TILE: K
- * a multiple of 8 in [8, 256]).  Host only. */
-int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid);
+/* Plan `index` of an op's plan list:
+ *   0..14   variant v = index / 5 (ROWS, MERGE, SLAB) with lanes 4 << (index % 5)
+ *           (SDDMM MERGE plans use 256 entries per group);
+ *   SpMM 15 SPK_VAR_BSR4 (lanes 64);
+ *   TILE    SpMM 16..23, SDDMM 15..22: the plain lanes for K (SDDMM at least
+ *           16), slabs of 16 KiB (SpMM 16, 18, 20, 21) or 32 KiB (17, 19, 22,
+ *           23) of F32 rows, 8 rows per group for the odd indices, one entry
+ *           per quad (flags bit 2) for the last four;
+ *   wide    SpMM 24, 25 / SDDMM 23, 24: one entry per quad in wide
+ *           workgroups (flags 12), slabs of 32 and 64 KiB of F32 rows;
+ *   SLAB16  SpMM 26, 27 / SDDMM 25, 26: the column-slab form with 2 or 8 MiB
+ *           of F32 rows per slab (between 256 and 65536 columns), the plain
+ *           lanes (SDDMM: 8, widened until K fits 8 register slices);
+ *   DCSR    SpMM 28 (plain lanes), 29 (4 lanes) / SDDMM 27;
+ *   COO     SDDMM 28: 16 lanes, runs of 16 entries.
+ * Slab widths count F32 rows; BF16 slabs of the same width take half the
+ * bytes.  *valid is 1 when the plan suits dense width K and the dense dtype
+ * (SPK_F32, SPK_BF16 or SPK_F64: rows lanes not wider than twice K rounded up
+ * to a power of two, at least 16; SDDMM: at most 8 register slices; TILE:
+ * K a multiple of 8 in [8, 256]; wide 64 KiB: rows the quad split takes;
+ * F64 only plans 0..14).  Host only. */
+int32_t plan_of_index(int32_t op, int32_t index, int64_t K, int32_t dtype, spk_plan *out, int32_t *valid);
 
 /* Integer structural features of A into features (device, 28 int64):
  *   0 m, 1 n, 2 nnz, 3..22 row-length histogram (bin 0 empty rows, bin b in
@@ -446,13 +457,15 @@ int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32
  * ws    spk_workspace_bytes(SPK_OP_SELECT, ...) bytes. */
 int32_t csr_features(const spk_csr *A, int64_t *features, void *ws, size_t ws_bytes, void *stream);
 
-/* The 32 network inputs from features (device, 28) and K, into x (device, 32):
+/* The 33 network inputs from features (device, 28), K and the dense
+ * operands' dtype, into x (device, 33):
  *   x0 log2(1+m)/20, x1 log2(1+n)/20, x2 log2(1+nnz)/30, x3..x22 fraction of
  *   rows per length bin, x23 log2(1+max len)/20, x24 log2(1+mean len)/20,
  *   x25 log2(1+cv)/4 (cv: std / mean of row lengths), x26 log2(1+max|i-j|)/20,
  *   x27 mean |i-j| / n, x28 nnz / (16 blocks), x29 log2(K)/8,
- *   x30 1 + log10(density)/5, x31 1.  Binary32 arithmetic. */
-int32_t selector_inputs(const int64_t *features, int64_t K, float *x, void *stream);
+ *   x30 1 + log10(density)/5, x31 1, x32 1 for SPK_BF16 and 0 otherwise.
+ *   Binary32 arithmetic. */
+int32_t selector_inputs(const int64_t *features, int64_t K, int32_t dtype, float *x, void *stream);
 
 /* Network y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 for `batch` rows of X
  * (device [batch x F]) into Y (device [batch x P]).  params (device) holds
@@ -482,26 +495,28 @@ int32_t adam_update(float *params, const float *grads, float *mom, float *vel, i
 /* Load a trained selector for op (SPK_OP_SPMM or SPK_OP_SDDMM) on the current
  * device from host memory: mean[F], scale[F] (inputs are standardised as
  * (x - mean) / scale), then the F x H x P parameters as for mlp_forward.
- * F must be 32 and P the op's plan count.  Synchronous; copies into a static
+ * F must be 33 and P the op's plan count.  Synchronous; copies into a static
  * table of the library (no allocation). */
 int32_t selector_load(int32_t op, const float *table, int64_t F, int64_t H, int64_t P);
 
-/* Learned plan for op on A with dense width K: features, inputs, network and
- * the argmin of its outputs over the plans valid for K, all on the device.
- * Synchronises `stream` to return the plan in *out.  SPK_ERR_NO_MODEL when
- * no selector is loaded for op on this device (callers then fall back to a
- * timed search).  ws: spk_workspace_bytes(SPK_OP_SELECT, ...) bytes. */
-int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void *ws, size_t ws_bytes,
-                    void *stream);
+/* Learned plan for op on A with dense width K and dense dtype: features,
+ * inputs, network and the argmin of its outputs over the plans valid for K
+ * and dtype, all on the device.  Synchronises `stream` to return the plan in
+ * *out.  SPK_ERR_NO_MODEL when no selector is loaded for op on this device
+ * (callers then fall back to a timed search).
+ * ws: spk_workspace_bytes(SPK_OP_SELECT, ...) bytes. */
+int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, int32_t dtype, spk_plan *out, void *ws,
+                    size_t ws_bytes, void *stream);
 
-/* The network's k best plans (1 <= k <= 32) for op on A with dense width K,
- * in ascending predicted time, into out[0 .. *count) (host; *count <= k, the
- * number of plans valid for K).  Same features, network and workspace as
- * plan_select (whose plan is out[0]); a caller may time these few candidates
- * and keep the fastest, which guards against a mispredicted first choice at
- * the cost of a short timed search.  Synchronises `stream`. */
-int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t k, spk_plan *out, int32_t *count, void *ws,
-                  size_t ws_bytes, void *stream);
+/* The network's k best plans (1 <= k <= 32) for op on A with dense width K
+ * and dtype, in ascending predicted time, into out[0 .. *count) (host;
+ * *count <= k, the number of plans valid for K and dtype).  Same features,
+ * network and workspace as plan_select (whose plan is out[0]); a caller may
+ * time these few candidates and keep the fastest, which guards against a
+ * mispredicted first choice at the cost of a short timed search.
+ * Synchronises `stream`. */
+int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t dtype, int32_t k, spk_plan *out,
+                  int32_t *count, void *ws, size_t ws_bytes, void *stream);
 
 /* Rules of canonical CSR, as bits of spk_csr_validate's *rules.  The paper
  * sends CSR with 32-bit column indices (Section III-A) and leaves order and

@@ -98,17 +98,17 @@ SIGNATURES = {
     "csr_row_index": ([_CSR_P, _P, _P], _I32),
     "sddmm_coo": ([_CSR_P, _P, _P, _I64, _P, _I64, _I32, _I64, _P, _PLAN_P, _P], _I32),
     "plan_count": ([_I32], _I32),
-    "plan_of_index": ([_I32, _I32, _I64, _PLAN_P, ctypes.POINTER(_I32)], _I32),
+    "plan_of_index": ([_I32, _I32, _I64, _I32, _PLAN_P, ctypes.POINTER(_I32)], _I32),
     "csr_features": ([_CSR_P, _P, _P, _SZ, _P], _I32),
-    "selector_inputs": ([_P, _I64, _P, _P], _I32),
+    "selector_inputs": ([_P, _I64, _I32, _P, _P], _I32),
     "mlp_forward": ([_P, _I64, _I64, _I64, _P, _I64, _P, _P], _I32),
     "mlp_workspace_bytes": ([_I64, _I64, _I64, _I64], _SZ),
     "mlp_loss_grad": ([_P, _I64, _I64, _I64, _P, _P, _P, _I64, _P, _P, _P, _SZ, _P], _I32),
     "adam_update": ([_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I64,
                      _P], _I32),
     "selector_load": ([_I32, _P, _I64, _I64, _I64], _I32),
-    "plan_select": ([_CSR_P, _I64, _I32, _PLAN_P, _P, _SZ, _P], _I32),
-    "plan_rank": ([_CSR_P, _I64, _I32, _I32, _PLAN_P, ctypes.POINTER(_I32), _P, _SZ, _P], _I32),
+    "plan_select": ([_CSR_P, _I64, _I32, _I32, _PLAN_P, _P, _SZ, _P], _I32),
+    "plan_rank": ([_CSR_P, _I64, _I32, _I32, _I32, _PLAN_P, ctypes.POINTER(_I32), _P, _SZ, _P], _I32),
 }
 
 _lib = None

@@ -53,7 +53,7 @@ def plans_for(op: int, K: int, dtype: torch.dtype = torch.float32) -> list[api.P
         return spmm_plans(K, dtype) if op == OP_SPMM else sddmm_plans(K, dtype)
     from . import selector
 
-    return [p for p, ok in selector.plan_list(op, K) if ok]
+    return [p for p, ok in selector.plan_list(op, K, selector.dtype_code(dtype)) if ok]
 
 
 def time_plan(A: api.CSR, K: int, op: int, plan: api.Plan | None, B=None, U=None, V=None, reps: int = 5,

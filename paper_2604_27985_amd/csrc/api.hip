@@ -759,33 +759,54 @@ static int current_device() {
     return d;
 }
 
-int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 24 : op == SPK_OP_SDDMM ? 23 : 0; }
+int32_t plan_count(int32_t op) { return op == SPK_OP_SPMM ? 30 : op == SPK_OP_SDDMM ? 29 : 0; }
 
-int32_t plan_of_index(int32_t op, int32_t index, int64_t K, spk_plan *out, int32_t *valid) {
+int32_t plan_of_index(int32_t op, int32_t index, int64_t K, int32_t dtype, spk_plan *out, int32_t *valid) {
     if (!out) return SPK_ERR_NULL;
     if (op != SPK_OP_SPMM && op != SPK_OP_SDDMM) return SPK_ERR_OP;
+    if (dtype != SPK_F32 && dtype != SPK_BF16 && dtype != SPK_F64) return SPK_ERR_DTYPE;
     if (index < 0 || index >= plan_count(op)) return SPK_ERR_PLAN;
+    const int64_t k = K > 0 ? K : 1;
+    // widths below are in F32 rows (BF16 slabs take half the bytes)
+    const int32_t tile_first = op == SPK_OP_SPMM ? 16 : 15;
+    const int32_t wide_first = op == SPK_OP_SPMM ? 24 : 23;
+    int32_t sddmm_lanes = 8;  // the default SDDMM group, widened until K fits 8 register slices
+    while (sddmm_lanes < 64 && (k + sddmm_lanes * 4 - 1) / (sddmm_lanes * 4) > 8) sddmm_lanes <<= 1;
+    const int32_t tile_lanes =
+        op == SPK_OP_SDDMM && default_spmm_lanes(K) < 16 ? 16 : default_spmm_lanes(K);  // SDDMM TILE: 16-lane rows
+    const int32_t row_lanes = op == SPK_OP_SPMM ? default_spmm_lanes(K) : sddmm_lanes;
+    auto slab16_width = [&](int64_t bytes) {
+        int64_t w = bytes / (4 * k);
+        return static_cast<int32_t>(w < 256 ? 256 : w > 65536 ? 65536 : w);
+    };
     if (op == SPK_OP_SPMM && index == 15) {
         *out = spk_plan{SPK_VAR_BSR4, 64, 0, 0};
-    } else if ((op == SPK_OP_SPMM && index >= 16) || (op == SPK_OP_SDDMM && index >= 15)) {
-        // LDS slabs of 16 or 32 KiB of F32 rows (half that for BF16), 4 or 8
-        // rows per lane group; the last four split the work one entry per
-        // quad (16 KiB slabs, then 32 KiB)
-        const int t = index - (op == SPK_OP_SPMM ? 16 : 15);
+    } else if (index >= tile_first && index < wide_first) {
+        // LDS slabs of 16 or 32 KiB, 4 or 8 rows per lane group; the last
+        // four split the work one entry per quad (16 KiB slabs, then 32 KiB)
+        const int t = index - tile_first;
         const int64_t bytes = (t < 4 ? t % 2 == 1 : t >= 6) ? 32768 : 16384;
-        const int64_t k = K > 0 ? K : 1;
         const int64_t w = bytes / (4 * k);
-        int32_t lanes = default_spmm_lanes(K);
-        if (op == SPK_OP_SDDMM && lanes < 16) lanes = 16;  // SDDMM TILE reduces over 16-lane rows
         const int32_t flags = t < 4 ? (t >= 2 ? 2 : 0) : 4 | (t % 2 == 1 ? 2 : 0);
-        *out = spk_plan{SPK_VAR_TILE, lanes, static_cast<int32_t>(w > 0 ? w : 1), flags};
+        *out = spk_plan{SPK_VAR_TILE, tile_lanes, static_cast<int32_t>(w > 0 ? w : 1), flags};
+    } else if (index == wide_first || index == wide_first + 1) {
+        // one entry per quad in wide workgroups, slabs of 32 or 64 KiB
+        const int64_t w = (index == wide_first ? 32768 : 65536) / (4 * k);
+        *out = spk_plan{SPK_VAR_TILE, tile_lanes, static_cast<int32_t>(w > 0 ? w : 1), 12};
+    } else if (index == wide_first + 2 || index == wide_first + 3) {
+        // column-slab form: 2 or 8 MiB of the dense operand per slab
+        *out = spk_plan{SPK_VAR_SLAB16, row_lanes, slab16_width(index == wide_first + 2 ? 2 << 20 : 8 << 20), 0};
+    } else if (index == wide_first + 4) {
+        *out = spk_plan{SPK_VAR_DCSR, row_lanes, 0, 0};
+    } else if (index == wide_first + 5) {
+        *out = op == SPK_OP_SPMM ? spk_plan{SPK_VAR_DCSR, 4, 0, 0} : spk_plan{SPK_VAR_COO, 16, 16, 0};
     } else {
         static const int32_t variants[3] = {SPK_VAR_ROWS, SPK_VAR_MERGE, SPK_VAR_SLAB};
         const int32_t v = variants[index / 5];
         const int32_t chunk = (op == SPK_OP_SDDMM && v == SPK_VAR_MERGE) ? 256 : 0;
         *out = spk_plan{v, 4 << (index % 5), chunk, 0};
     }
-    if (valid) *valid = plan_valid_host(op, index, K) ? 1 : 0;
+    if (valid) *valid = plan_valid_host(op, index, K, dtype) ? 1 : 0;
     return SPK_OK;
 }
 
@@ -798,10 +819,11 @@ int32_t csr_features(const spk_csr *A, int64_t *features, void *ws, size_t ws_by
                                       static_cast<hipStream_t>(stream)));
 }
 
-int32_t selector_inputs(const int64_t *features, int64_t K, float *x, void *stream) {
+int32_t selector_inputs(const int64_t *features, int64_t K, int32_t dtype, float *x, void *stream) {
     if (!features || !x) return SPK_ERR_NULL;
     if (K < 0) return SPK_ERR_SIZE;
-    return hip_status(inputs_launch(features, K, x, static_cast<hipStream_t>(stream)));
+    if (dtype != SPK_F32 && dtype != SPK_BF16 && dtype != SPK_F64) return SPK_ERR_DTYPE;
+    return hip_status(inputs_launch(features, K, dtype, x, static_cast<hipStream_t>(stream)));
 }
 
 int32_t mlp_forward(const float *params, int64_t F, int64_t H, int64_t P, const float *X, int64_t batch, float *Y,
@@ -838,7 +860,7 @@ int32_t adam_update(float *params, const float *grads, float *mom, float *vel, i
 int32_t selector_load(int32_t op, const float *table, int64_t F, int64_t H, int64_t P) {
     if (op != SPK_OP_SPMM && op != SPK_OP_SDDMM) return SPK_ERR_OP;
     if (!table) return SPK_ERR_NULL;
-    if (F != 32 || !mlp_dims_ok(F, H, P) || P != plan_count(op)) return SPK_ERR_SIZE;
+    if (F != 33 || !mlp_dims_ok(F, H, P) || P != plan_count(op)) return SPK_ERR_SIZE;
     const int dev = current_device();
     if (dev < 0) return SPK_ERR_HIP;
     int32_t st = hip_status(selector_table_load(op, table, F, H, P));
@@ -850,10 +872,11 @@ int32_t selector_load(int32_t op, const float *table, int64_t F, int64_t H, int6
     return SPK_OK;
 }
 
-int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t k, spk_plan *out, int32_t *count, void *ws,
-                  size_t ws_bytes, void *stream) {
+int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t dtype, int32_t k, spk_plan *out, int32_t *count,
+                  void *ws, size_t ws_bytes, void *stream) {
     int32_t st = check_csr(A);
     if (st) return st;
+    if (dtype != SPK_F32 && dtype != SPK_BF16 && dtype != SPK_F64) return SPK_ERR_DTYPE;
     if (!out || !count) return SPK_ERR_NULL;
     if (k < 1 || k > kRankSlots) return SPK_ERR_SIZE;
     if (K < 0 || K > kMaxIndex) return SPK_ERR_SIZE;
@@ -870,21 +893,22 @@ int32_t plan_rank(const spk_csr *A, int64_t K, int32_t op, int32_t k, spk_plan *
     if ((st = hip_status(features_launch(A->m, A->n, A->nnz, A->row_ptr, A->col_idx, f, w + f_bytes + o_bytes, s))))
         return st;
     const int64_t *d = g_dims[dev][op];
-    if ((st = hip_status(select_launch(op, f, K, d[0], d[1], d[2], idx, s)))) return st;
+    if ((st = hip_status(select_launch(op, f, K, dtype, d[0], d[1], d[2], idx, s)))) return st;
     int32_t host[kRankSlots];
     if (hipMemcpyAsync(host, idx, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess) return SPK_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return SPK_ERR_HIP;
     int32_t c = 0;
     for (; c < k && host[c] >= 0; ++c)
-        if ((st = plan_of_index(op, host[c], K, &out[c], nullptr))) return st;
+        if ((st = plan_of_index(op, host[c], K, dtype, &out[c], nullptr))) return st;
     *count = c;
     return c > 0 ? SPK_OK : SPK_ERR_PLAN;
 }
 
-int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, spk_plan *out, void *ws, size_t ws_bytes, void *stream) {
+int32_t plan_select(const spk_csr *A, int64_t K, int32_t op, int32_t dtype, spk_plan *out, void *ws, size_t ws_bytes,
+                    void *stream) {
     if (!out) return SPK_ERR_NULL;
     int32_t count = 0;
-    return plan_rank(A, K, op, 1, out, &count, ws, ws_bytes, stream);
+    return plan_rank(A, K, op, dtype, 1, out, &count, ws, ws_bytes, stream);
 }
 
 int32_t spk_csr_validate(const spk_csr *A, int32_t *rules, void *ws, size_t ws_bytes, void *stream) {

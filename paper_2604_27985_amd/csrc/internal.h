@@ -125,7 +125,7 @@ hipError_t bsr4_spmm_launch(const Bsr4Args &a, hipStream_t s);
 size_t features_ws_bytes(int64_t m);
 hipError_t features_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, int64_t *f,
                            void *ws, hipStream_t s);
-hipError_t inputs_launch(const int64_t *f, int64_t K, float *x, hipStream_t s);
+hipError_t inputs_launch(const int64_t *f, int64_t K, int32_t dtype, float *x, hipStream_t s);
 bool mlp_dims_ok(int64_t F, int64_t H, int64_t P);
 hipError_t mlp_forward_launch(const float *params, int64_t F, int64_t H, int64_t P, const float *X, int64_t batch,
                               float *Y, hipStream_t s);
@@ -135,9 +135,9 @@ hipError_t mlp_loss_grad_launch(const float *params, int64_t F, int64_t H, int64
 hipError_t adam_launch(float *w, const float *g, float *mom, float *vel, int64_t count, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t s);
 hipError_t selector_table_load(int32_t op, const float *host_table, int64_t F, int64_t H, int64_t P);
-hipError_t select_launch(int32_t op, const int64_t *f, int64_t K, int64_t F, int64_t H, int64_t P, int32_t *out,
-                         hipStream_t s);
-bool plan_valid_host(int32_t op, int idx, int64_t K);
+hipError_t select_launch(int32_t op, const int64_t *f, int64_t K, int32_t dtype, int64_t F, int64_t H, int64_t P,
+                         int32_t *out, hipStream_t s);
+bool plan_valid_host(int32_t op, int idx, int64_t K, int32_t dtype);
 
 // In-place exclusive scan of int32 values (transpose.hip).
 size_t scan_ws_bytes_i32(int64_t count);

@@ -2,10 +2,10 @@
 //
 //   features   integer structural counts of a CSR pattern (row-length
 //              histogram, lengths, bandwidth, 4x4-block count)
-//   inputs     32 scaled inputs from the features and the dense width K
+//   inputs     33 scaled inputs from the features, the dense width K and dtype
 //   MLP        three affine layers with ReLU between them; one output per
 //              plan of the op's plan list, predicting log(time / best time)
-//   select     argmin of the outputs over the plans valid for K
+//   select     argmin of the outputs over the plans valid for K and dtype
 //   training   batched forward, hand-derived backward of the masked mean
 //              squared error, and Adam; every reduction runs in a fixed order,
 //              so gradients are reproducible bit for bit
@@ -20,7 +20,7 @@
 namespace spk {
 
 constexpr int kNFeat = 28;
-constexpr int kNIn = 32;
+constexpr int kNIn = 33;
 constexpr int kMaxIn = 64, kMaxHidden = 128, kMaxOut = 32;
 constexpr int kTable = 2 * kMaxIn + kMaxHidden * kMaxIn + kMaxHidden + kMaxHidden * kMaxHidden + kMaxHidden +
                        kMaxOut * kMaxHidden + kMaxOut;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void features_blocks_lds_kernel(int64_t m, 
 }
 
 // ---------------------------------------------------------------- inputs
-__device__ void inputs_of(const long long *f, int64_t K, float *x) {
+__device__ void inputs_of(const long long *f, int64_t K, int32_t dtype, float *x) {
     const float m = static_cast<float>(f[0]), n = static_cast<float>(f[1]), nnz = static_cast<float>(f[2]);
     const float md = m > 0 ? m : 1.f, nd = n > 0 ? n : 1.f, zd = nnz > 0 ? nnz : 1.f;
     x[0] = log2f(1.f + m) / 20.f;
@@ -196,12 +196,13 @@ __device__ void inputs_of(const long long *f, int64_t K, float *x) {
     const float dens = nnz / (md * nd);
     x[30] = 1.f + log10f(dens > 1e-12f ? dens : 1e-12f) / 5.f;
     x[31] = 1.f;
+    x[32] = dtype == SPK_BF16 ? 1.f : 0.f;
 }
 
-__global__ void inputs_kernel(const long long *__restrict__ f, int64_t K, float *__restrict__ x) {
+__global__ void inputs_kernel(const long long *__restrict__ f, int64_t K, int32_t dtype, float *__restrict__ x) {
     if (threadIdx.x == 0) {
         float t[kNIn];
-        inputs_of(f, K, t);
+        inputs_of(f, K, dtype, t);
         for (int i = 0; i < kNIn; ++i) x[i] = t[i];
     }
 }
@@ -233,29 +234,42 @@ __device__ void mlp_eval(const float *__restrict__ p, Dims d, const float *x, fl
     __syncthreads();
 }
 
-// Plans of an op that suit width K (mirrors the plan lists in plan_of).
-__device__ __host__ inline bool plan_valid(int32_t op, int idx, int64_t K) {
+// Plans of an op that suit width K and dense dtype (mirrors the plan lists
+// of plan_of_index in api.hip).
+__device__ __host__ inline bool quad_fits(int32_t op, int64_t K, int32_t dtype) {
+    const int64_t row = K * (dtype == SPK_BF16 ? 2 : 4);
+    return row == 128 || row == 256 || (row == 512 && (op == SPK_OP_SDDMM || dtype == SPK_F32));
+}
+
+__device__ __host__ inline bool plan_valid(int32_t op, int idx, int64_t K, int32_t dtype) {
+    const bool tile_ok = K >= 8 && K <= 256 && K % 8 == 0;  // LDS slabs: 16-byte pieces of F32 and BF16 rows
+    if (dtype == SPK_F64 && idx >= 15) return false;  // block, slab, compressed forms: F32 and BF16 only
     if (op == SPK_OP_SPMM) {
-        if (idx == 15) return true;  // 4x4 blocks on matrix cores
-        if (idx >= 16) return K >= 8 && K <= 256 && K % 8 == 0;  // LDS slabs: 16-byte pieces of F32 and BF16 rows
+        if (idx == 15) return true;                   // 4x4 blocks on matrix cores
+        if (idx >= 16 && idx <= 24) return tile_ok;   // TILE (24: wide, 32 KiB slabs)
+        if (idx == 25) return tile_ok && quad_fits(op, K, dtype);  // wide, 64 KiB slabs
+        if (idx >= 26) return true;                   // column-slab form, doubly compressed rows
         const int lanes = 4 << (idx % 5);
         int64_t cap = 16;
         while (cap < K) cap <<= 1;
         return lanes == 4 || lanes * 4 <= 2 * cap;
     }
-    if (idx >= 15) return K >= 8 && K <= 256 && K % 8 == 0;  // LDS slabs of V
+    if (idx >= 15 && idx <= 23) return tile_ok;  // TILE of V (23: wide, 32 KiB slabs)
+    if (idx == 24) return tile_ok && quad_fits(op, K, dtype);
+    if (idx >= 25 && idx <= 27) return true;  // column-slab form, doubly compressed rows
+    if (idx == 28) return K <= 512;           // COO entries, 16 lanes: at most 8 slices of 64 columns
     const int lanes = 4 << (idx % 5);
     const int64_t ns = (K + lanes * 4 - 1) / (lanes * 4);
     return ns <= 8 && (lanes == 4 || lanes * 4 <= 2 * (K > 4 ? K : 4));
 }
 
 __global__ __launch_bounds__(kMaxHidden) void select_kernel(int32_t op, const long long *__restrict__ f, int64_t K,
-                                                            Dims d, int32_t *__restrict__ out) {
+                                                            int32_t dtype, Dims d, int32_t *__restrict__ out) {
     __shared__ float x[kMaxIn], a1[kMaxHidden], a2[kMaxHidden], y[kMaxOut];
     const float *tab = g_table[op];
     if (threadIdx.x == 0) {
         float t[kNIn];
-        inputs_of(f, K, t);
+        inputs_of(f, K, dtype, t);
         for (int i = 0; i < d.F; ++i) x[i] = (i < kNIn ? t[i] : 0.f);
     }
     __syncthreads();
@@ -270,7 +284,7 @@ __global__ __launch_bounds__(kMaxHidden) void select_kernel(int32_t op, const lo
         for (int r = 0; r < kMaxOut; ++r) {
             int best = -1;
             for (int p = 0; p < d.P; ++p)
-                if (!taken[p] && plan_valid(op, p, K) && (best < 0 || y[p] < y[best])) best = p;
+                if (!taken[p] && plan_valid(op, p, K, dtype) && (best < 0 || y[p] < y[best])) best = p;
             out[r] = best;
             if (best >= 0) taken[best] = true;
         }
@@ -456,8 +470,8 @@ hipError_t features_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
     return hipGetLastError();
 }
 
-hipError_t inputs_launch(const int64_t *f, int64_t K, float *x, hipStream_t s) {
-    hipLaunchKernelGGL(inputs_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<const long long *>(f), K, x);
+hipError_t inputs_launch(const int64_t *f, int64_t K, int32_t dtype, float *x, hipStream_t s) {
+    hipLaunchKernelGGL(inputs_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<const long long *>(f), K, dtype, x);
     return hipGetLastError();
 }
 
@@ -524,14 +538,14 @@ hipError_t selector_table_load(int32_t op, const float *host_table, int64_t F, i
     return hipMemcpyToSymbol(HIP_SYMBOL(g_table), staging, sizeof(staging), sizeof(staging) * op, hipMemcpyHostToDevice);
 }
 
-hipError_t select_launch(int32_t op, const int64_t *f, int64_t K, int64_t F, int64_t H, int64_t P, int32_t *out,
-                         hipStream_t s) {
+hipError_t select_launch(int32_t op, const int64_t *f, int64_t K, int32_t dtype, int64_t F, int64_t H, int64_t P,
+                         int32_t *out, hipStream_t s) {
     Dims d{static_cast<int>(F), static_cast<int>(H), static_cast<int>(P)};
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kMaxHidden), 0, s, op, reinterpret_cast<const long long *>(f), K, d,
-                       out);
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kMaxHidden), 0, s, op, reinterpret_cast<const long long *>(f), K,
+                       dtype, d, out);
     return hipGetLastError();
 }
 
-bool plan_valid_host(int32_t op, int idx, int64_t K) { return plan_valid(op, idx, K); }
+bool plan_valid_host(int32_t op, int idx, int64_t K, int32_t dtype) { return plan_valid(op, idx, K, dtype); }
 
 }  // namespace spk

@@ -29,7 +29,7 @@ import torch
 from . import _lib, api, synth
 from ._lib import OP_SDDMM, OP_SELECT, OP_SPMM
 
-F, H = 32, 64
+F, H = 33, 64
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector_weights.json")
 PATTERNS = ("uniform", "banded", "powerlaw", "block4")
 KS = (32, 64, 128, 256)
@@ -41,14 +41,29 @@ def plan_count(op: int) -> int:
     return int(_lib.load().plan_count(op))
 
 
-def plan_list(op: int, K: int) -> list[tuple[api.Plan, bool]]:
-    """[(plan, valid for K)] in the op's plan-list order (include/spk.h)."""
+DTYPES = {"f32": _lib.F32, "bf16": _lib.BF16}
+TORCH_DTYPES = {"f32": torch.float32, "bf16": torch.bfloat16}
+
+
+def dtype_code(t) -> int:
+    """spk_dtype of a torch dtype, a tensor, or a record's dtype name (F32 for None)."""
+    if t is None:
+        return _lib.F32
+    if isinstance(t, str):
+        return DTYPES[t]
+    if isinstance(t, torch.Tensor):
+        t = t.dtype
+    return {torch.float32: _lib.F32, torch.bfloat16: _lib.BF16, torch.float64: _lib.F64}[t]
+
+
+def plan_list(op: int, K: int, dtype: int = _lib.F32) -> list[tuple[api.Plan, bool]]:
+    """[(plan, valid for K and the dense dtype)] in the op's plan-list order (include/spk.h)."""
     lib = _lib.load()
     out = []
     for i in range(plan_count(op)):
         p = _lib.spk_plan()
         v = ctypes.c_int32(0)
-        _lib.check(lib.plan_of_index(op, i, K, ctypes.byref(p), ctypes.byref(v)), "plan_of_index")
+        _lib.check(lib.plan_of_index(op, i, K, dtype, ctypes.byref(p), ctypes.byref(v)), "plan_of_index")
         out.append((api.Plan(p.variant, p.lanes, p.chunk, p.flags), bool(v.value)))
     return out
 
@@ -62,6 +77,8 @@ def sample_spec(index: int, cap: int = NNZ_CAP) -> dict:
     workloads (N x N up to N = 65536 at 90-99.9% sparsity, and denser): n
     log-uniform in [8192, 131072], density log-uniform in [1e-3, 0.3] (at most
     LARGE_CAP expected entries), half of them uniform."""
+    if index >= BF16_FIRST:
+        return _bf16_spec(index)
     if index >= LARGE_FIRST:
         return _large_spec(index)
     rng = np.random.default_rng([2604, 27985, index])
@@ -78,6 +95,22 @@ def sample_spec(index: int, cap: int = NNZ_CAP) -> dict:
 
 LARGE_FIRST = 2000
 LARGE_CAP = 6e8
+BF16_FIRST, BF16_LAST = 3000, 3600
+
+
+def _bf16_spec(index: int) -> dict:
+    """BF16 dense operands: the first family's distribution with K in {64, 128,
+    256} (the BF16 workload's widths)."""
+    rng = np.random.default_rng([2604, 27985, 2, index])
+    pattern = PATTERNS[int(rng.integers(len(PATTERNS)))]
+    K = (64, 128, 256)[int(rng.integers(3))]
+    while True:
+        n = int(round(math.exp(rng.uniform(math.log(4096), math.log(524288))) / 64) * 64)
+        d = math.exp(rng.uniform(math.log(1e-4), math.log(0.1)))
+        if expected_nnz(n, d, pattern) <= NNZ_CAP:
+            break
+    return {"index": index, "n": n, "density": d, "pattern": pattern, "K": K, "seed": index, "dtype": "bf16",
+            "split": "test" if index % 5 == 0 else "train"}
 
 
 def _large_spec(index: int) -> dict:
@@ -130,27 +163,28 @@ def features(A: api.CSR) -> torch.Tensor:
     return f
 
 
-def inputs(f: torch.Tensor, K: int) -> torch.Tensor:
-    """The 32 network inputs (device float32) of features f and width K."""
+def inputs(f: torch.Tensor, K: int, dtype: int = _lib.F32) -> torch.Tensor:
+    """The 33 network inputs (device float32) of features f, width K and dense dtype."""
     lib = _lib.load()
     x = torch.empty(F, dtype=torch.float32, device=f.device)
-    _lib.check(lib.selector_inputs(ctypes.c_void_p(f.data_ptr()), K, ctypes.c_void_p(x.data_ptr()), api._stream()),
-               "selector_inputs")
+    _lib.check(lib.selector_inputs(ctypes.c_void_p(f.data_ptr()), K, dtype, ctypes.c_void_p(x.data_ptr()),
+                                   api._stream()), "selector_inputs")
     return x
 
 
 # ---------------------------------------------------------------- timings
 def time_plans(A: api.CSR, K: int, op: int, reps: int = 3, warmup: int = 1,
-               indices: list[int] | None = None) -> list[float | None]:
+               indices: list[int] | None = None, dtype: str = "f32") -> list[float | None]:
     """Median ms of every plan of the op's list, or of the plans `indices`
-    only (None where invalid for K)."""
+    only (None where invalid for K and dtype), dense operands of `dtype`."""
     from . import autotune
 
     dev = A.row_ptr.device
-    B = torch.randn(A.n, K, device=dev)
-    U = torch.randn(A.m, K, device=dev) if op == OP_SDDMM else None
+    tdt = TORCH_DTYPES[dtype]
+    B = torch.randn(A.n, K, device=dev).to(tdt)
+    U = torch.randn(A.m, K, device=dev).to(tdt) if op == OP_SDDMM else None
     out = []
-    plans = plan_list(op, K)
+    plans = plan_list(op, K, dtype_code(dtype))
     for plan, valid in (plans if indices is None else [plans[i] for i in indices]):
         if not valid:
             out.append(None)
@@ -184,7 +218,8 @@ def build_timings(path: str, count: int = 2000, start: int = 0, ops=(OP_SPMM, OP
             f = features(dA)
             rec = dict(spec, nnz=A.nnz, features=f.cpu().tolist(), gen_s=round(time.time() - tg, 3))
             for op in ops:
-                rec["ms_" + ("spmm" if op == OP_SPMM else "sddmm")] = time_plans(dA, spec["K"], op)
+                rec["ms_" + ("spmm" if op == OP_SPMM else "sddmm")] = time_plans(dA, spec["K"], op,
+                                                                                 dtype=spec.get("dtype", "f32"))
             fh.write(json.dumps(rec) + "\n")
             fh.flush()
             added += 1
@@ -224,12 +259,11 @@ def extend_timings(path: str, out_path: str, op: int, indices: list[int], log=pr
             A, v = make_matrix(spec)
             assert A.nnz == rec["nnz"], f"matrix {i} does not regenerate"
             dA = api.CSR.from_host(A, v)
-            ms = time_plans(dA, spec["K"], op, indices=indices)
+            ms = time_plans(dA, spec["K"], op, indices=indices, dtype=rec.get("dtype", "f32"))
             fh.write(json.dumps({"index": i, "op": key, "plans": indices, "ms": ms}) + "\n")
             fh.flush()
             added += 1
-            if added % 50 == 0:
-                log(f"[{i}] {added} matrices extended ({time.time() - t0:.0f} s)")
+            log(f"[{i}] n={spec['n']} nnz={A.nnz} K={spec['K']}: {added} matrices extended ({time.time() - t0:.0f} s)")
             del dA
     return added
 
@@ -268,7 +302,8 @@ def dataset(records: list[dict], op: int):
     P = plan_count(op)
     dev = torch.device("cuda")
     feats = torch.tensor([r["features"] for r in records], dtype=torch.int64, device=dev)
-    X = torch.stack([inputs(feats[i].contiguous(), r["K"]) for i, r in enumerate(records)]).cpu().numpy()
+    X = torch.stack([inputs(feats[i].contiguous(), r["K"], dtype_code(r.get("dtype")))
+                     for i, r in enumerate(records)]).cpu().numpy()
     times = np.full((len(records), P), np.nan)
     for i, r in enumerate(records):
         for p, t in enumerate(r[key]):
@@ -379,8 +414,20 @@ def plain_index(op: int, K: int) -> int:
     return 5 + int(math.log2(lanes)) - 2
 
 
-def train_op(records: list[dict], op: int, steps: int = 4000, lr: float = 3e-3, seed: int = 0, log=None):
-    """Train on the train split, evaluate on the test split; returns (table dict, report)."""
+def time_weights(times: np.ndarray, rows: np.ndarray, power: float) -> np.ndarray:
+    """Per-matrix loss weights (best time / median best time)^power, clipped to
+    [1/16, 16] and scaled to mean 1 over `rows`: with power > 0 the network
+    weighs the matrices whose time dominates a total more."""
+    best = np.nanmin(times, axis=1)
+    w = np.clip((best / np.median(best[rows])) ** power, 1.0 / 16, 16.0)
+    return (w / w[rows].mean()).astype(np.float32)
+
+
+def train_op(records: list[dict], op: int, steps: int = 4000, lr: float = 3e-3, seed: int = 0, log=None,
+             weight_power: float = 0.0):
+    """Train on the train split, evaluate on the test split; returns (table dict, report).
+    weight_power > 0 weighs each matrix's squared errors by its best time
+    (time_weights), which favours the total-time ratio."""
     X, T, mask, times = dataset(records, op)
     split = np.array([r["split"] for r in records])
     tr, te = split == "train", split == "test"
@@ -390,13 +437,18 @@ def train_op(records: list[dict], op: int, steps: int = 4000, lr: float = 3e-3, 
     Xs = ((X - mean) / scale).astype(np.float32)
     P = plan_count(op)
     trainer = Trainer(P, seed=seed)
-    hist = trainer.fit(Xs[tr], T[tr], mask[tr], steps=steps, lr=lr, log=log)
+    wmask = mask * time_weights(times, tr, weight_power)[:, None] if weight_power > 0 else mask
+    hist = trainer.fit(Xs[tr], T[tr], wmask[tr], steps=steps, lr=lr, log=log)
     Y = trainer.forward(torch.from_numpy(Xs).cuda()).cpu().numpy()
     pick = choose(Y, mask)
     plain = np.array([plain_index(op, r["K"]) for r in records])
-    report = {"op": "spmm" if op == OP_SPMM else "sddmm", "loss_history": hist,
+    report = {"op": "spmm" if op == OP_SPMM else "sddmm", "loss_history": hist, "weight_power": weight_power,
               "train": regret_stats(times[tr], pick[tr], plain[tr]),
               "test": regret_stats(times[te], pick[te], plain[te])}
+    bf = np.array([r.get("dtype", "f32") == "bf16" for r in records])
+    if (te & bf).any():
+        report["test_bf16"] = regret_stats(times[te & bf], pick[te & bf], plain[te & bf])
+        report["test_f32"] = regret_stats(times[te & ~bf], pick[te & ~bf], plain[te & ~bf])
     for k in (3, 5):
         pk = best_of_top(Y, mask, times, k)
         report[f"test_best_of_top{k}"] = regret_stats(times[te], pk[te], plain[te])
@@ -442,12 +494,14 @@ def offline_choices(table: dict, records: list[dict]) -> np.ndarray:
     tr = Trainer(table["P"], table["H"])
     tr.params = torch.tensor(table["params"], dtype=torch.float32, device="cuda")
     Y = tr.forward(torch.from_numpy(Xs).cuda()).cpu().numpy()
-    valid = np.array([[ok for _, ok in plan_list(op, r["K"])] for r in records], np.float32)
+    valid = np.array([[ok for _, ok in plan_list(op, r["K"], dtype_code(r.get("dtype")))] for r in records],
+                     np.float32)
     return choose(Y, valid)
 
 
-def rank(A: api.CSR, K: int, op: int, k: int) -> list[api.Plan]:
-    """The network's k best plans for (A, K, op), best first (plan_rank)."""
+def rank(A: api.CSR, K: int, op: int, k: int, dtype: int = _lib.F32) -> list[api.Plan]:
+    """The network's k best plans for (A, K, op) with dense operands of
+    `dtype`, best first (plan_rank)."""
     lib = _lib.load()
     load_default()
     nb = api.workspace_bytes(OP_SELECT, A, K)
@@ -455,8 +509,8 @@ def rank(A: api.CSR, K: int, op: int, k: int) -> list[api.Plan]:
     ca = A.c(use_vals=False)
     out = (_lib.spk_plan * k)()
     count = ctypes.c_int32(0)
-    st = lib.plan_rank(ctypes.byref(ca), K, op, k, out, ctypes.byref(count), ctypes.c_void_p(ws.data_ptr()), nb,
-                       api._stream())
+    st = lib.plan_rank(ctypes.byref(ca), K, op, dtype, k, out, ctypes.byref(count), ctypes.c_void_p(ws.data_ptr()),
+                       nb, api._stream())
     _lib.check(st, "plan_rank")
     return [api.Plan(p.variant, p.lanes, p.chunk, p.flags) for p in out[:count.value]]
 
@@ -469,9 +523,10 @@ def select(A: api.CSR, K: int, op: int, fallback: bool = True, verify: int = 1, 
     fastest: a short timed search that guards against a mispredicted first
     choice."""
     lib = _lib.load()
+    dt = dtype_code(B if op == OP_SPMM else U)
     if verify > 1:
         try:
-            cands = rank(A, K, op, verify)
+            cands = rank(A, K, op, verify, dt)
         except _lib.SpkError as e:
             if e.status != -10 or not fallback:
                 raise
@@ -483,8 +538,9 @@ def select(A: api.CSR, K: int, op: int, fallback: bool = True, verify: int = 1, 
         if op == OP_SPMM and B is None:
             B = torch.randn(A.n, K, device=A.row_ptr.device)
         if op == OP_SDDMM and (U is None or V is None):
-            U = torch.randn(A.m, K, device=A.row_ptr.device)
-            V = torch.randn(A.n, K, device=A.row_ptr.device)
+            tdt = U.dtype if U is not None else torch.float32
+            U = torch.randn(A.m, K, device=A.row_ptr.device).to(tdt)
+            V = torch.randn(A.n, K, device=A.row_ptr.device).to(tdt)
         timed = []
         for p in cands:
             if p.variant == _lib.VAR_BSR4:
@@ -496,7 +552,7 @@ def select(A: api.CSR, K: int, op: int, fallback: bool = True, verify: int = 1, 
     ws = torch.empty(nb, dtype=torch.uint8, device=A.row_ptr.device)
     ca = A.c(use_vals=False)
     out = _lib.spk_plan()
-    st = lib.plan_select(ctypes.byref(ca), K, op, ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), nb,
+    st = lib.plan_select(ctypes.byref(ca), K, op, dt, ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), nb,
                          api._stream())
     if st == -10 and fallback:
         from . import autotune
@@ -534,6 +590,8 @@ def main(argv=None) -> None:
     t.add_argument("--steps", type=int, default=4000)
     t.add_argument("--lr", type=float, default=3e-3)
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--weight-power", type=float, default=0.0,
+                   help="weigh each matrix by (best time / median)^p in the loss")
     t.add_argument("--ops", default="spmm,sddmm",
                    help="ops to train; the other ops' tables are kept from --out")
     args = ap.parse_args(argv)
@@ -563,7 +621,8 @@ def main(argv=None) -> None:
             if op in kept:
                 tables.append(kept[op])
             continue
-        table, report = train_op(records, op, steps=args.steps, lr=args.lr, seed=args.seed, log=log)
+        table, report = train_op(records, op, steps=args.steps, lr=args.lr, seed=args.seed, log=log,
+                                 weight_power=args.weight_power)
         tables.append(table)
         reports.append(report)
         print(json.dumps({k: v for k, v in report.items() if k != "loss_history"}), flush=True)

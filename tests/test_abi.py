@@ -97,13 +97,14 @@ def test_plan_rank_argument_errors(lib):
     out = (_lib.spk_plan * 4)()
     count = ctypes.c_int32(-1)
     f = lib.plan_rank
-    assert f(ctypes.byref(A), 64, 0, 4, None, ctypes.byref(count), FAKE, 1 << 20, None) == -1
-    assert f(ctypes.byref(A), 64, 0, 4, out, None, FAKE, 1 << 20, None) == -1
-    assert f(ctypes.byref(A), 64, 0, 0, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
-    assert f(ctypes.byref(A), 64, 0, 33, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
-    assert f(ctypes.byref(A), -1, 0, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
-    assert f(ctypes.byref(A), 64, 7, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) < 0
-    assert f(None, 64, 0, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) == -1
+    assert f(ctypes.byref(A), 64, 0, 0, 4, None, ctypes.byref(count), FAKE, 1 << 20, None) == -1
+    assert f(ctypes.byref(A), 64, 0, 0, 4, out, None, FAKE, 1 << 20, None) == -1
+    assert f(ctypes.byref(A), 64, 0, 0, 0, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
+    assert f(ctypes.byref(A), 64, 0, 0, 33, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
+    assert f(ctypes.byref(A), -1, 0, 0, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) == -2
+    assert f(ctypes.byref(A), 64, 7, 0, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) < 0
+    assert f(ctypes.byref(A), 64, 0, 9, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) == -3  # dtype
+    assert f(None, 64, 0, 0, 4, out, ctypes.byref(count), FAKE, 1 << 20, None) == -1
     assert count.value == -1  # untouched on errors
 
 

@@ -53,12 +53,13 @@ def test_inputs_match_oracle(spk, sel):
     for (n, d, K) in [(3000, 0.01, 64), (777, 0.2, 33), (10, 0.0, 1)]:
         A = synth.bernoulli(n, n, d, 2)
         f = sel.features(spk.CSR.from_host(A))
-        x = sel.inputs(f, K).cpu().numpy().astype(np.float64)
-        ref = oracle.selector_inputs(f.cpu().numpy(), K)
-        assert np.allclose(x, ref, rtol=2e-6, atol=2e-7), (x - ref)
+        for dt in (0, 1):  # F32 and BF16 dense operands
+            x = sel.inputs(f, K, dt).cpu().numpy().astype(np.float64)
+            ref = oracle.selector_inputs(f.cpu().numpy(), K, dt)
+            assert np.allclose(x, ref, rtol=2e-6, atol=2e-7), (x - ref)
 
 
-def rand_params(P, H=64, F=32, seed=0):
+def rand_params(P, H=64, F=33, seed=0):
     r = np.random.default_rng(seed)
     W1, b1 = r.normal(size=(H, F)) / 4, r.normal(size=H) / 4
     W2, b2 = r.normal(size=(H, H)) / 8, r.normal(size=H) / 4
@@ -67,7 +68,7 @@ def rand_params(P, H=64, F=32, seed=0):
 
 
 def test_mlp_forward_grad_adam_match_oracle(spk, sel):
-    P, H, F, N = 16, 64, 32, 300
+    P, H, F, N = 16, 64, 33, 300
     parts = rand_params(P, H, F, 1)
     r = np.random.default_rng(2)
     X = r.normal(size=(N, F)).astype(np.float32)
@@ -108,9 +109,9 @@ def test_plan_select_matches_oracle_argmin(spk, sel):
     the same features (near-ties excluded)."""
     P = sel.plan_count(0)
     parts = rand_params(P, seed=3)
-    mean = np.linspace(0, 0.5, 32).astype(np.float32)
-    scale = np.linspace(0.5, 1.5, 32).astype(np.float32)
-    table = {"op": 0, "F": 32, "H": 64, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
+    mean = np.linspace(0, 0.5, 33).astype(np.float32)
+    scale = np.linspace(0.5, 1.5, 33).astype(np.float32)
+    table = {"op": 0, "F": 33, "H": 64, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
              "params": np.concatenate([a.reshape(-1) for a in parts]).tolist()}
     sel.load_table(table)
     sel._loaded.add(torch.cuda.current_device())  # keep select() from loading the shipped tables
@@ -120,18 +121,21 @@ def test_plan_select_matches_oracle_argmin(spk, sel):
                                    (500, 0.3, 16), (4096, 0.002, 100)]):
         A = synth.bernoulli(n, n, d, i)
         dA = spk.CSR.from_host(A)
-        plan = sel.select(dA, K, 0, fallback=False)
-        x = oracle.selector_inputs(oracle.features(A.row_ptr, A.col_idx, n), K)
-        y = net.forward(((x - mean) / scale)[None])[0]
-        valid = np.array([ok for _, ok in sel.plan_list(0, K)])
-        order = np.argsort(np.where(valid, y, np.inf))
-        if y[order[1]] - y[order[0]] < 1e-3:
-            continue
-        expect = sel.plan_list(0, K)[order[0]][0]
-        assert (plan.variant, plan.lanes, plan.chunk, plan.flags) == (expect.variant, expect.lanes, expect.chunk,
-                                                                      expect.flags)
-        checked += 1
-    assert checked >= 4
+        for dt in (0, 1):  # F32 and BF16 dense operands: the dtype input and the valid plans differ
+            plan = sel.rank(dA, K, 0, 1, dt)[0]
+            x = oracle.selector_inputs(oracle.features(A.row_ptr, A.col_idx, n), K, dt)
+            y = net.forward(((x - mean) / scale)[None])[0]
+            valid = np.array([ok for _, ok in sel.plan_list(0, K, dt)])
+            order = np.argsort(np.where(valid, y, np.inf))
+            if y[order[1]] - y[order[0]] < 1e-3:
+                continue
+            expect = sel.plan_list(0, K, dt)[order[0]][0]
+            assert (plan.variant, plan.lanes, plan.chunk, plan.flags) == (expect.variant, expect.lanes, expect.chunk,
+                                                                          expect.flags)
+            if dt == 0:
+                assert sel.select(dA, K, 0, fallback=False) == plan
+            checked += 1
+    assert checked >= 8
     sel._loaded.clear()
 
 
@@ -140,9 +144,9 @@ def test_plan_rank_matches_oracle_order(spk, sel):
     excluded); its first plan is plan_select's, and select(verify=k) keeps one of the k."""
     P = sel.plan_count(1)
     parts = rand_params(P, seed=4)
-    mean = np.linspace(0, 0.5, 32).astype(np.float32)
-    scale = np.linspace(0.5, 1.5, 32).astype(np.float32)
-    table = {"op": 1, "F": 32, "H": 64, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
+    mean = np.linspace(0, 0.5, 33).astype(np.float32)
+    scale = np.linspace(0.5, 1.5, 33).astype(np.float32)
+    table = {"op": 1, "F": 33, "H": 64, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
              "params": np.concatenate([a.reshape(-1) for a in parts]).tolist()}
     sel.load_table(table)
     sel._loaded.add(torch.cuda.current_device())
@@ -177,7 +181,7 @@ def test_training_reduces_loss(spk, sel):
     """A few hundred full-batch steps on a synthetic regression task."""
     P, N = 16, 512
     r = np.random.default_rng(4)
-    X = r.normal(size=(N, 32)).astype(np.float32)
+    X = r.normal(size=(N, 33)).astype(np.float32)
     T = np.abs(np.tanh(X[:, :P] * 0.7 + X[:, P:2 * P] * 0.3)).astype(np.float32)
     mask = np.ones((N, P), np.float32)
     tr = sel.Trainer(P, seed=5)

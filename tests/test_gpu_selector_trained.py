@@ -1,9 +1,9 @@
 """The shipped selector against the exhaustive search (GPU).
 
-The timing set (2250 seeded synthetic matrices: 2000 of up to 2^24 entries
-and 250 large ones in the regime of the paper's workloads, every plan timed
-on an MI355X) ships with the package; the network was trained on its train
-split (index % 5 != 0).  On the held-out split the learned plan must be within 10%
+The timing set (2850 seeded synthetic matrices: 2000 of up to 2^24 entries,
+250 large ones in the regime of the paper's workloads and 600 with BF16
+dense operands, every plan timed on an MI355X) ships with the package; the
+network was trained on its train split (index % 5 != 0).  On the held-out split the learned plan must be within 10%
 of the timed best in geometric mean, and the test reports what it gains over
 the plain method (NULL plan).  A few held-out matrices are regenerated and
 run through the full device path (plan_select) to check it picks what the
@@ -52,6 +52,11 @@ def test_held_out_regret_and_gain(sel, shipped, op):
     print(json.dumps(st))
     assert st["geomean_regret"] <= 1.10
     assert st["geomean_gain_over_plain"] > 1.0
+    bf = np.array([r.get("dtype") == "bf16" for r in test])
+    assert bf.sum() >= 100  # BF16 dense operands are part of the held-out split
+    stb = sel.regret_stats(times[bf], pick[bf], plain[bf])
+    print(json.dumps({"bf16": stb}))
+    assert stb["geomean_regret"] <= 1.10
 
 
 def test_device_path_picks_the_offline_choice(sel, shipped):
@@ -61,12 +66,14 @@ def test_device_path_picks_the_offline_choice(sel, shipped):
     sel._loaded.clear()
     assert sel.load_default()
     test = [r for r in records if r["split"] == "test" and r["nnz"] < 3_000_000][:12]
+    test += [r for r in records if r["split"] == "test" and r.get("dtype") == "bf16" and r["nnz"] < 3_000_000][:6]
     for op in (0, 1):
         pick = sel.offline_choices(tables[op], test)
         for r, p in zip(test, pick):
             A, v = sel.make_matrix(r)
             assert A.nnz == r["nnz"]
-            plan = sel.select(spk.CSR.from_host(A, v), r["K"], op, fallback=False)
-            expect = sel.plan_list(op, r["K"])[int(p)][0]
+            dt = sel.dtype_code(r.get("dtype"))
+            plan = sel.rank(spk.CSR.from_host(A, v), r["K"], op, 1, dt)[0]
+            expect = sel.plan_list(op, r["K"], dt)[int(p)][0]
             assert (plan.variant, plan.lanes, plan.chunk, plan.flags) == (
                 expect.variant, expect.lanes, expect.chunk, expect.flags), r["index"]

@@ -15,17 +15,28 @@ from paper_2604_27985_amd import selector  # noqa: E402
 
 
 def test_plan_lists():
-    assert selector.plan_count(_lib.OP_SPMM) == 24 and selector.plan_count(_lib.OP_SDDMM) == 23
+    assert selector.plan_count(_lib.OP_SPMM) == 30 and selector.plan_count(_lib.OP_SDDMM) == 29
     pl = selector.plan_list(_lib.OP_SPMM, 64)
     assert [p.variant for p, _ in pl[:15]] == [0] * 5 + [1] * 5 + [3] * 5 and pl[15][0].variant == 2
     # LDS slabs of 16 / 32 KiB of F32 rows (K = 64: 256-byte rows), 4 or 8 rows per group, then one
     # entry per quad (flags bit 2) with 16 and 32 KiB slabs
-    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in pl[16:]] == [
+    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in pl[16:24]] == [
         (4, 16, 64, 0), (4, 16, 128, 0), (4, 16, 64, 2), (4, 16, 128, 2), (4, 16, 64, 4), (4, 16, 64, 6),
         (4, 16, 128, 4), (4, 16, 128, 6)]
+    # wide quad plans (32 and 64 KiB slabs), the column-slab form (2 and 8 MiB
+    # of B per slab), doubly compressed rows (plain lanes, then 4)
+    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in pl[24:]] == [
+        (4, 16, 128, 12), (4, 16, 256, 12), (5, 16, 8192, 0), (5, 16, 32768, 0), (6, 16, 0, 0), (6, 4, 0, 0)]
     assert all(ok for _, ok in pl[16:])
     for K, ok in ((8, True), (36, False), (256, True), (512, False)):
-        assert all(v == ok for _, v in selector.plan_list(_lib.OP_SPMM, K)[16:]), K
+        assert all(v == ok for _, v in selector.plan_list(_lib.OP_SPMM, K)[16:25]), K
+    # 64 KiB wide slabs only where the quad split takes the rows (F32 K 32, 64, 128; BF16 K 64, 128)
+    for K, ok32, okbf in ((32, True, False), (64, True, True), (128, True, True), (256, False, False), (8, False, False)):
+        assert selector.plan_list(_lib.OP_SPMM, K)[25][1] == ok32, K
+        assert selector.plan_list(_lib.OP_SPMM, K, _lib.BF16)[25][1] == okbf, K
+    assert selector.plan_list(_lib.OP_SDDMM, 256, _lib.BF16)[24][1]  # SDDMM quad takes 512-byte BF16 rows
+    # F64 operands: the first 15 plans only
+    assert [ok for _, ok in selector.plan_list(_lib.OP_SPMM, 64, _lib.F64)][15:] == [False] * 15
     assert [p.chunk for p, _ in selector.plan_list(_lib.OP_SPMM, 256)[16:18]] == [16, 32]
     assert [p.lanes for p, _ in pl[:5]] == [4, 8, 16, 32, 64]
     # K = 64: lanes x 4 up to 2 x 64
@@ -36,10 +47,13 @@ def test_plan_lists():
     assert not sd[0][1] and sd[1][1]
     assert all(p.chunk == 256 for p, _ in sd[5:10])
     # SDDMM TILE plans: at least 16 lanes (reductions over 16-lane rows)
-    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in selector.plan_list(_lib.OP_SDDMM, 32)[15:]] == [
+    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in selector.plan_list(_lib.OP_SDDMM, 32)[15:23]] == [
         (4, 16, 128, 0), (4, 16, 256, 0), (4, 16, 128, 2), (4, 16, 256, 2), (4, 16, 128, 4), (4, 16, 128, 6),
         (4, 16, 256, 4), (4, 16, 256, 6)]
-    assert [p.lanes for p, _ in sd[15:]] == [64] * 8 and all(ok for _, ok in sd[15:])
+    assert [p.lanes for p, _ in sd[15:25]] == [64] * 10 and all(ok for _, ok in sd[15:24])
+    assert not sd[24][1]  # F32 rows of 1 KiB: no quad split, no 64 KiB slabs
+    assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in selector.plan_list(_lib.OP_SDDMM, 64)[25:]] == [
+        (5, 8, 8192, 0), (5, 8, 32768, 0), (6, 8, 0, 0), (7, 16, 16, 0)]
 
 
 def test_plain_index_matches_null_plan_rule():
@@ -104,9 +118,9 @@ def test_extended_timings_merge(tmp_path):
     ext.write_text(json.dumps({"index": 1, "op": "spmm", "plans": [16, 17, 18, 19], "ms": [0.5, None, 0.7, 0.8]}) + "\n")
     assert selector.merge_timings(str(base), str(ext), str(out)) == 1
     m = selector.load_timings(str(out))
-    assert m[0]["ms_spmm"] == [1.0] * 16 + [None] * 8
-    assert m[1]["ms_spmm"] == [3.0] * 16 + [0.5, None, 0.7, 0.8] + [None] * 4
-    assert m[1]["ms_sddmm"] == [4.0] * 15 + [None] * 8  # widened to the SDDMM plan count
+    assert m[0]["ms_spmm"] == [1.0] * 16 + [None] * 14
+    assert m[1]["ms_spmm"] == [3.0] * 16 + [0.5, None, 0.7, 0.8] + [None] * 10
+    assert m[1]["ms_sddmm"] == [4.0] * 15 + [None] * 14  # widened to the SDDMM plan count
 
 
 def test_plan_names_round_trip():
