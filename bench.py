@@ -331,11 +331,24 @@ def to_device(p, kind):
 VERIFY = 5  # candidates of the learned ranking timed before the run
 
 
+# plan variants spmm_csr_backward takes for its A^T product and its pattern
+# SDDMM (rows, merge-path, column slabs, LDS slabs); the forms built per
+# pattern (blocks, 16-bit slabs, compressed rows, COO) have their own calls
+BACKWARD_VARIANTS = (0, 1, 3, 4)
+
+
 def autotune_sweep(A, K, B, plans):
     import paper_2604_27985_amd as spk
     from paper_2604_27985_amd import autotune
 
     return autotune.sweep(A, K, spk.OP_SPMM, B=B, plans=plans, reps=3, warmup=1)
+
+
+def autotune_sweep_sddmm(A, K, U, V, plans):
+    import paper_2604_27985_amd as spk
+    from paper_2604_27985_amd import autotune
+
+    return autotune.sweep(A, K, spk.OP_SDDMM, U=U, V=V, plans=plans, reps=3, warmup=1)
 
 
 def choose_plans(mode, dA, K, B, U, V, kind):
@@ -351,9 +364,10 @@ def choose_plans(mode, dA, K, B, U, V, kind):
         p1 = selector.select(dA, K, spk.OP_SPMM, verify=VERIFY, B=B)
         if kind == "gcn":
             # the backward's product runs on A^T: ask for a plan for that matrix
+            # among the variants spmm_csr_backward takes
             trp, tci, _ = dA.transpose()
             AT = spk.CSR(trp, tci, None, (dA.n, dA.m))
-            cands = [p for p in selector.rank(AT, K, spk.OP_SPMM, VERIFY + 1) if p.variant != spk.VAR_BSR4]
+            cands = [p for p in selector.rank(AT, K, spk.OP_SPMM, 16) if p.variant in BACKWARD_VARIANTS]
             return p1, min(autotune_sweep(AT, K, U, cands[:VERIFY]), key=lambda r: r[1])[0]
         return p1, selector.select(dA, K, spk.OP_SDDMM, verify=VERIFY, U=U, V=V)
     from paper_2604_27985_amd import autotune
@@ -362,7 +376,7 @@ def choose_plans(mode, dA, K, B, U, V, kind):
     if kind == "gcn":
         trp, tci, perm = dA.transpose()
         AT = spk.CSR(trp, tci, None, (dA.n, dA.m))
-        plans = [p for p in autotune.plans_for(spk.OP_SPMM, K) if p.variant != spk.VAR_BSR4]
+        plans = [p for p in autotune.plans_for(spk.OP_SPMM, K) if p.variant in BACKWARD_VARIANTS]
         return p1, min(autotune.sweep(AT, K, spk.OP_SPMM, B=U, plans=plans), key=lambda r: r[1])[0]
     return p1, autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
 
@@ -377,10 +391,12 @@ def choose_dvals_plan(mode, dA, K, U, V):
     if mode == "learned":
         from paper_2604_27985_amd import selector
 
-        return selector.select(dA, K, spk.OP_SDDMM, verify=VERIFY, U=U, V=V)
+        cands = [p for p in selector.rank(dA, K, spk.OP_SDDMM, 16) if p.variant in BACKWARD_VARIANTS]
+        return min(autotune_sweep_sddmm(dA, K, U, V, cands[:VERIFY]), key=lambda r: r[1])[0]
     from paper_2604_27985_amd import autotune
 
-    return autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
+    plans = [p for p in autotune.plans_for(spk.OP_SDDMM, K) if p.variant in BACKWARD_VARIANTS]
+    return min(autotune.sweep(dA, K, spk.OP_SDDMM, U=U, V=V, plans=plans), key=lambda r: r[1])[0]
 
 
 class Step:
