@@ -498,6 +498,8 @@ void oracle_mlp_forward(int64_t F, int64_t H, int64_t P, const double *W1, const
 /* Masked mean-squared error  L = (1 / (2 * count)) * sum mask * (y - t)^2, */
 /* count = number of nonzero mask entries, and its gradient with respect    */
 /* to every weight and bias (accumulated over the batch).  Returns L.       */
+/* The mask's values weigh the terms (0 drops a term; a 0/1 mask is the     */
+/* plain masked mean).                                                      */
 double oracle_mlp_loss_grad(int64_t F, int64_t H, int64_t P, const double *W1,
                             const double *b1, const double *W2, const double *b2,
                             const double *W3, const double *b3, int64_t batch,
@@ -530,7 +532,7 @@ double oracle_mlp_loss_grad(int64_t F, int64_t H, int64_t P, const double *W1,
         for (int64_t o = 0; o < H; ++o) a2[o] = z2[o] > 0.0 ? z2[o] : 0.0;
         affine(P, H, W3, b3, a2, y);
         for (int64_t o = 0; o < P; ++o) {
-            double w = mask[s * P + o] != 0.0 ? 1.0 : 0.0;
+            double w = mask[s * P + o];
             double e = y[o] - T[s * P + o];
             loss += w * e * e;
             dy[o] = w * e / count; /* dL/dy */

@@ -298,15 +298,20 @@ def _rand_mlp(F, H, P, seed):
                       r.normal(size=H), r.normal(size=(P, H)) / 4, r.normal(size=P))
 
 
-def test_mlp_gradients_match_finite_differences():
+@pytest.mark.parametrize("weighted", [False, True])
+def test_mlp_gradients_match_finite_differences(weighted):
+    """A 0/1 mask gives the masked mean of squared errors; other mask values
+    weigh the terms (count stays the number of nonzero entries)."""
     F, H, P, Bsz = 6, 8, 5, 7
     net = _rand_mlp(F, H, P, 0)
     r = np.random.default_rng(1)
     X, T = r.normal(size=(Bsz, F)), r.normal(size=(Bsz, P))
     mask = (r.random((Bsz, P)) < 0.7).astype(np.float64)
+    if weighted:
+        mask *= r.uniform(0.1, 5.0, size=(Bsz, 1))
     loss, grads = net.loss_grad(X, T, mask)
     Y = net.forward(X)
-    assert np.isclose(loss, ((Y - T) ** 2 * mask).sum() / (2 * mask.sum()), rtol=1e-13)
+    assert np.isclose(loss, ((Y - T) ** 2 * mask).sum() / (2 * (mask != 0).sum()), rtol=1e-13)
     h = 1e-6
     for W, g in zip(net.params(), grads):
         flat, gflat = W.reshape(-1), g.reshape(-1)
