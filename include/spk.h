@@ -478,7 +478,8 @@ int32_t mlp_forward(const float *params, int64_t F, int64_t H, int64_t P, const 
 size_t mlp_workspace_bytes(int64_t F, int64_t H, int64_t P, int64_t batch);
 
 /* Masked mean squared error L = sum mask (y - T)^2 / (2 count) (count = number
- * of nonzero mask entries) and its gradient with respect to params (same
+ * of nonzero mask entries; mask values other than 0/1 weigh the terms) and
+ * its gradient with respect to params (same
  * layout) for a batch: X [batch x F], T and mask [batch x P], all device.
  * loss: device, 1 float.  Gradients are summed over samples in order (the
  * result does not vary between runs). */

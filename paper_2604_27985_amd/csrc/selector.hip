@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kMaxHidden) void mlp_delta_kernel(const float *__re
     mlp_eval(params, d, x, a1, a2, y);
     const float cnt = count[0];
     if (t < d.P) {
-        const float w = mask[s * d.P + t] != 0.f ? 1.f : 0.f;
+        const float w = mask[s * d.P + t];  // the mask's value weighs the term
         const float e = y[t] - T[s * d.P + t];
         dy[t] = cnt > 0.f ? w * e / cnt : 0.f;
         sc[L.dy + t] = dy[t];
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kMaxHidden) void mlp_delta_kernel(const float *__re
     if (t == 0) {
         float l = 0.f;
         for (int p = 0; p < d.P; ++p) {
-            const float w = mask[s * d.P + p] != 0.f ? 1.f : 0.f;
+            const float w = mask[s * d.P + p];
             const float e = y[p] - T[s * d.P + p];
             l = fmaf(w * e, e, l);
         }

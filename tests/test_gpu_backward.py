@@ -98,11 +98,16 @@ def test_backward_full_size_sampled(spk):
     Bd, Gd = dev(B), dev(G)
     trp_d, tci_d, _ = dA.transpose()
     AT_d = spk.CSR(trp_d, tci_d, None, (A.n, A.m))
-    cands = [p for p in selector.rank(AT_d, K, spk.OP_SPMM, 6) if p.variant != spk.VAR_BSR4]
+    # the backward runs the CSR variants (rows, merge-path, column slabs, LDS
+    # slabs); the forms built per pattern have calls of their own
+    csr_variants = (spk.VAR_ROWS, spk.VAR_MERGE, spk.VAR_SLAB, spk.VAR_TILE)
+    cands = [p for p in selector.rank(AT_d, K, spk.OP_SPMM, 16) if p.variant in csr_variants]
     from paper_2604_27985_amd import autotune
     learned_bwd = min(autotune.sweep(AT_d, K, spk.OP_SPMM, B=Gd, plans=cands[:5], reps=2, warmup=1),
                       key=lambda r: r[1])[0]
-    learned_dv = selector.select(dA, K, spk.OP_SDDMM, verify=5, U=Gd, V=Bd)
+    dv_cands = [p for p in selector.rank(dA, K, spk.OP_SDDMM, 16) if p.variant in csr_variants]
+    learned_dv = min(autotune.sweep(dA, K, spk.OP_SDDMM, U=Gd, V=Bd, plans=dv_cands[:5], reps=2, warmup=1),
+                     key=lambda r: r[1])[0]
     # dB rows j: the oracle's SpMM over the sampled rows of A^T (the oracle's
     # own transpose), values gathered through its perm
     trp, tci, perm = oracle.csr_transpose(A.row_ptr, A.col_idx, A.n)

@@ -73,7 +73,8 @@ def test_mlp_forward_grad_adam_match_oracle(spk, sel):
     r = np.random.default_rng(2)
     X = r.normal(size=(N, F)).astype(np.float32)
     T = r.normal(size=(N, P)).astype(np.float32)
-    mask = (r.random((N, P)) < 0.8).astype(np.float32)
+    # a weighted mask: per-sample weights as the time-weighted training uses
+    mask = ((r.random((N, P)) < 0.8) * r.uniform(0.2, 4.0, size=(N, 1))).astype(np.float32)
     net = oracle.MLP(*parts)
     tr = sel.Trainer(P, H)
     tr.params = torch.from_numpy(np.concatenate([a.reshape(-1) for a in parts])).cuda()
