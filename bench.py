@@ -665,12 +665,55 @@ def run_workload(args):
         out["plain"] = {"ms_per_step": round(p_ms, 4), "value": round(flops_step / (p_ms * 1e-3) / 1e9, 2),
                         "ms": [round(float(np.mean(p1)), 4), round(float(np.mean(p2)), 4)]}
         out["speedup_vs_plain"] = round(p_ms / ms_step, 3)
+    if kind in ("uniform", "gcn") and not args.no_compare:
+        # F32 operands only: the library takes no BF16 sparse product
+        out["library"] = library_times(dA, B, U, V, kt, sddmm=kind == "uniform")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, kind, step.C, step.S, args.cpu_budget)
         out["parity"] = {"max_scaled_err": out["cpu_baseline"]["gpu_max_scaled_err"], "gate": 1e-5,
                          "ok": out["cpu_baseline"]["gpu_max_scaled_err"] <= 1e-5,
                          "sample": out["cpu_baseline"]["sample"].split(":")[0]}
     print(json.dumps(out), flush=True)
+
+
+def median_ms(f, reps=5, warmup=2):
+    """Median milliseconds of `reps` launches of f after `warmup` untimed ones."""
+    import torch
+
+    for _ in range(warmup):
+        f()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        f()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[len(ts) // 2]
+
+
+def library_times(dA, B, U, V, kt, sddmm=True):
+    """The vendor sparse library on the same CSR and F32 operands, as PyTorch
+    calls it (torch.sparse.mm and torch.sparse.sampled_addmm, hipSPARSE on
+    ROCm, including whatever PyTorch does around the call), against the
+    median times of this line's kernels.  The library's sampled product is the
+    pattern SDDMM (no multiply by A's values).  Context, not the baseline."""
+    import torch
+
+    A = torch.sparse_csr_tensor(dA.row_ptr, dA.col_idx, dA.vals, size=(dA.m, dA.n))
+    res = {"what": "torch.sparse.mm / torch.sparse.sampled_addmm (hipSPARSE) on the same CSR, median of 5"}
+    t = median_ms(lambda: torch.sparse.mm(A, B))
+    res["spmm_ms"] = round(t, 4)
+    res["spmm_ratio"] = round(t / kt["spmm"]["ms_median"], 2)
+    if sddmm:
+        Vt = V.t().contiguous()
+        t = median_ms(lambda: torch.sparse.sampled_addmm(A, U, Vt, beta=0.0, alpha=1.0))
+        res["sddmm_ms"] = round(t, 4)
+        res["sddmm_ratio"] = round(t / kt["sddmm"]["ms_median"], 2)
+    del A
+    torch.cuda.empty_cache()
+    return res
 
 
 def attention_bytes(m, n, nnz, K1, K2, s=4):
