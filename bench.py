@@ -94,10 +94,10 @@ def roofline(bytes_, flops, seconds):
 PROFILES = os.path.join(ROOT, "profiles")
 # kernels of each part of a step (rocprofv3 names), for attributing counter readings
 PART_KERNELS = {"spmm": ("spmm_", "slab_bounds_kernel", "merge_partition_kernel", "merge_fixup_kernel",
-                         "gather_vals_kernel"),
+                         "gather_vals_kernel", "zero_rows_kernel"),
                 "sddmm": ("sddmm_",),
-                "attention": ("attn_rows_kernel",),
-                "softmax": ("row_softmax_kernel",)}
+                "attention": ("attn_",),
+                "softmax": ("softmax_",)}
 
 
 def kernel_source_digest():
@@ -222,6 +222,13 @@ def profile_summary(args):
             plan = line["config"]["plans"][part]
             out.append(f"traffic {line['config']['workload']} {part} {plan} {b:.0f} {digest}")
         out += ["```", ""]
+        if line["config"]["ops"] == "attention" and "attention" in part_bytes:
+            # the unfused chain the bench line times beside the fused kernel
+            chain = {k: part_bytes.get(k, 0.0) for k in ("sddmm", "softmax", "spmm")}
+            tot = sum(chain.values())
+            out += [f"Fused attention: {part_bytes['attention']:.4g} HBM bytes per step; the unfused chain "
+                    f"(SDDMM {chain['sddmm']:.4g}, row softmax {chain['softmax']:.4g}, SpMM {chain['spmm']:.4g}): "
+                    f"{tot:.4g} bytes per step ({tot / part_bytes['attention']:.2f}x the fused kernel's).", ""]
     else:  # the backward runs SpMM kernels too: kernel names do not separate the parts
         out += ["", "No per-part traffic: forward and backward share kernel names.", ""]
     with open(args.out, "w") as fh:
