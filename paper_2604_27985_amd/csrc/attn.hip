@@ -258,8 +258,13 @@ __global__ __launch_bounds__(kBlock) void attn_split_kernel(int64_t m, int64_t n
 
 // One wave per run: a run whose slot 1 holds a row's first piece combines it
 // with the slot-0 pieces of the following runs that carry the same row, in
-// run order (pieces are loaded 8 at a time), and writes the row of O and lse.
-__global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int K2,
+// run order, and writes the row of O and lse.  The row's last run follows
+// from its end in row_ptr.  Loads of pieces go out in batches from clamped
+// indices with no branch around them, so that a batch is in flight at once:
+// a hub row spans hundreds of runs, and its chain of batches is the kernel's
+// critical path.
+__global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int64_t items, int K2,
+                                                            const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ slot_row,
                                                             const float *__restrict__ slot_ml,
                                                             const float *__restrict__ slot_acc,
@@ -270,30 +275,33 @@ __global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int
     if (g >= ngroups) return;
     const int32_t r = slot_row[2 * g + 1];
     if (r < 0) return;
-    // the end of the row's run of pieces, 64 runs per probe
-    int64_t h_end = g + 1;
-    for (;;) {
-        const int64_t h = h_end + lane;
-        const uint64_t other = __ballot(!(h < ngroups && slot_row[2 * h] == r));
-        if (other) {
-            h_end += __ffsll(static_cast<long long>(other)) - 1;
-            break;
-        }
-        h_end += kWave;
-    }
+    // runs g .. h_end - 1 hold the row: the last is the run of its last entry
+    const int64_t h_end = (static_cast<int64_t>(rp[r + 1]) - 1) / items + 1;
     // Maximum and normaliser over the pieces: piece 0 is slot 1 of run g,
     // piece t > 0 slot 0 of run g + t.  Lane j combines pieces j, j + 64, ...
     // in order, then the 64 lane states are combined by a butterfly whose
     // two partners compute the same (commutative) expression, so every lane
     // ends with the same bits.
     const int64_t npieces = h_end - g;
+    auto ml_slot = [&](int64_t t) { return t == 0 ? 2 * g + 1 : 2 * (g + t); };
     float mx = -INFINITY, l = 0.f;
-    for (int64_t t = lane; t < npieces; t += kWave) {
-        const int64_t sl = t == 0 ? 2 * g + 1 : 2 * (g + t);
-        const float m2 = slot_ml[2 * sl], l2 = slot_ml[2 * sl + 1];
-        const float mn = fmaxf(mx, m2);
-        l = l * __expf(mx - mn) + l2 * __expf(m2 - mn);
-        mx = mn;
+    constexpr int E = 4;  // pieces per lane and batch
+    for (int64_t t0 = lane; t0 < npieces; t0 += E * kWave) {
+        float mb[E], lb[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t t = t0 + e * kWave;
+            const int64_t sl = ml_slot(t < npieces ? t : npieces - 1);
+            mb[e] = slot_ml[2 * sl];
+            lb[e] = slot_ml[2 * sl + 1];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (t0 + e * kWave >= npieces) break;
+            const float mn = fmaxf(mx, mb[e]);
+            l = l * __expf(mx - mn) + lb[e] * __expf(mb[e] - mn);
+            mx = mn;
+        }
     }
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -306,20 +314,20 @@ __global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int
         mx = mn;
     }
     const float inv = 1.f / l;
-    constexpr int D = 8;
+    constexpr int D = 16;  // pieces per batch of the weighted sum
     for (int k = lane; k < K2; k += kWave) {
         float a = slot_acc[(2 * g + 1) * K2 + k] * __expf(slot_ml[2 * (2 * g + 1)] - mx);
         for (int64_t h = g + 1; h < h_end; h += D) {
             float v[D], w[D];
 #pragma unroll
             for (int u = 0; u < D; ++u) {
-                const bool in = h + u < h_end;
-                v[u] = in ? slot_acc[(2 * (h + u)) * K2 + k] : 0.f;
-                w[u] = in ? __expf(slot_ml[2 * (2 * (h + u))] - mx) : 0.f;
+                const int64_t hu = h + u < h_end ? h + u : h_end - 1;
+                v[u] = slot_acc[(2 * hu) * K2 + k];
+                w[u] = slot_ml[2 * (2 * hu)];
             }
 #pragma unroll
             for (int u = 0; u < D; ++u)
-                if (h + u < h_end) a = fma(v[u], w[u], a);  // wave-uniform condition
+                if (h + u < h_end) a = fma(v[u], __expf(w[u] - mx), a);  // wave-uniform condition
         }
         O[static_cast<int64_t>(r) * ldo + k] = a * inv;
     }
@@ -364,7 +372,8 @@ static hipError_t launch_attn(const AttnArgs &a, hipStream_t s) {
         if (e != hipSuccess) return e;
         constexpr int wpb = kBlock / kWave;
         hipLaunchKernelGGL(attn_fixup_kernel, dim3(static_cast<unsigned>((L.ngroups + wpb - 1) / wpb)), dim3(kBlock), 0,
-                           s, L.ngroups, static_cast<int>(a.K2), slot_row, slot_ml, slot_acc, a.O, a.ldo, a.lse);
+                           s, L.ngroups, L.items, static_cast<int>(a.K2), a.rp, slot_row, slot_ml, slot_acc, a.O,
+                           a.ldo, a.lse);
         return hipGetLastError();
     }
     const int64_t nb = (a.m + GPB - 1) / GPB;

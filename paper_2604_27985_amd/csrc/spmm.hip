@@ -723,7 +723,10 @@ __global__ __launch_bounds__(kBlock) void spmm_merge_kernel(
 }
 
 // One wave per share: the first share of each run of shares carrying the
-// same row adds the run's carries, in share order, to that row of C.
+// same row adds the run's carries, in share order, to that row of C.  Loads
+// go out from clamped indices with no branch around them, so that a batch is
+// in flight at once: a hub row's run spans thousands of shares, and its chain
+// of batches is the kernel's critical path.
 template <typename A>
 __global__ __launch_bounds__(kBlock) void merge_fixup_kernel(int64_t ngroups, int K, const int32_t *__restrict__ carry_row,
                                                              const A *__restrict__ carry_val, A *__restrict__ C,
@@ -732,36 +735,69 @@ __global__ __launch_bounds__(kBlock) void merge_fixup_kernel(int64_t ngroups, in
     if (g >= ngroups) return;
     const int32_t r = carry_row[g];
     if (r < 0 || (g > 0 && carry_row[g - 1] == r)) return;
-    // The run's end, 64 shares per probe: each lane tests one share and the
-    // first lane whose share carries another row (or lies past the end) marks
-    // it.  The conditions above are uniform over the wave, so all 64 lanes
-    // take part.
+    // The run's end, 256 shares per probe: each lane tests four shares and the
+    // first share that carries another row (or lies past the end) marks it.
+    // The conditions above are uniform over the wave, so all 64 lanes take
+    // part.
     const int lane = threadIdx.x & (kWave - 1);
+    constexpr int E = 4;
     int64_t g_end = g + 1;
-    for (;;) {
-        const int64_t h = g_end + lane;
-        const uint64_t other = __ballot(!(h < ngroups && carry_row[h] == r));
-        if (other) {
-            g_end += __ffsll(static_cast<long long>(other)) - 1;
-            break;
-        }
-        g_end += kWave;
-    }
-    // A long row's run spans many shares: 16 carries are loaded at a time
-    // (independent loads in flight) and added in share order, so the sum is
-    // the same as one carry at a time.
-    constexpr int D = 16;
-    for (int k = threadIdx.x & (kWave - 1); k < K; k += kWave) {
-        A s = A(0);
-        for (int64_t h = g; h < g_end; h += D) {
-            A v[D];
+    for (bool found = false; !found; ) {
+        int32_t cr[E];
 #pragma unroll
-            for (int u = 0; u < D; ++u) v[u] = h + u < g_end ? carry_val[(h + u) * K + k] : A(0);
+        for (int e = 0; e < E; ++e) {
+            const int64_t h = g_end + e * kWave + lane;
+            cr[e] = carry_row[h < ngroups ? h : ngroups - 1];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t h = g_end + e * kWave + lane;
+            const uint64_t other = __ballot(!(h < ngroups && cr[e] == r));
+            if (other) {
+                g_end += e * kWave + __ffsll(static_cast<long long>(other)) - 1;
+                found = true;
+                break;
+            }
+        }
+        if (!found) g_end += E * kWave;
+    }
+    if (g_end - g <= 4) {  // most runs: one share and its successor
+        for (int k = lane; k < K; k += kWave) {
+            A s = A(0);
+            for (int64_t h = g; h < g_end; ++h) s += carry_val[h * K + k];
+            C[static_cast<int64_t>(r) * ldc + k] += s;
+        }
+        return;
+    }
+    // A long run: D shares x KB column blocks of 64 per batch, added in share
+    // order, so the sum is the same as one carry at a time.
+    constexpr int D = 16, KB = 4;
+    for (int k0 = lane; k0 < K; k0 += KB * kWave) {
+        A s[KB];
+#pragma unroll
+        for (int b = 0; b < KB; ++b) s[b] = A(0);
+        for (int64_t h = g; h < g_end; h += D) {
+            A v[D][KB];
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int64_t hu = h + u < g_end ? h + u : g_end - 1;
+#pragma unroll
+                for (int b = 0; b < KB; ++b) {
+                    const int k = k0 + b * kWave;
+                    v[u][b] = carry_val[hu * K + (k < K ? k : 0)];
+                }
+            }
 #pragma unroll
             for (int u = 0; u < D; ++u)
-                if (h + u < g_end) s += v[u];  // wave-uniform condition
+                if (h + u < g_end)  // wave-uniform condition
+#pragma unroll
+                    for (int b = 0; b < KB; ++b) s[b] += v[u][b];
         }
-        C[static_cast<int64_t>(r) * ldc + k] += s;
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+            const int k = k0 + b * kWave;
+            if (k < K) C[static_cast<int64_t>(r) * ldc + k] += s[b];
+        }
     }
 }
 
