@@ -235,11 +235,12 @@ def load_timings(path: str) -> list[dict]:
 
 
 def extend_timings(path: str, out_path: str, op: int, indices: list[int], log=print,
-                   time_budget_s: float | None = None) -> int:
-    """Time plans added to an op's list after `path` was built: every matrix of
-    `path` is generated again from its spec (seeded) and only plans `indices`
-    are timed.  Appends {"index", "op", "plans", "ms"} records to `out_path`
-    (resumable); merge_timings folds them into the timing set."""
+                   time_budget_s: float | None = None, min_k: int = 0) -> int:
+    """Time plans added to an op's list after `path` was built, or plans whose
+    definition changed for widths K >= min_k: every matrix of `path` with
+    K >= min_k is generated again from its spec (seeded) and only plans
+    `indices` are timed.  Appends {"index", "op", "plans", "ms"} records to
+    `out_path` (resumable); merge_timings folds them into the timing set."""
     done = set()
     if os.path.exists(out_path):
         with open(out_path) as fh:
@@ -251,7 +252,7 @@ def extend_timings(path: str, out_path: str, op: int, indices: list[int], log=pr
     with open(out_path, "a") as fh:
         for rec in load_timings(path):
             i = rec["index"]
-            if i in done:
+            if i in done or rec["K"] < min_k:
                 continue
             if time_budget_s is not None and time.time() - t0 > time_budget_s:
                 break
@@ -579,6 +580,7 @@ def main(argv=None) -> None:
     e.add_argument("--op", choices=("spmm", "sddmm"), required=True)
     e.add_argument("--plans", required=True, help="first-last plan indices, e.g. 16-19")
     e.add_argument("--budget", type=float, default=None, help="stop after this many seconds")
+    e.add_argument("--min-k", type=int, default=0, help="only matrices with dense width K >= this")
     g = sub.add_parser("merge", help="fold extend records into a timing set")
     g.add_argument("--timings", required=True)
     g.add_argument("--ext", required=True)
@@ -603,7 +605,8 @@ def main(argv=None) -> None:
     if args.cmd == "extend":
         lo, hi = (int(x) for x in args.plans.split("-"))
         op = OP_SPMM if args.op == "spmm" else OP_SDDMM
-        n = extend_timings(args.timings, args.out, op, list(range(lo, hi + 1)), log=log, time_budget_s=args.budget)
+        n = extend_timings(args.timings, args.out, op, list(range(lo, hi + 1)), log=log, time_budget_s=args.budget,
+                           min_k=args.min_k)
         print(f"extended {n} records", flush=True)
         return
     if args.cmd == "merge":
