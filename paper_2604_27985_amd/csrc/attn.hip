@@ -431,42 +431,73 @@ __device__ __forceinline__ float wave_sum(float v, int lane) {
     return v;
 }
 
+// A wave's run of scores, staged in LDS with coalesced loads (lane l holds
+// slot j * 64 + l), and the ends of the run's rows, 64 at a time in a
+// register of each lane (read back with readlane): the walk over the run's
+// rows then waits on no global load per row.
+constexpr int kSoftmaxWaves = kBlock / kWave;
+static_assert(kSoftmaxItems % kWave == 0, "a run fills whole slots of the wave");
+
+__device__ __forceinline__ void stage_run(const float *__restrict__ S, int64_t p0, int64_t p1, float *xs, int lane) {
+#pragma unroll 4
+    for (int j = 0; j < kSoftmaxItems / kWave; ++j) {
+        const int64_t p = p0 + j * kWave + lane;
+        xs[j * kWave + lane] = S[p < p1 ? p : p1 - 1];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(kBlock) void softmax_stats_kernel(int64_t m, int64_t nnz, const int32_t *__restrict__ rp,
                                                                const float *__restrict__ S, int64_t items,
                                                                int64_t ngroups, float *__restrict__ rowml,
                                                                int32_t *__restrict__ slot_row,
                                                                float *__restrict__ slot_ml) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    __shared__ float xs_all[kSoftmaxWaves][kSoftmaxItems];
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kSoftmaxWaves + threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     if (g >= ngroups) return;
+    float *xs = xs_all[threadIdx.x / kWave];
     const int64_t p0 = g * items;
     const int64_t p1 = p0 + items < nnz ? p0 + items : nnz;
+    stage_run(S, p0, p1, xs, lane);
     int32_t used0 = -1, used1 = -1;
     int64_t r = last_at_most(0, m - 1, p0, [&](int64_t i) { return static_cast<int64_t>(rp[i]); });
-    for (; r < m; ++r) {
-        const int64_t ra = rp[r], rb = rp[r + 1];
-        if (ra >= p1) break;
-        const int64_t a = ra > p0 ? ra : p0, b = rb < p1 ? rb : p1;
-        if (a >= b) continue;
-        float mx = -INFINITY;
-        for (int64_t p = a + lane; p < b; p += kWave) mx = fmaxf(mx, S[p]);
-        mx = wave_max(mx, lane);
-        float l = 0.f;
-        for (int64_t p = a + lane; p < b; p += kWave) l += __expf(S[p] - mx);
-        l = wave_sum(l, lane);
-        if (ra >= p0 && rb <= p1) {
-            if (lane == 0) {
-                rowml[2 * r] = mx;
-                rowml[2 * r + 1] = l;
+    int64_t ra = rp[r];
+    for (bool more = true; more && r < m;) {
+        // ends of rows r .. r + 63 (clamped past the last row)
+        const int32_t ends = rp[(r + 1 + lane) < m ? r + 1 + lane : m];
+        for (int k = 0; k < kWave && r < m; ++k, ++r) {
+            const int64_t rb = __builtin_amdgcn_readlane(ends, k);
+            if (ra >= p1) {
+                more = false;
+                break;
             }
-            continue;
-        }
-        const int64_t slot = 2 * g + (ra >= p0 ? 1 : 0);
-        if (ra >= p0) used1 = static_cast<int32_t>(r);
-        else used0 = static_cast<int32_t>(r);
-        if (lane == 0) {
-            slot_ml[2 * slot] = mx;
-            slot_ml[2 * slot + 1] = l;
+            const int64_t a = ra > p0 ? ra : p0, b = rb < p1 ? rb : p1;
+            const int64_t row_start = ra;
+            ra = rb;
+            if (a >= b) continue;
+            float mx = -INFINITY;
+            for (int64_t p = a + lane; p < b; p += kWave) mx = fmaxf(mx, xs[p - p0]);
+            mx = wave_max(mx, lane);
+            float l = 0.f;
+            for (int64_t p = a + lane; p < b; p += kWave) l += __expf(xs[p - p0] - mx);
+            l = wave_sum(l, lane);
+            if (row_start >= p0 && rb <= p1) {
+                if (lane == 0) {
+                    rowml[2 * r] = mx;
+                    rowml[2 * r + 1] = l;
+                }
+                continue;
+            }
+            const int64_t slot = 2 * g + (row_start >= p0 ? 1 : 0);
+            if (row_start >= p0) used1 = static_cast<int32_t>(r);
+            else used0 = static_cast<int32_t>(r);
+            if (lane == 0) {
+                slot_ml[2 * slot] = mx;
+                slot_ml[2 * slot + 1] = l;
+            }
         }
     }
     if (lane == 0) {
@@ -521,20 +552,45 @@ __global__ __launch_bounds__(kBlock) void softmax_apply_kernel(int64_t m, int64_
                                                                float *__restrict__ S, int64_t items, int64_t ngroups,
                                                                const float *__restrict__ rowml,
                                                                float *__restrict__ lse) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    __shared__ float xs_all[kSoftmaxWaves][kSoftmaxItems];
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kSoftmaxWaves + threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     if (g >= ngroups) return;
+    float *xs = xs_all[threadIdx.x / kWave];
     const int64_t p0 = g * items;
     const int64_t p1 = p0 + items < nnz ? p0 + items : nnz;
+    stage_run(S, p0, p1, xs, lane);
     int64_t r = last_at_most(0, m - 1, p0, [&](int64_t i) { return static_cast<int64_t>(rp[i]); });
-    for (; r < m; ++r) {
-        const int64_t ra = rp[r], rb = rp[r + 1];
-        if (ra >= p1) break;
-        const int64_t a = ra > p0 ? ra : p0, b = rb < p1 ? rb : p1;
-        if (a >= b) continue;
-        const float mx = rowml[2 * r], inv = 1.f / rowml[2 * r + 1];
-        for (int64_t p = a + lane; p < b; p += kWave) S[p] = __expf(S[p] - mx) * inv;
-        if (lse && lane == 0 && ra >= p0) lse[r] = mx + logf(rowml[2 * r + 1]);
+    int64_t ra = rp[r];
+    for (bool more = true; more && r < m;) {
+        // ends, maxima and normalisers of rows r .. r + 63
+        const int64_t rl = (r + lane) < m ? r + lane : m - 1;
+        const int32_t ends = rp[rl + 1];
+        const float mxs = rowml[2 * rl], ls = rowml[2 * rl + 1];
+        for (int k = 0; k < kWave && r < m; ++k, ++r) {
+            const int64_t rb = __builtin_amdgcn_readlane(ends, k);
+            if (ra >= p1) {
+                more = false;
+                break;
+            }
+            const int64_t a = ra > p0 ? ra : p0, b = rb < p1 ? rb : p1;
+            const bool first = ra >= p0;
+            ra = rb;
+            if (a >= b) continue;
+            const float mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mxs), k));
+            const float lr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ls), k));
+            const float inv = 1.f / lr;
+            for (int64_t p = a + lane; p < b; p += kWave) xs[p - p0] = __expf(xs[p - p0] - mx) * inv;
+            if (lse && lane == 0 && first) lse[r] = mx + logf(lr);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
+    for (int j = 0; j < kSoftmaxItems / kWave; ++j) {
+        const int64_t p = p0 + j * kWave + lane;
+        if (p < p1) S[p] = xs[j * kWave + lane];
     }
 }
 

@@ -722,6 +722,41 @@ __global__ __launch_bounds__(kBlock) void spmm_merge_kernel(
     if (lig == 0 && blockIdx.y == 0) carry_row[g] = has_carry ? static_cast<int32_t>(i1) : -1;
 }
 
+// A long run's carries for columns k0 + b * 64 (b < KB), D shares per batch,
+// added in share order, so the sum is the same as one carry at a time.
+template <typename A, int KB>
+__device__ __forceinline__ void fixup_long_run(int64_t g, int64_t g_end, int K, int lane, int32_t r,
+                                               const A *__restrict__ carry_val, A *__restrict__ C, int64_t ldc) {
+    constexpr int D = 16;
+    for (int k0 = lane; k0 < K; k0 += KB * kWave) {
+        A s[KB];
+#pragma unroll
+        for (int b = 0; b < KB; ++b) s[b] = A(0);
+        for (int64_t h = g; h < g_end; h += D) {
+            A v[D][KB];
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int64_t hu = h + u < g_end ? h + u : g_end - 1;
+#pragma unroll
+                for (int b = 0; b < KB; ++b) {
+                    const int k = k0 + b * kWave;
+                    v[u][b] = carry_val[hu * K + (k < K ? k : 0)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < D; ++u)
+                if (h + u < g_end)  // wave-uniform condition
+#pragma unroll
+                    for (int b = 0; b < KB; ++b) s[b] += v[u][b];
+        }
+#pragma unroll
+        for (int b = 0; b < KB; ++b) {
+            const int k = k0 + b * kWave;
+            if (k < K) C[static_cast<int64_t>(r) * ldc + k] += s[b];
+        }
+    }
+}
+
 // One wave per share: the first share of each run of shares carrying the
 // same row adds the run's carries, in share order, to that row of C.  Loads
 // go out from clamped indices with no branch around them, so that a batch is
@@ -769,36 +804,9 @@ __global__ __launch_bounds__(kBlock) void merge_fixup_kernel(int64_t ngroups, in
         }
         return;
     }
-    // A long run: D shares x KB column blocks of 64 per batch, added in share
-    // order, so the sum is the same as one carry at a time.
-    constexpr int D = 16, KB = 4;
-    for (int k0 = lane; k0 < K; k0 += KB * kWave) {
-        A s[KB];
-#pragma unroll
-        for (int b = 0; b < KB; ++b) s[b] = A(0);
-        for (int64_t h = g; h < g_end; h += D) {
-            A v[D][KB];
-#pragma unroll
-            for (int u = 0; u < D; ++u) {
-                const int64_t hu = h + u < g_end ? h + u : g_end - 1;
-#pragma unroll
-                for (int b = 0; b < KB; ++b) {
-                    const int k = k0 + b * kWave;
-                    v[u][b] = carry_val[hu * K + (k < K ? k : 0)];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < D; ++u)
-                if (h + u < g_end)  // wave-uniform condition
-#pragma unroll
-                    for (int b = 0; b < KB; ++b) s[b] += v[u][b];
-        }
-#pragma unroll
-        for (int b = 0; b < KB; ++b) {
-            const int k = k0 + b * kWave;
-            if (k < K) C[static_cast<int64_t>(r) * ldc + k] += s[b];
-        }
-    }
+    if (K <= kWave) fixup_long_run<A, 1>(g, g_end, K, lane, r, carry_val, C, ldc);
+    else if (K <= 2 * kWave) fixup_long_run<A, 2>(g, g_end, K, lane, r, carry_val, C, ldc);
+    else fixup_long_run<A, 4>(g, g_end, K, lane, r, carry_val, C, ldc);
 }
 
 // -------------------------------------------------------------------------

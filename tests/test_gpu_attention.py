@@ -114,8 +114,18 @@ def test_attention_bf16_empty_rows_and_strides(spk):
     assert not O.any() and bool(torch.isneginf(lse).all())
 
 
-def test_row_softmax_matches_oracle(spk):
-    A = synth.powerlaw(20000, 16, 2.1, 3)
+@pytest.mark.parametrize("kind", ["powerlaw", "short", "hub"])
+def test_row_softmax_matches_oracle(spk, kind):
+    """Every row's probabilities and log-normaliser.  "short": rows of about
+    three entries and many empty rows, so one run of scores spans hundreds of
+    rows; "hub": one row of every column beside single-entry rows."""
+    if kind == "powerlaw":
+        A = synth.powerlaw(20000, 16, 2.1, 3)
+    elif kind == "short":
+        A = synth.bernoulli(30000, 30000, 1e-4, 3)
+    else:
+        rows = [[j] for j in range(0, 3000, 7)] + [list(range(3000))] + [[], [5]] * 50
+        A = host_csr(len(rows), 3000, rows)
     v, U, V, B = operands(A, 16, 4, 3)
     S64, _ = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
     dA = spk.CSR.from_host(A, v)
@@ -125,14 +135,18 @@ def test_row_softmax_matches_oracle(spk):
     fin = np.isfinite(L)
     assert np.array_equal(np.isneginf(lse.cpu().numpy()), ~fin)
     assert np.all(np.abs(lse.cpu().numpy()[fin] - L[fin]) <= 4 * 16 * U_ROUND * E[fin] + 8 * U_ROUND * np.abs(L[fin]) + 1e-6)
-    P = P.cpu().numpy().astype(np.float64)
-    for i in np.concatenate([np.arange(50), np.argsort(A.row_lengths())[-5:]]):
-        a, b = A.row_ptr[i], A.row_ptr[i + 1]
-        if b == a:
-            continue
-        s = S64[a:b]
-        p = np.exp(s - s.max()) / np.exp(s - s.max()).sum()
-        assert np.all(np.abs(P[a:b] - p) <= (1e-5 + 4 * 16 * U_ROUND * E[i]) * p + 1e-7), i
+    # reference probabilities of every entry, row by row in FP64
+    lens = A.row_lengths()
+    rows = np.repeat(np.arange(A.m), lens)
+    nz = lens > 0
+    mx = np.full(A.m, -np.inf)
+    mx[nz] = np.maximum.reduceat(S64, A.row_ptr[:-1][nz])
+    ex = np.exp(S64 - mx[rows])
+    tot = np.zeros(A.m)
+    tot[nz] = np.add.reduceat(ex, A.row_ptr[:-1][nz])
+    p = ex / tot[rows]
+    got = P.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - p) <= (1e-5 + 4 * 16 * U_ROUND * E[rows]) * p + 1e-7)
 
 
 def test_attention_full_size_sampled(spk):
