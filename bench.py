@@ -60,10 +60,29 @@ WORKLOADS = {
     "uniform-n16384-s99.9-K64": (16384, 0.001, 64, "uniform"),
     "uniform-n16384-s99.9-K128": (16384, 0.001, 128, "uniform"),
     "uniform-n1024-s90-K64": (1024, 0.1, 64, "uniform"),
+    # hyper-sparse: most rows of the dense operands are never referenced
+    "uniform-n1048576-d1e-06-K64": (1 << 20, 1e-6, 64, "uniform"),
+    "uniform-n1048576-d1e-07-K64": (1 << 20, 1e-7, 64, "uniform"),
+    "uniform-n2097152-d1e-07-K64": (1 << 21, 1e-7, 64, "uniform"),
     "attention-powerlaw-n262144-mean16-K64": (262144, 16, 64, "attention"),
 }
 DEFAULT_WORKLOAD = "uniform-n65536-s90-K128"
-SWEEP = [w for w, v in WORKLOADS.items() if v[3] == "uniform" and v[0] >= 16384]
+SWEEP = [w for w, v in WORKLOADS.items() if v[3] == "uniform" and 16384 <= v[0] <= 65536]
+HYPER = [w for w, v in WORKLOADS.items() if v[3] == "uniform" and v[0] > 65536]
+
+
+def touched_bytes(A, K):
+    """Bytes of the rows the products actually reference (hyper-sparse
+    patterns leave most rows of the dense operands untouched): SpMM reads the
+    referenced rows of B and writes all of C; SDDMM reads the rows of U of the
+    non-empty rows and the referenced rows of V."""
+    import numpy as np
+
+    cols = int(np.unique(A.col_idx).size)
+    rows = int(np.count_nonzero(np.diff(A.row_ptr)))
+    spmm = 4 * (A.m + 1) + A.nnz * 8 + cols * K * 4 + A.m * K * 4
+    sddmm = 4 * (A.m + 1) + A.nnz * 12 + rows * K * 4 + cols * K * 4
+    return {"spmm": spmm, "sddmm": sddmm}
 
 
 def spmm_bytes(m, n, nnz, K, sv=4, sb=4, perm=False):
@@ -379,13 +398,16 @@ def choose_plans(mode, dA, K, B, U, V, kind):
         return p1, selector.select(dA, K, spk.OP_SDDMM, verify=VERIFY, U=U, V=V)
     from paper_2604_27985_amd import autotune
 
-    p1 = autotune.best_plan(dA, K, spk.OP_SPMM, B=B)[0]
+    def log(line):  # the search is long on large patterns: one line per timed plan
+        print(line, file=sys.stderr, flush=True)
+
+    p1 = autotune.best_plan(dA, K, spk.OP_SPMM, B=B, log=log)[0]
     if kind == "gcn":
         trp, tci, perm = dA.transpose()
         AT = spk.CSR(trp, tci, None, (dA.n, dA.m))
         plans = [p for p in autotune.plans_for(spk.OP_SPMM, K) if p.variant in BACKWARD_VARIANTS]
-        return p1, min(autotune.sweep(AT, K, spk.OP_SPMM, B=U, plans=plans), key=lambda r: r[1])[0]
-    return p1, autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V)[0]
+        return p1, min(autotune.sweep(AT, K, spk.OP_SPMM, B=U, plans=plans, log=log), key=lambda r: r[1])[0]
+    return p1, autotune.best_plan(dA, K, spk.OP_SDDMM, U=U, V=V, log=log)[0]
 
 
 def choose_dvals_plan(mode, dA, K, U, V):
@@ -891,11 +913,13 @@ def run_sweep(args):
     import torch
 
     with open(args.sweep, "w") as f:
-        for name in SWEEP:
+        for name in (HYPER if args.sweep_set == "hyper" else SWEEP):
             n, d, K, kind = WORKLOADS[name]
             p = make_problem(name)
             dA, B, U, V = to_device(p, kind)
+            touched = touched_bytes(p.A, K) if args.sweep_set == "hyper" else None
             for mode in args.sweep_modes.split(","):
+                print(f"{name}: {mode} plans", file=sys.stderr, flush=True)
                 ps, pd = choose_plans(mode, dA, K, B, U, V, kind)
                 step = Step(dA, B, U, V, ps, pd, kind)
                 _, _, first_ms, second_ms = time_steps(step, args.steps, args.warmup)
@@ -906,6 +930,9 @@ def run_sweep(args):
                            "n": n, "sparsity": 1 - d, "K": K, "nnz": p.A.nnz, "ms_median": v["ms"],
                            "gflops": v["gflops"], "alg_bytes": v["alg_bytes"], "hbm_frac": v["hbm_frac"],
                            "roofline": roofline(v["_b"], v["_f"], v["_t"])}
+                    if touched:
+                        rec["touched_bytes"] = touched[op]
+                        rec["touched_roofline"] = roofline(touched[op], v["_f"], v["_t"])
                     f.write(json.dumps(rec) + "\n")
                     f.flush()
                     print(json.dumps(rec), file=sys.stderr, flush=True)
@@ -930,6 +957,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--sweep", default=None, help="write the grid sweep to this JSONL file")
     ap.add_argument("--sweep-modes", default="plain,tuned")
+    ap.add_argument("--sweep-set", default="grid", choices=["grid", "hyper"],
+                    help="the n x sparsity x K grid, or the hyper-sparse patterns (n = 2^20, 2^21)")
     ap.add_argument("--profile-summary", default=None, metavar="DIR",
                     help="summarise the rocprofv3 passes under DIR (cmd.txt, digest.txt, trace.log, trace/, "
                          "fetch/, write/) into --out; no GPU needed")

@@ -93,13 +93,19 @@ def time_plan(A: api.CSR, K: int, op: int, plan: api.Plan | None, B=None, U=None
 
 
 def sweep(A: api.CSR, K: int, op: int, B=None, U=None, V=None, reps: int = 5, warmup: int = 2,
-          plans: list[api.Plan] | None = None) -> list[tuple[api.Plan, float]]:
-    """Time every plan; returns [(plan, ms)] in plan-space order."""
+          plans: list[api.Plan] | None = None, log=None) -> list[tuple[api.Plan, float]]:
+    """Time every plan; returns [(plan, ms)] in plan-space order.  `log`, if
+    given, receives one line per plan as it is timed."""
     dtype = (B if op == OP_SPMM else U).dtype if (B is not None or U is not None) else torch.float32
     plans = plans if plans is not None else plans_for(op, K, dtype)
-    return [(p, time_plan(A, K, op, p, B=B, U=U, V=V, reps=reps, warmup=warmup)) for p in plans]
+    out = []
+    for p in plans:
+        out.append((p, time_plan(A, K, op, p, B=B, U=U, V=V, reps=reps, warmup=warmup)))
+        if log is not None:
+            log(f"{'spmm' if op == OP_SPMM else 'sddmm'} {p.name()}: {out[-1][1]:.4f} ms")
+    return out
 
 
-def best_plan(A: api.CSR, K: int, op: int, B=None, U=None, V=None, reps: int = 5) -> tuple[api.Plan, float]:
-    res = sweep(A, K, op, B=B, U=U, V=V, reps=reps)
+def best_plan(A: api.CSR, K: int, op: int, B=None, U=None, V=None, reps: int = 5, log=None) -> tuple[api.Plan, float]:
+    res = sweep(A, K, op, B=B, U=U, V=V, reps=reps, log=log)
     return min(res, key=lambda r: r[1])
