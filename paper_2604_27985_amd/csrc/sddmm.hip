@@ -363,17 +363,23 @@ __global__ __launch_bounds__(kBlock) void sddmm_coo_kernel(int64_t nnz, int K, c
     }
 }
 
-// SLAB16: group g takes run (s, g) of the column-slab form (slab16.hip): its
-// entries are positions [seg[s m + g], seg[s m + g + 1]) of col16 (columns
-// s W + col16), and entry k sits at A position apos[s m + g] + k, where its
-// value is read and its output written (the runs of a row cover its entries
-// once, so every output is written by one group).
+// SLAB16: group g of a block takes run (s, row) of the column-slab form
+// (slab16.hip): its entries are positions [seg[s m + row], seg[s m + row + 1])
+// of col16 (columns s W + col16), and entry k sits at A position
+// apos[s m + row] + k, where its value is read and its output written (the
+// runs of a row cover its entries once, so every output is written by one
+// group).  One launch covers every (slab, row block) item in slab-major
+// order, renumbered so that each XCD takes a contiguous range of it: an XCD
+// works through one slab (or part of one) at a time, and the rows of V it
+// gathers come from that slab alone, which its own L2 holds.  Outputs are
+// per entry, so items running at once on different XCDs never share one.
 template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
 __global__ __launch_bounds__(kBlock) void sddmm_s16_kernel(int64_t m, int K, const int32_t *__restrict__ seg,
                                                            const int32_t *__restrict__ apos,
-                                                           const uint16_t *__restrict__ col16, int s, int32_t cbase,
-                                                           const TV *__restrict__ vals, const TUV *__restrict__ U,
-                                                           int64_t ldu, const TUV *__restrict__ V, int64_t ldv,
+                                                           const uint16_t *__restrict__ col16, int64_t nbr,
+                                                           int32_t width, const TV *__restrict__ vals,
+                                                           const TUV *__restrict__ U, int64_t ldu,
+                                                           const TUV *__restrict__ V, int64_t ldv,
                                                            typename acc_of<TUV>::type *__restrict__ S) {
     constexpr int GPB = kBlock / LANES;
     constexpr int R = LANES < 8 ? LANES : 8;
@@ -381,9 +387,11 @@ __global__ __launch_bounds__(kBlock) void sddmm_s16_kernel(int64_t m, int K, con
     const int lig = threadIdx.x & (LANES - 1);
     const int gbase = lane & ~(LANES - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t row = blk * GPB + threadIdx.x / LANES;
+    const int64_t s = blk / nbr;
+    const int64_t row = (blk - s * nbr) * GPB + threadIdx.x / LANES;
     if (row >= m) return;
-    const int64_t run = static_cast<int64_t>(s) * m + row;
+    const int32_t cbase = static_cast<int32_t>(s * width);
+    const int64_t run = s * m + row;
     const int64_t a = seg[run], b = seg[run + 1];
     if (a >= b) return;
     const int64_t voff = static_cast<int64_t>(apos[run]) - a;
@@ -831,18 +839,15 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
         return hipGetLastError();
     }
     if (a.variant == SPK_VAR_SLAB16) {
-        const int64_t nb = (a.m + GPB - 1) / GPB;
-        if (nb > 0x7FFFFFFF || a.s16.nslabs < 1) return hipErrorInvalidValue;
-        for (int64_t sl = 0; sl < a.s16.nslabs; ++sl) {
-            hipLaunchKernelGGL((sddmm_s16_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
-                               dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.s16.seg, a.s16.apos, a.s16.col16,
-                               static_cast<int>(sl), static_cast<int32_t>(sl * a.s16.width),
-                               static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
-                               static_cast<const TUV *>(a.V), a.ldv, static_cast<A *>(a.S));
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+        const int64_t nbr = (a.m + GPB - 1) / GPB;  // row blocks per slab
+        const int64_t nb = a.s16.nslabs * nbr;
+        if (nb > 0x7FFFFFFF || a.s16.nslabs < 1 || a.s16.width > 65536) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((sddmm_s16_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
+                           dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.s16.seg, a.s16.apos, a.s16.col16, nbr,
+                           static_cast<int32_t>(a.s16.width), static_cast<const TV *>(a.vals),
+                           static_cast<const TUV *>(a.U), a.ldu, static_cast<const TUV *>(a.V), a.ldv,
+                           static_cast<A *>(a.S));
+        return hipGetLastError();
     }
     int nslabs = 1;
     int64_t width = a.n > 0 ? a.n : 1;
