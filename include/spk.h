@@ -419,7 +419,7 @@ size_t row_softmax_workspace_bytes(const spk_csr *A);
  * compile-time tile parameters (rows buffered per chunk, columns per worker
  * row, Section III-A and IV-C) chosen by sweeping; here a small network maps
  * sparsity features to the fastest plan and an exhaustive timed search is
- * the fallback and the judge.
+ * the fallback and the yardstick of its regret.
  * ------------------------------------------------------------------------ */
 
 /* Number of plans in an op's plan list (SPK_OP_SPMM: 30, SPK_OP_SDDMM: 29),

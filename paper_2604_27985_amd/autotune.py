@@ -1,6 +1,6 @@
 """Exhaustive plan search: time every plan of the plan space on the GPU.
 
-This is the fallback of the learned selector and the judge of its regret:
+This is the fallback of the learned selector and the yardstick of its regret:
 for a matrix, K and op it launches every valid plan through the C ABI,
 times each with HIP events on the launch stream (median of `reps` after
 `warmup` launches) and returns the fastest.

@@ -13,7 +13,7 @@ data:
   inference  plan_select (features -> inputs -> network -> masked argmin)
 
 The exhaustive search (autotune) stays the fallback when no model is loaded
-and is the judge of the selector's regret.
+and is the yardstick of the selector's regret.
 """
 from __future__ import annotations
 

@@ -27,6 +27,24 @@ def test_algorithmic_bytes():
     assert bench.sddmm_bytes(m, n, nnz, K, sv=0) == bench.sddmm_bytes(m, n, nnz, K) - 4 * nnz
 
 
+def test_touched_bytes_counts_referenced_rows_only():
+    """Hyper-sparse accounting: 5 x 8 pattern with two empty rows, columns
+    {1, 3, 6} referenced (column 3 twice)."""
+    import numpy as np
+    from types import SimpleNamespace
+
+    A = SimpleNamespace(m=5, n=8, nnz=4, row_ptr=np.array([0, 2, 2, 3, 3, 4], np.int32),
+                        col_idx=np.array([1, 3, 3, 6], np.int32))
+    K = 16
+    t = bench.touched_bytes(A, K)
+    # SpMM: row_ptr, (col, val) per entry, 3 referenced rows of B, all 5 rows of C
+    assert t["spmm"] == 4 * 6 + 4 * 8 + 3 * K * 4 + 5 * K * 4
+    # SDDMM: row_ptr, (col, val, out) per entry, 3 non-empty rows of U, 3 referenced rows of V
+    assert t["sddmm"] == 4 * 6 + 4 * 12 + 3 * K * 4 + 3 * K * 4
+    # never more than the byte model, which counts every dense row
+    assert t["spmm"] <= bench.spmm_bytes(5, 8, 4, K) and t["sddmm"] <= bench.sddmm_bytes(5, 8, 4, K)
+
+
 def test_roofline_picks_the_binding_roof():
     # 8e9 bytes, tiny flops: HBM binds; 1 s at 8 GB/s of 8 TB/s is 0.1%
     r = bench.roofline(8e9, 1.0, 1.0)
