@@ -396,15 +396,17 @@ def test_f64_kernels_match_oracle(spk):
     assert_within(S, S64, SM, TOL_F64, "f64 sddmm")
 
 
-def test_uniform_90_percent_full_size_sampled(spk):
-    """n = 65536 at 90% sparsity (4.3e8 entries), K = 64, seed 0: the plans the
-    bench times (the learned ones, best of the network's top five) and the
-    LDS-slab plans, plain and one entry per quad, on sampled rows of C and the
-    entries of sampled rows of S."""
+@pytest.mark.parametrize("K", [64, 128])
+def test_uniform_90_percent_full_size_sampled(spk, K):
+    """n = 65536 at 90% sparsity (4.3e8 entries), K = 64 and 128, seed 0: the
+    plans the bench times (the learned ones, best of the network's top five,
+    and the wide one-entry-per-quad plans its lines recorded) and LDS-slab
+    plans, plain and one entry per quad, on sampled rows of C and the entries
+    of sampled rows of S."""
     from paper_2604_27985_amd import selector
     from spk_testutil import sub_rows
 
-    n, K = 65536, 64
+    n = 65536
     p = synth.uniform_problem(n, 0.1, K, 0)
     A, v = p.A, p.vals
     dA = spk.CSR.from_host(A, v)
@@ -417,13 +419,21 @@ def test_uniform_90_percent_full_size_sampled(spk):
     lo = torch.from_numpy(A.row_ptr[rows].astype(np.int64)).cuda()
     cnt = torch.from_numpy((A.row_ptr[rows + 1] - A.row_ptr[rows]).astype(np.int64)).cuda()
     ent = torch.cat([torch.arange(int(a), int(a) + int(c), device="cuda") for a, c in zip(lo, cnt)])
-    for plan in (selector.select(dA, K, spk.OP_SPMM, verify=5, B=B), spk.Plan(4, 16, 64), spk.Plan(4, 16, 128, 2),
-                 spk.Plan(4, 16, 64, 4), spk.Plan(4, 16, 64, 6)):
+    if K == 64:
+        fixed_spmm = [spk.Plan(4, 16, 128, 12), spk.Plan(4, 16, 64), spk.Plan(4, 16, 128, 2), spk.Plan(4, 16, 64, 4),
+                      spk.Plan(4, 16, 64, 6)]
+        fixed_sddmm = [spk.Plan(4, 16, 256, 12), spk.Plan(4, 16, 64), spk.Plan(4, 16, 128, 2),
+                       spk.Plan(4, 16, 64, 4), spk.Plan(4, 16, 64, 6)]
+    else:  # 512-byte rows: 1024-thread workgroups, 64 KiB slabs
+        fixed_spmm = [spk.Plan(4, 32, 128, 12), spk.Plan(4, 32, 64, 12), spk.Plan(4, 32, 32, 4)]
+        fixed_sddmm = [spk.Plan(4, 32, 128, 12), spk.Plan(4, 32, 64, 12), spk.Plan(4, 32, 32, 6)]
+    for plan in [selector.select(dA, K, spk.OP_SPMM, verify=5, B=B)] + fixed_spmm:
         C = spk.spmm(dA, B, plan=plan)
-        assert_within(C[r].cpu().numpy(), C64, CM, TOL_F32, f"full-size spmm {plan.name()}")
-    for plan in (selector.select(dA, K, spk.OP_SDDMM, verify=5, U=U, V=V), spk.Plan(4, 16, 64),
-                 spk.Plan(4, 16, 128, 2), spk.Plan(4, 16, 64, 4), spk.Plan(4, 16, 64, 6)):
+        assert_within(C[r].cpu().numpy(), C64, CM, TOL_F32, f"full-size spmm K={K} {plan.name()}")
+        del C
+    for plan in [selector.select(dA, K, spk.OP_SDDMM, verify=5, U=U, V=V)] + fixed_sddmm:
         S = spk.sddmm(dA, U, V, plan=plan)
-        assert_within(S[ent].cpu().numpy(), S64, SM, TOL_F32, f"full-size sddmm {plan.name()}")
+        assert_within(S[ent].cpu().numpy(), S64, SM, TOL_F32, f"full-size sddmm K={K} {plan.name()}")
+        del S
     del dA, B, U, V
     torch.cuda.empty_cache()

@@ -150,3 +150,31 @@ def test_slab16_full_size_99_percent_sampled(spk):
             assert_within(S[e].cpu().numpy(), S64, SM, TOL_F32, f"full-size sddmm_slab16 W={W} K={K}")
             del F, C, S
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("sparsity,K,plans", [
+    (0.99, 128, [(5, 32, 4096), (5, 16, 4096)]),
+    (0.99, 64, [(5, 16, 8192), (5, 8, 8192)]),
+    (0.999, 128, [(5, 32, 16384), (5, 16, 16384)]),
+])
+def test_sparse_bench_plans_full_size_sampled(spk, sparsity, K, plans):
+    """The column-slab plans the 99% and 99.9% bench lines run (SpMM, then
+    SDDMM, through spmm / sddmm on the CSR), n = 65536, the bench's seed-0
+    operands, on sampled rows of C and the entries of sampled rows of S."""
+    n = 65536
+    p = synth.uniform_problem(n, 1 - sparsity, K, 0)
+    A, v = p.A, p.vals
+    dA = spk.CSR.from_host(A, v)
+    B, U, V = dev(p.B), dev(p.U), dev(p.V)
+    rows = np.unique(np.concatenate([[0, n - 1], synth.randint(96, n, 13)]))
+    srp, sci, idx = sub_rows(A, rows)
+    C64, CM = oracle.spmm(srp, sci, v[idx], p.B)
+    S64, SM = oracle.sddmm(srp, sci, v[idx], p.U[rows], p.V)
+    r = torch.from_numpy(rows).cuda()
+    e = torch.from_numpy(idx).cuda()
+    C = spk.spmm(dA, B, plan=spk.Plan(*plans[0]))
+    assert_within(C[r].cpu().numpy(), C64, CM, TOL_F32, f"bench spmm {plans[0]}")
+    S = spk.sddmm(dA, U, V, plan=spk.Plan(*plans[1]))
+    assert_within(S[e].cpu().numpy(), S64, SM, TOL_F32, f"bench sddmm {plans[1]}")
+    del dA, B, U, V, C, S
+    torch.cuda.empty_cache()
