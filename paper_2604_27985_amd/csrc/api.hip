@@ -700,7 +700,7 @@ size_t attention_workspace_bytes(const spk_csr *A, int64_t K2, const spk_plan *p
     int32_t variant;
     int64_t items;
     if (check_csr(A) != SPK_OK || K2 < 0 || resolve_attn(plan, variant, items) != SPK_OK) return 0;
-    return variant == SPK_VAR_MERGE ? attn_layout(A->nnz, K2, items).total : 0;
+    return variant == SPK_VAR_MERGE ? attn_layout(A->nnz, K2, items, true).total : 0;
 }
 
 int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv, int64_t K1,
@@ -728,7 +728,7 @@ int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const v
                     aligned(O, 16);
     const int32_t vec = v4 ? 4 : 1;
     if ((kmax + lanes * vec - 1) / (lanes * vec) > 8) return SPK_ERR_PLAN;
-    if (variant == SPK_VAR_MERGE && (st = check_ws(attn_layout(A->nnz, K2, items).total, ws, ws_bytes))) return st;
+    if (variant == SPK_VAR_MERGE && (st = check_ws(attn_layout(A->nnz, K2, items, true).total, ws, ws_bytes))) return st;
     AttnArgs a{A->m, A->n, A->nnz, K1, K2, A->row_ptr, A->col_idx, static_cast<const float *>(A->vals), U, ldu, V, ldv,
                B, ldb, dtype, O, ldo, lse, lanes, vec, variant, items, ws};
     return hip_status(attn_launch(a, static_cast<hipStream_t>(stream)));

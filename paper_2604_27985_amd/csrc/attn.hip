@@ -256,48 +256,31 @@ __global__ __launch_bounds__(kBlock) void attn_split_kernel(int64_t m, int64_t n
     }
 }
 
-// One wave per run: a run whose slot 1 holds a row's first piece combines it
-// with the slot-0 pieces of the following runs that carry the same row, in
-// run order, and writes the row of O and lse.  The row's last run follows
-// from its end in row_ptr.  Loads of pieces go out in batches from clamped
-// indices with no branch around them, so that a batch is in flight at once:
-// a hub row spans hundreds of runs, and its chain of batches is the kernel's
-// critical path.
-__global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int64_t items, int K2,
-                                                            const int32_t *__restrict__ rp,
-                                                            const int32_t *__restrict__ slot_row,
-                                                            const float *__restrict__ slot_ml,
-                                                            const float *__restrict__ slot_acc,
-                                                            float *__restrict__ O, int64_t ldo,
-                                                            float *__restrict__ lse) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (g >= ngroups) return;
-    const int32_t r = slot_row[2 * g + 1];
-    if (r < 0) return;
-    // runs g .. h_end - 1 hold the row: the last is the run of its last entry
-    const int64_t h_end = (static_cast<int64_t>(rp[r + 1]) - 1) / items + 1;
-    // Maximum and normaliser over the pieces: piece 0 is slot 1 of run g,
-    // piece t > 0 slot 0 of run g + t.  Lane j combines pieces j, j + 64, ...
-    // in order, then the 64 lane states are combined by a butterfly whose
-    // two partners compute the same (commutative) expression, so every lane
-    // ends with the same bits.
-    const int64_t npieces = h_end - g;
-    auto ml_slot = [&](int64_t t) { return t == 0 ? 2 * g + 1 : 2 * (g + t); };
-    float mx = -INFINITY, l = 0.f;
-    constexpr int E = 4;  // pieces per lane and batch
-    for (int64_t t0 = lane; t0 < npieces; t0 += E * kWave) {
+// Partial softmax states (maximum, normaliser, K2 weighted sums) are
+// combined in a fixed order.  states_max_sum: state t (t < count) sits at
+// slot slot_of(t) of ml; lane j combines states j, j + 64, ... in order,
+// loading four at a time from clamped indices (no branch around the loads,
+// so they are in flight together), then the 64 lane states are combined by
+// a butterfly whose two partners compute the same (commutative) expression,
+// so every lane ends with the same bits.
+template <typename SlotOf>
+__device__ __forceinline__ void states_max_sum(int64_t count, SlotOf slot_of, const float *__restrict__ ml, int lane,
+                                               float &mx, float &l) {
+    mx = -INFINITY;
+    l = 0.f;
+    constexpr int E = 4;
+    for (int64_t t0 = lane; t0 < count; t0 += E * kWave) {
         float mb[E], lb[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int64_t t = t0 + e * kWave;
-            const int64_t sl = ml_slot(t < npieces ? t : npieces - 1);
-            mb[e] = slot_ml[2 * sl];
-            lb[e] = slot_ml[2 * sl + 1];
+            const int64_t sl = slot_of(t < count ? t : count - 1);
+            mb[e] = ml[2 * sl];
+            lb[e] = ml[2 * sl + 1];
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            if (t0 + e * kWave >= npieces) break;
+            if (t0 + e * kWave >= count) break;
             const float mn = fmaxf(mx, mb[e]);
             l = l * __expf(mx - mn) + lb[e] * __expf(mb[e] - mn);
             mx = mn;
@@ -313,24 +296,103 @@ __global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int
         l = ea + eb;
         mx = mn;
     }
-    const float inv = 1.f / l;
-    constexpr int D = 16;  // pieces per batch of the weighted sum
-    for (int k = lane; k < K2; k += kWave) {
-        float a = slot_acc[(2 * g + 1) * K2 + k] * __expf(slot_ml[2 * (2 * g + 1)] - mx);
-        for (int64_t h = g + 1; h < h_end; h += D) {
-            float v[D], w[D];
+}
+
+// Column k of the states' sums rescaled to the maximum mx and added in state
+// order, 16 states' loads in flight at a time (clamped indices).
+template <typename SlotOf>
+__device__ __forceinline__ float states_weighted(int64_t count, SlotOf slot_of, const float *__restrict__ ml,
+                                                 const float *__restrict__ acc, int K2, int k, float mx) {
+    constexpr int D = 16;
+    float a = 0.f;
+    for (int64_t h = 0; h < count; h += D) {
+        float v[D], w[D];
 #pragma unroll
-            for (int u = 0; u < D; ++u) {
-                const int64_t hu = h + u < h_end ? h + u : h_end - 1;
-                v[u] = slot_acc[(2 * hu) * K2 + k];
-                w[u] = slot_ml[2 * (2 * hu)];
-            }
-#pragma unroll
-            for (int u = 0; u < D; ++u)
-                if (h + u < h_end) a = fma(v[u], __expf(w[u] - mx), a);  // wave-uniform condition
+        for (int u = 0; u < D; ++u) {
+            const int64_t sl = slot_of(h + u < count ? h + u : count - 1);
+            v[u] = acc[sl * K2 + k];
+            w[u] = ml[2 * sl];
         }
-        O[static_cast<int64_t>(r) * ldo + k] = a * inv;
+#pragma unroll
+        for (int u = 0; u < D; ++u)
+            if (h + u < count) a = fma(v[u], __expf(w[u] - mx), a);  // wave-uniform condition
     }
+    return a;
+}
+
+// Pieces per first-level fold of a long row.
+constexpr int64_t kFold = 64;
+
+// First level for rows cut into more than kFold pieces: one wave per run; a
+// run holding piece t0 of such a row with t0 a multiple of kFold (the first
+// piece in slot 1, later ones in slot 0) combines pieces t0 .. t0 + kFold - 1
+// into the fold slot of that piece.  A hub row's chain of loads is then
+// kFold pieces long here and count / kFold folds long in the fix-up.
+__global__ __launch_bounds__(kBlock) void attn_fold_kernel(int64_t ngroups, int64_t items, int K2,
+                                                           const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ slot_row,
+                                                           const float *__restrict__ slot_ml,
+                                                           const float *__restrict__ slot_acc,
+                                                           float *__restrict__ fold_ml, float *__restrict__ fold_acc) {
+    const int64_t h = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (h >= ngroups) return;
+    for (int slot = 0; slot < 2; ++slot) {
+        const int32_t r = slot_row[2 * h + slot];
+        if (r < 0) continue;
+        const int64_t g0 = static_cast<int64_t>(rp[r]) / items;  // the run of the row's first piece
+        const int64_t np = (static_cast<int64_t>(rp[r + 1]) - 1) / items + 1 - g0;
+        const int64_t t0 = h - g0;
+        if (np <= kFold || t0 % kFold != 0) continue;
+        const int64_t count = np - t0 < kFold ? np - t0 : kFold;
+        auto slot_of = [&](int64_t t) { return t0 + t == 0 ? 2 * g0 + 1 : 2 * (g0 + t0 + t); };
+        float mx, l;
+        states_max_sum(count, slot_of, slot_ml, lane, mx, l);
+        const int64_t fs = 2 * h + slot;
+        for (int k = lane; k < K2; k += kWave)
+            fold_acc[fs * K2 + k] = states_weighted(count, slot_of, slot_ml, slot_acc, K2, k, mx);
+        if (lane == 0) {
+            fold_ml[2 * fs] = mx;
+            fold_ml[2 * fs + 1] = l;
+        }
+    }
+}
+
+// One wave per run: a run whose slot 1 holds a row's first piece combines the
+// row's pieces (at most kFold of them) or the first level's folds of them, in
+// run order, and writes the row of O and lse.  The row's last run follows
+// from its end in row_ptr.
+__global__ __launch_bounds__(kBlock) void attn_fixup_kernel(int64_t ngroups, int64_t items, int K2,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ slot_row,
+                                                            const float *__restrict__ slot_ml,
+                                                            const float *__restrict__ slot_acc,
+                                                            const float *__restrict__ fold_ml,
+                                                            const float *__restrict__ fold_acc,
+                                                            float *__restrict__ O, int64_t ldo,
+                                                            float *__restrict__ lse) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (g >= ngroups) return;
+    const int32_t r = slot_row[2 * g + 1];
+    if (r < 0) return;
+    // runs g .. h_end - 1 hold the row: the last is the run of its last entry
+    const int64_t np = (static_cast<int64_t>(rp[r + 1]) - 1) / items + 1 - g;
+    const bool folded = np > kFold;
+    const int64_t count = folded ? (np + kFold - 1) / kFold : np;
+    // piece t: slot 1 of run g for t = 0, else slot 0 of run g + t; fold b:
+    // the slot of piece b * kFold
+    auto slot_of = [&](int64_t t) {
+        const int64_t piece = folded ? t * kFold : t;
+        return piece == 0 ? 2 * g + 1 : 2 * (g + piece);
+    };
+    const float *ml = folded ? fold_ml : slot_ml;
+    const float *acc = folded ? fold_acc : slot_acc;
+    float mx, l;
+    states_max_sum(count, slot_of, ml, lane, mx, l);
+    const float inv = 1.f / l;
+    for (int k = lane; k < K2; k += kWave)
+        O[static_cast<int64_t>(r) * ldo + k] = states_weighted(count, slot_of, ml, acc, K2, k, mx) * inv;
     if (lse && lane == 0) lse[r] = mx + logf(l);
 }
 
@@ -349,11 +411,13 @@ template <typename T, int VW, int LANES, int NS>
 static hipError_t launch_attn(const AttnArgs &a, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
     if (a.variant == SPK_VAR_MERGE) {
-        const AttnLayout L = attn_layout(a.nnz, a.K2, a.items);
+        const AttnLayout L = attn_layout(a.nnz, a.K2, a.items, true);
         char *ws = static_cast<char *>(a.ws);
         int32_t *slot_row = reinterpret_cast<int32_t *>(ws + L.row_off);
         float *slot_ml = reinterpret_cast<float *>(ws + L.ml_off);
         float *slot_acc = reinterpret_cast<float *>(ws + L.acc_off);
+        float *fold_ml = reinterpret_cast<float *>(ws + L.fold_ml_off);
+        float *fold_acc = reinterpret_cast<float *>(ws + L.fold_acc_off);
         if (a.m > 0) {
             hipLaunchKernelGGL(attn_empty_kernel, dim3(static_cast<unsigned>((a.m + kBlock - 1) / kBlock)), dim3(kBlock),
                                0, s, a.m, static_cast<int>(a.K2), a.rp, a.O, a.ldo, a.lse);
@@ -371,9 +435,12 @@ static hipError_t launch_attn(const AttnArgs &a, hipStream_t s) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         constexpr int wpb = kBlock / kWave;
-        hipLaunchKernelGGL(attn_fixup_kernel, dim3(static_cast<unsigned>((L.ngroups + wpb - 1) / wpb)), dim3(kBlock), 0,
-                           s, L.ngroups, L.items, static_cast<int>(a.K2), a.rp, slot_row, slot_ml, slot_acc, a.O,
-                           a.ldo, a.lse);
+        const dim3 grid(static_cast<unsigned>((L.ngroups + wpb - 1) / wpb));
+        hipLaunchKernelGGL(attn_fold_kernel, grid, dim3(kBlock), 0, s, L.ngroups, L.items, static_cast<int>(a.K2), a.rp,
+                           slot_row, slot_ml, slot_acc, fold_ml, fold_acc);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(attn_fixup_kernel, grid, dim3(kBlock), 0, s, L.ngroups, L.items, static_cast<int>(a.K2), a.rp,
+                           slot_row, slot_ml, slot_acc, fold_ml, fold_acc, a.O, a.ldo, a.lse);
         return hipGetLastError();
     }
     const int64_t nb = (a.m + GPB - 1) / GPB;

@@ -176,20 +176,26 @@ struct AttnArgs {
 };
 
 // Workspace of the entry-split attention: per run two slots (a row id, the
-// running maximum and normaliser, K2 accumulated values).
+// running maximum and normaliser, K2 accumulated values), and with `fold`
+// two more slots of (maximum, normaliser, K2 values) per run for the partial
+// states of long rows folded 64 pieces at a time.
 struct AttnLayout {
     int64_t items, ngroups;
-    size_t row_off, ml_off, acc_off, total;
+    size_t row_off, ml_off, acc_off, fold_ml_off, fold_acc_off, total;
 };
 
-inline AttnLayout attn_layout(int64_t nnz, int64_t K2, int64_t items) {
+inline AttnLayout attn_layout(int64_t nnz, int64_t K2, int64_t items, bool fold = false) {
     AttnLayout L;
     L.items = items > 0 ? items : 1;
     L.ngroups = nnz > 0 ? (nnz + L.items - 1) / L.items : 0;
+    const size_t ml_bytes = align_up(sizeof(float) * 4 * static_cast<size_t>(L.ngroups));
+    const size_t acc_bytes = align_up(sizeof(float) * 2 * static_cast<size_t>(L.ngroups) * static_cast<size_t>(K2));
     L.row_off = 0;
     L.ml_off = align_up(sizeof(int32_t) * 2 * static_cast<size_t>(L.ngroups));
-    L.acc_off = L.ml_off + align_up(sizeof(float) * 4 * static_cast<size_t>(L.ngroups));
-    L.total = L.acc_off + align_up(sizeof(float) * 2 * static_cast<size_t>(L.ngroups) * static_cast<size_t>(K2));
+    L.acc_off = L.ml_off + ml_bytes;
+    L.fold_ml_off = L.acc_off + acc_bytes;
+    L.fold_acc_off = L.fold_ml_off + (fold ? ml_bytes : 0);
+    L.total = L.fold_acc_off + (fold ? acc_bytes : 0);
     return L;
 }
 hipError_t attn_launch(const AttnArgs &a, hipStream_t s);

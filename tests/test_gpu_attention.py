@@ -91,6 +91,23 @@ def test_attention_matches_oracle(spk, kind, m, n, d, K1, K2):
     check(spk.attention(dA, Ud, Vd, Bd, pattern=True).cpu().numpy(), None, ref1, K1, "fused pattern")
 
 
+def test_attention_fold_boundaries(spk):
+    """Runs of 16 entries: a row of exactly 64 pieces (combined directly), rows
+    of 65 and 66 pieces (folded 64 at a time, then a partial fold), a short
+    row, an empty row and a row of 188 pieces, against the oracle."""
+    n = 4096
+    lens = [1024, 1040, 1041, 5, 0, 3000]
+    A = host_csr(len(lens), n, [list(range(k)) for k in lens])
+    rp = A.row_ptr.astype(np.int64)
+    pieces = [(rp[i + 1] - 1) // 16 + 1 - rp[i] // 16 if lens[i] else 0 for i in range(len(lens))]
+    assert pieces[:3] == [64, 65, 66] and pieces[5] > 64
+    v, U, V, B = operands(A, 64, 64, 5)
+    ref = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, v, U, V, B)
+    dA = spk.CSR.from_host(A, v)
+    O, lse = spk.attention(dA, dev(U), dev(V), dev(B), plan=spk.Plan(1, 8, 16), with_lse=True)
+    check(O.cpu().numpy(), lse.cpu().numpy(), ref, 64, "fold boundaries")
+
+
 def test_attention_bf16_empty_rows_and_strides(spk):
     A = host_csr(7, 40, [[], [3], [0, 1, 2, 39], [], [5, 6, 30], [7], list(range(0, 40, 2))])
     K1, K2, ld = 32, 64, 72
