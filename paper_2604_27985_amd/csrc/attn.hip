@@ -486,16 +486,28 @@ hipError_t attn_launch(const AttnArgs &a, hipStream_t s) {
 // attention).  Pass 1 finds each row piece's maximum and sum of exponentials
 // (a row wholly inside the run is finished into rowml), pass 2 combines the
 // pieces of cut rows in run order, pass 3 rewrites every score as its
-// probability.  Reductions use fixed butterflies: deterministic.
-__device__ __forceinline__ float wave_max(float v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) v = fmaxf(v, lane_read(v, lane ^ d));
-    return v;
+// probability.  Reductions are deterministic: inside each 16-lane row by
+// DPP moves (lane ^ 1, lane ^ 2, then the 8- and 16-lane mirrors; the two
+// lanes of every pair compute the same commutative expression), then the
+// four rows' values read back with readlane and combined in a fixed order,
+// so every lane ends with the same bits.  No LDS round trip: a row of a few
+// entries costs a handful of VALU moves instead of six ds_bpermute waits.
+__device__ __forceinline__ float lane_value(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
-__device__ __forceinline__ float wave_sum(float v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) v += lane_read(v, lane ^ d);
-    return v;
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));
+    v = fmaxf(v, dpp_f<0x4E>(v));
+    v = fmaxf(v, dpp_f<0x141>(v));
+    v = fmaxf(v, dpp_f<0x140>(v));
+    return fmaxf(fmaxf(lane_value(v, 0), lane_value(v, 16)), fmaxf(lane_value(v, 32), lane_value(v, 48)));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // A wave's run of scores, staged in LDS with coalesced loads (lane l holds
@@ -547,10 +559,10 @@ __global__ __launch_bounds__(kBlock) void softmax_stats_kernel(int64_t m, int64_
             if (a >= b) continue;
             float mx = -INFINITY;
             for (int64_t p = a + lane; p < b; p += kWave) mx = fmaxf(mx, xs[p - p0]);
-            mx = wave_max(mx, lane);
+            mx = wave_max(mx);
             float l = 0.f;
             for (int64_t p = a + lane; p < b; p += kWave) l += __expf(xs[p - p0] - mx);
-            l = wave_sum(l, lane);
+            l = wave_sum(l);
             if (row_start >= p0 && rb <= p1) {
                 if (lane == 0) {
                     rowml[2 * r] = mx;
@@ -573,7 +585,9 @@ __global__ __launch_bounds__(kBlock) void softmax_stats_kernel(int64_t m, int64_
     }
 }
 
-__global__ __launch_bounds__(kBlock) void softmax_fixup_kernel(int64_t ngroups, const int32_t *__restrict__ slot_row,
+__global__ __launch_bounds__(kBlock) void softmax_fixup_kernel(int64_t ngroups, int64_t items,
+                                                               const int32_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ slot_row,
                                                                const float *__restrict__ slot_ml,
                                                                float *__restrict__ rowml) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
@@ -581,34 +595,11 @@ __global__ __launch_bounds__(kBlock) void softmax_fixup_kernel(int64_t ngroups, 
     if (g >= ngroups) return;
     const int32_t r = slot_row[2 * g + 1];
     if (r < 0) return;
-    int64_t h_end = g + 1;
-    for (;;) {
-        const int64_t h = h_end + lane;
-        const uint64_t other = __ballot(!(h < ngroups && slot_row[2 * h] == r));
-        if (other) {
-            h_end += __ffsll(static_cast<long long>(other)) - 1;
-            break;
-        }
-        h_end += kWave;
-    }
-    const int64_t npieces = h_end - g;
-    float mx = -INFINITY, l = 0.f;
-    for (int64_t t = lane; t < npieces; t += kWave) {
-        const int64_t sl = t == 0 ? 2 * g + 1 : 2 * (g + t);
-        const float m2 = slot_ml[2 * sl], l2 = slot_ml[2 * sl + 1];
-        const float mn = fmaxf(mx, m2);
-        l = l * __expf(mx - mn) + l2 * __expf(m2 - mn);
-        mx = mn;
-    }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const float m2 = lane_read(mx, lane ^ d), l2 = lane_read(l, lane ^ d);
-        const float mn = fmaxf(mx, m2);
-        const float ea = mx == -INFINITY ? 0.f : l * __expf(mx - mn);
-        const float eb = m2 == -INFINITY ? 0.f : l2 * __expf(m2 - mn);
-        l = ea + eb;
-        mx = mn;
-    }
+    // runs g .. the run of the row's last entry hold its pieces
+    const int64_t npieces = (static_cast<int64_t>(rp[r + 1]) - 1) / items + 1 - g;
+    auto slot_of = [&](int64_t t) { return t == 0 ? 2 * g + 1 : 2 * (g + t); };
+    float mx, l;
+    states_max_sum(npieces, slot_of, slot_ml, lane, mx, l);
     if (lane == 0) {
         rowml[2 * r] = mx;
         rowml[2 * r + 1] = l;
@@ -691,7 +682,8 @@ hipError_t row_softmax_launch(int64_t m, int64_t nnz, const int32_t *rp, float *
     hipLaunchKernelGGL(softmax_stats_kernel, dim3(nb), dim3(kBlock), 0, s, m, nnz, rp, S, L.items, L.ngroups, rowml,
                        slot_row, slot_ml);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(softmax_fixup_kernel, dim3(nb), dim3(kBlock), 0, s, L.ngroups, slot_row, slot_ml, rowml);
+    hipLaunchKernelGGL(softmax_fixup_kernel, dim3(nb), dim3(kBlock), 0, s, L.ngroups, L.items, rp, slot_row, slot_ml,
+                       rowml);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(softmax_apply_kernel, dim3(nb), dim3(kBlock), 0, s, m, nnz, rp, S, L.items, L.ngroups, rowml, lse);
     return hipGetLastError();

@@ -202,7 +202,7 @@ hipError_t attn_launch(const AttnArgs &a, hipStream_t s);
 // Row softmax of stored scores in place (the unfused middle step), balanced
 // over runs of kSoftmaxItems entries; the workspace holds each row's maximum
 // and normaliser and the runs' partial states.
-constexpr int64_t kSoftmaxItems = 1024;
+constexpr int64_t kSoftmaxItems = 256;
 size_t row_softmax_ws_bytes(int64_t m, int64_t nnz);
 hipError_t row_softmax_launch(int64_t m, int64_t nnz, const int32_t *rp, float *S, float *lse, void *ws, hipStream_t s);
 
