@@ -371,8 +371,9 @@ __global__ __launch_bounds__(kBlock) void sddmm_coo_kernel(int64_t nnz, int K, c
 // group).  One launch covers every (slab, row block) item in slab-major
 // order, renumbered so that each XCD takes a contiguous range of it: an XCD
 // works through one slab (or part of one) at a time, and the rows of V it
-// gathers come from that slab alone, which its own L2 holds.  Outputs are
-// per entry, so items running at once on different XCDs never share one.
+// gathers come from that slab alone, which its own 4 MiB L2 holds when the
+// slab fits (2 MiB: 4096 columns of 512-byte rows).  Outputs are per entry,
+// so items running at once on different XCDs never share one.
 template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
 __global__ __launch_bounds__(kBlock) void sddmm_s16_kernel(int64_t m, int K, const int32_t *__restrict__ seg,
                                                            const int32_t *__restrict__ apos,
