@@ -387,12 +387,13 @@ int32_t sddmm_coo(const spk_csr *A, const int32_t *rowidx, const void *U, int64_
  *         entries (0: 512) whatever the rows, so rows of very different
  *         lengths cost no imbalance; a row cut by a run's ends leaves a
  *         partial state (maximum, normaliser, K2 sums) that a fix-up
- *         combines in run order;
+ *         combines in run order (for a row cut into more than 64 pieces,
+ *         64 pieces at a time first, then those folds in order);
  *       SPK_VAR_ROWS - one group per row (no workspace).
  *       Each row's entries are taken in storage order with an online
  *       (rescaled) softmax and fixed reductions: deterministic.
  * ws    attention_workspace_bytes(A, K2, plan) bytes (MERGE: per run two
- *       partial states). */
+ *       partial states and two folds). */
 int32_t sddmm_softmax_spmm(const spk_csr *A, const void *U, int64_t ldu, const void *V, int64_t ldv,
                            int64_t K1, const void *B, int64_t ldb, int64_t K2, int32_t dtype, float *O,
                            int64_t ldo, float *lse, const spk_plan *plan, void *ws, size_t ws_bytes,
