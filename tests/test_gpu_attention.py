@@ -108,6 +108,33 @@ def test_attention_fold_boundaries(spk):
     check(O.cpu().numpy(), lse.cpu().numpy(), ref, 64, "fold boundaries")
 
 
+def test_attention_and_softmax_workspace_sizes(spk):
+    """Caller workspaces: one byte short is refused before any launch; the
+    exact size gives the same bits as the library-sized call (entry-split
+    attention with runs of 16, so the long rows' folds are in use)."""
+    A = synth.powerlaw(3000, 16, 2.1, 7)
+    v, U, V, B = operands(A, 32, 32, 7)
+    dA = spk.CSR.from_host(A, v)
+    Ud, Vd, Bd = dev(U), dev(V), dev(B)
+    plan = spk.Plan(1, 8, 16)
+    nb = spk.attention_workspace_bytes(dA, 32, plan)
+    assert nb > 0
+    ref = spk.attention(dA, Ud, Vd, Bd, plan=plan)
+    with pytest.raises(spk.SpkError):
+        spk.attention(dA, Ud, Vd, Bd, plan=plan, workspace=torch.empty(nb - 1, dtype=torch.uint8, device="cuda"))
+    O = spk.attention(dA, Ud, Vd, Bd, plan=plan, workspace=torch.empty(nb, dtype=torch.uint8, device="cuda"))
+    assert torch.equal(O, ref)
+    S = spk.sddmm(dA, Ud, Vd)
+    P_ref = spk.csr_row_softmax(dA, S.clone())
+    from paper_2604_27985_amd import _lib
+    import ctypes
+    ns = int(_lib.load().row_softmax_workspace_bytes(ctypes.byref(dA.c(use_vals=False))))
+    with pytest.raises(spk.SpkError):
+        spk.csr_row_softmax(dA, S.clone(), workspace=torch.empty(ns - 1, dtype=torch.uint8, device="cuda"))
+    P = spk.csr_row_softmax(dA, S.clone(), workspace=torch.empty(ns, dtype=torch.uint8, device="cuda"))
+    assert torch.equal(P, P_ref)
+
+
 def test_attention_bf16_empty_rows_and_strides(spk):
     A = host_csr(7, 40, [[], [3], [0, 1, 2, 39], [], [5, 6, 30], [7], list(range(0, 40, 2))])
     K1, K2, ld = 32, 64, 72
