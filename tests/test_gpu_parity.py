@@ -382,6 +382,32 @@ def test_adjoint_identity_on_gpu(spk):
     assert abs(lhs - rhs) <= 2 * TOL_F32 * scale
 
 
+@pytest.mark.parametrize("K", [40, 100, 200, 300])
+def test_merge_fixup_long_runs(spk, K):
+    """One row of 5000 entries among short and empty rows, merge-path shares
+    of 16 (rows + entries): the long row's carries span hundreds of shares,
+    summed in batches of 1, 2 or 4 column blocks of 64 by K (300: one more
+    pass over the columns); F32, F64 and BF16 dense operands."""
+    n = 6000
+    rows = [list(range(0, 5000))] + [[7, 900, 5999], [], [1], list(range(100, 160))] * 20
+    A = host_csr(len(rows), n, rows)
+    v = synth.normal(A.nnz, 13, synth.S_VALS)
+    B = synth.normal((n, K), 13, synth.S_B)
+    C64, M = oracle.spmm(A.row_ptr, A.col_idx, v, B)
+    dA = spk.CSR.from_host(A, v)
+    for plan in (spk.Plan(1, 16, 16), spk.Plan(1, 64, 16), spk.Plan(1, 8, 40)):
+        C = spk.spmm(dA, dev(B), plan=plan)
+        assert_within(C.cpu().numpy(), C64, M, TOL_F32, f"merge long runs K={K} {plan.name()}")
+        assert torch.equal(C, spk.spmm(dA, dev(B), plan=plan))  # run to run
+    dA64 = spk.CSR.from_host(A, v, vals_dtype=torch.float64)
+    C = spk.spmm(dA64, dev(B, torch.float64), plan=spk.Plan(1, 16, 16)).cpu().numpy()
+    assert_within(C, C64, M, TOL_F64, f"f64 merge long runs K={K}")
+    Br = oracle.round_bf16(B)
+    Cr64, Mr = oracle.spmm(A.row_ptr, A.col_idx, v, Br)
+    C = spk.spmm(dA, dev(Br).to(torch.bfloat16), plan=spk.Plan(1, 16, 16)).cpu().numpy()
+    assert_within(C, Cr64, Mr, TOL_F32, f"bf16 merge long runs K={K}")
+
+
 # ------------------------------------------------------------------ FP64
 def test_f64_kernels_match_oracle(spk):
     A, v, B, U = problem(900, 700, 0.03, 24, 11)
