@@ -158,18 +158,23 @@ def test_attention_bf16_empty_rows_and_strides(spk):
     assert not O.any() and bool(torch.isneginf(lse).all())
 
 
-@pytest.mark.parametrize("kind", ["powerlaw", "short", "hub"])
+@pytest.mark.parametrize("kind", ["powerlaw", "short", "hub", "long"])
 def test_row_softmax_matches_oracle(spk, kind):
     """Every row's probabilities and log-normaliser.  "short": rows of about
     three entries and many empty rows, so one run of scores spans hundreds of
-    rows; "hub": one row of every column beside single-entry rows."""
+    rows; "hub": one row of every column beside single-entry rows; "long": a
+    row of 80000 entries, cut into more than 256 runs, whose pieces the
+    fix-up combines in several batches."""
     if kind == "powerlaw":
         A = synth.powerlaw(20000, 16, 2.1, 3)
     elif kind == "short":
         A = synth.bernoulli(30000, 30000, 1e-4, 3)
-    else:
+    elif kind == "hub":
         rows = [[j] for j in range(0, 3000, 7)] + [list(range(3000))] + [[], [5]] * 50
         A = host_csr(len(rows), 3000, rows)
+    else:
+        rows = [[3, 9], list(range(80000)), [], [79999]]
+        A = host_csr(len(rows), 80000, rows)
     v, U, V, B = operands(A, 16, 4, 3)
     S64, _ = oracle.sddmm(A.row_ptr, A.col_idx, v, U, V)
     dA = spk.CSR.from_host(A, v)
