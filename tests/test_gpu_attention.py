@@ -108,6 +108,20 @@ def test_attention_fold_boundaries(spk):
     check(O.cpu().numpy(), lse.cpu().numpy(), ref, 64, "fold boundaries")
 
 
+def test_attention_many_folds(spk):
+    """A row of 80000 entries in runs of 3: 26667 pieces, 417 folds of 64,
+    which the fix-up combines in several batches; beside it short and empty
+    rows."""
+    rows = [[3, 9], list(range(80000)), [], [79999], list(range(0, 80000, 1000))]
+    A = host_csr(len(rows), 80000, rows)
+    v, U, V, B = operands(A, 16, 16, 9)
+    ref = oracle.sddmm_softmax_spmm(A.row_ptr, A.col_idx, v, U, V, B)
+    dA = spk.CSR.from_host(A, v)
+    for plan in (spk.Plan(1, 8, 3), spk.Plan(1, 4, 5)):
+        O, lse = spk.attention(dA, dev(U), dev(V), dev(B), plan=plan, with_lse=True)
+        check(O.cpu().numpy(), lse.cpu().numpy(), ref, 16, f"many folds {plan}")
+
+
 def test_attention_and_softmax_workspace_sizes(spk):
     """Caller workspaces: one byte short is refused before any launch; the
     exact size gives the same bits as the library-sized call (entry-split
