@@ -437,9 +437,10 @@ int32_t plan_count(int32_t op);
  *           per quad (flags bit 2) for the last four;
  *   wide    SpMM 24, 25 / SDDMM 23, 24: one entry per quad in wide
  *           workgroups (flags 12), slabs of 32 and 64 KiB of F32 rows;
- *   SLAB16  SpMM 26, 27 / SDDMM 25, 26: the column-slab form with 2 or 8 MiB
- *           of F32 rows per slab (between 256 and 65536 columns), the plain
- *           lanes (SDDMM: 8, widened until a lane holds at most 8 columns);
+ *   SLAB16  SpMM 26, 27 / SDDMM 25, 26: the column-slab form with 4 (SpMM;
+ *           SDDMM 2) or 8 MiB of F32 rows per slab (between 256 and 65536
+ *           columns), the plain lanes (SDDMM: 8, widened until a lane holds
+ *           at most 8 columns);
  *   DCSR    SpMM 28 (plain lanes), 29 (4 lanes) / SDDMM 27;
  *   COO     SDDMM 28: 16 lanes, runs of 16 entries.
  * Slab widths count F32 rows; BF16 slabs of the same width take half the

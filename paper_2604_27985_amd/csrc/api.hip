@@ -794,12 +794,14 @@ int32_t plan_of_index(int32_t op, int32_t index, int64_t K, int32_t dtype, spk_p
         const int64_t w = (index == wide_first ? 32768 : 65536) / (4 * k);
         *out = spk_plan{SPK_VAR_TILE, tile_lanes, static_cast<int32_t>(w > 0 ? w : 1), 12};
     } else if (index == wide_first + 2 || index == wide_first + 3) {
-        // column-slab form: 2 or 8 MiB of the dense operand per slab; SDDMM
-        // groups of 8 lanes widened until a lane holds at most 8 columns
+        // column-slab form: 4 (SpMM; SDDMM 2) or 8 MiB of the dense operand
+        // per slab; SDDMM groups of 8 lanes widened until a lane holds at
+        // most 8 columns
         int32_t s16_lanes = 8;
         while (s16_lanes < 64 && s16_lanes * 8 < k) s16_lanes <<= 1;
+        const int64_t small = op == SPK_OP_SPMM ? 4 << 20 : 2 << 20;
         *out = spk_plan{SPK_VAR_SLAB16, op == SPK_OP_SPMM ? row_lanes : s16_lanes,
-                        slab16_width(index == wide_first + 2 ? 2 << 20 : 8 << 20), 0};
+                        slab16_width(index == wide_first + 2 ? small : 8 << 20), 0};
     } else if (index == wide_first + 4) {
         *out = spk_plan{SPK_VAR_DCSR, row_lanes, 0, 0};
     } else if (index == wide_first + 5) {
