@@ -23,10 +23,14 @@ def test_plan_lists():
     assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in pl[16:24]] == [
         (4, 16, 64, 0), (4, 16, 128, 0), (4, 16, 64, 2), (4, 16, 128, 2), (4, 16, 64, 4), (4, 16, 64, 6),
         (4, 16, 128, 4), (4, 16, 128, 6)]
-    # wide quad plans (32 and 64 KiB slabs), the column-slab form (2 and 8 MiB
+    # wide quad plans (32 and 64 KiB slabs), the column-slab form (4 and 8 MiB
     # of B per slab), doubly compressed rows (plain lanes, then 4)
     assert [(p.variant, p.lanes, p.chunk, p.flags) for p, _ in pl[24:]] == [
-        (4, 16, 128, 12), (4, 16, 256, 12), (5, 16, 8192, 0), (5, 16, 32768, 0), (6, 16, 0, 0), (6, 4, 0, 0)]
+        (4, 16, 128, 12), (4, 16, 256, 12), (5, 16, 16384, 0), (5, 16, 32768, 0), (6, 16, 0, 0), (6, 4, 0, 0)]
+    # SDDMM column-slab plans: 2 and 8 MiB, groups of 8 lanes widened until a
+    # lane holds at most 8 columns (K = 128: 16 lanes)
+    sd = selector.plan_list(_lib.OP_SDDMM, 128)
+    assert [(p.variant, p.lanes, p.chunk) for p, _ in sd[25:27]] == [(5, 16, 4096), (5, 16, 16384)]
     assert all(ok for _, ok in pl[16:])
     for K, ok in ((8, True), (36, False), (256, True), (512, False)):
         assert all(v == ok for _, v in selector.plan_list(_lib.OP_SPMM, K)[16:25]), K
