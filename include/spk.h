@@ -439,8 +439,9 @@ int32_t plan_count(int32_t op);
  *           workgroups (flags 12), slabs of 32 and 64 KiB of F32 rows;
  *   SLAB16  SpMM 26, 27 / SDDMM 25, 26: the column-slab form with 4 (SpMM;
  *           SDDMM 2) or 8 MiB of F32 rows per slab (between 256 and 65536
- *           columns), the plain lanes (SDDMM: 8, widened until a lane holds
- *           at most 8 columns);
+ *           columns); SpMM 26 the plain lanes, SDDMM and SpMM 27 8 lanes
+ *           widened until a lane holds at most 8 columns (SpMM 27: at least
+ *           16, at most the plain lanes);
  *   DCSR    SpMM 28 (plain lanes), 29 (4 lanes) / SDDMM 27;
  *   COO     SDDMM 28: 16 lanes, runs of 16 entries.
  * Slab widths count F32 rows; BF16 slabs of the same width take half the

@@ -796,12 +796,17 @@ int32_t plan_of_index(int32_t op, int32_t index, int64_t K, int32_t dtype, spk_p
     } else if (index == wide_first + 2 || index == wide_first + 3) {
         // column-slab form: 4 (SpMM; SDDMM 2) or 8 MiB of the dense operand
         // per slab; SDDMM groups of 8 lanes widened until a lane holds at
-        // most 8 columns
+        // most 8 columns; the 8 MiB SpMM plan likewise, with at least 16
+        // lanes and no more than the plain ones
         int32_t s16_lanes = 8;
         while (s16_lanes < 64 && s16_lanes * 8 < k) s16_lanes <<= 1;
         const int64_t small = op == SPK_OP_SPMM ? 4 << 20 : 2 << 20;
-        *out = spk_plan{SPK_VAR_SLAB16, op == SPK_OP_SPMM ? row_lanes : s16_lanes,
-                        slab16_width(index == wide_first + 2 ? small : 8 << 20), 0};
+        int32_t lanes = s16_lanes;
+        if (op == SPK_OP_SPMM) {
+            const int32_t wide_lanes = s16_lanes < 16 ? 16 : s16_lanes;
+            lanes = index == wide_first + 2 || wide_lanes > row_lanes ? row_lanes : wide_lanes;
+        }
+        *out = spk_plan{SPK_VAR_SLAB16, lanes, slab16_width(index == wide_first + 2 ? small : 8 << 20), 0};
     } else if (index == wide_first + 4) {
         *out = spk_plan{SPK_VAR_DCSR, row_lanes, 0, 0};
     } else if (index == wide_first + 5) {

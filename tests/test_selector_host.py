@@ -31,6 +31,9 @@ def test_plan_lists():
     # lane holds at most 8 columns (K = 128: 16 lanes)
     sd = selector.plan_list(_lib.OP_SDDMM, 128)
     assert [(p.variant, p.lanes, p.chunk) for p, _ in sd[25:27]] == [(5, 16, 4096), (5, 16, 16384)]
+    # SpMM at K = 128: plain lanes for 4 MiB slabs, 16 lanes for 8 MiB
+    sp = selector.plan_list(_lib.OP_SPMM, 128)
+    assert [(p.variant, p.lanes, p.chunk) for p, _ in sp[26:28]] == [(5, 32, 8192), (5, 16, 16384)]
     assert all(ok for _, ok in pl[16:])
     for K, ok in ((8, True), (36, False), (256, True), (512, False)):
         assert all(v == ok for _, v in selector.plan_list(_lib.OP_SPMM, K)[16:25]), K
