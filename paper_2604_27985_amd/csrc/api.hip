@@ -191,7 +191,11 @@ int32_t check_ws(size_t need, const void *ws, size_t ws_bytes) {
     return SPK_OK;
 }
 
-int32_t hip_status(hipError_t e) { return e == hipSuccess ? SPK_OK : SPK_ERR_HIP; }
+// kGridTooLarge marks a launch whose grid would pass the 32-bit work-item
+// count of a dispatch: a shape beyond what the plan can cover.
+int32_t hip_status(hipError_t e) {
+    return e == hipSuccess ? SPK_OK : e == kGridTooLarge ? SPK_ERR_SIZE : SPK_ERR_HIP;
+}
 
 size_t spmm_ws(int64_t m, int64_t n, int64_t nnz, int64_t K, int32_t dt, const Resolved &r, bool permuted) {
     if (m == 0 || K == 0) return 0;

@@ -426,7 +426,7 @@ static hipError_t launch_attn(const AttnArgs &a, hipStream_t s) {
         }
         if (L.ngroups == 0) return hipSuccess;
         const int64_t nb = (L.ngroups + GPB - 1) / GPB;
-        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        if (!grid_fits(nb, kBlock)) return kGridTooLarge;
         hipLaunchKernelGGL((attn_split_kernel<T, VW, LANES, NS>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s,
                            a.m, a.nnz, static_cast<int>(a.K1), static_cast<int>(a.K2), a.rp, a.ci, a.vals,
                            static_cast<const T *>(a.U), a.ldu, static_cast<const T *>(a.V), a.ldv,
@@ -444,7 +444,7 @@ static hipError_t launch_attn(const AttnArgs &a, hipStream_t s) {
         return hipGetLastError();
     }
     const int64_t nb = (a.m + GPB - 1) / GPB;
-    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
     hipLaunchKernelGGL((attn_rows_kernel<T, VW, LANES, NS>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, a.m,
                        static_cast<int>(a.K1), static_cast<int>(a.K2), a.rp, a.ci, a.vals,
                        static_cast<const T *>(a.U), a.ldu, static_cast<const T *>(a.V), a.ldv,

@@ -146,7 +146,8 @@ static hipError_t launch_bsr(const Bsr4Args &a, hipStream_t s) {
     const int64_t mb = (a.m + 3) / 4;
     const int64_t nb = (mb + (kBlock / kWave) - 1) / (kBlock / kWave);
     const int64_t ktiles = (a.K + kWave * VW - 1) / (kWave * VW);
-    if (nb > 0x7FFFFFFF || ktiles > 65535) return hipErrorInvalidValue;
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
+    if (ktiles > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL((spmm_bsr4_kernel<TB, VW>), dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)),
                        dim3(kBlock), 0, s, a.m, a.n, mb, static_cast<int>(a.K), a.b_rp, a.b_col, a.b_vals,
                        static_cast<const TB *>(a.B), a.ldb, a.C, a.ldc);

@@ -116,6 +116,23 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// A dispatch counts the work-items of each grid dimension (blocks times
+// threads per block) in 32 bits.  Launchers check their block count with this
+// and return kGridTooLarge, which the ABI reports as a size error, rather than
+// hand the runtime a grid it refuses.
+constexpr hipError_t kGridTooLarge = hipErrorInvalidConfiguration;
+inline bool grid_fits(int64_t blocks, int threads) {
+    return blocks >= 0 && blocks <= static_cast<int64_t>(0xFFFFFFFFu) / threads;
+}
+
+// Kernels that give one wave to each row stride over the rows past their
+// grid: at most 2^16 workgroups (2^24 threads), which fill the chip many
+// times over and stay far below that count for any row count.
+inline unsigned wave_rows_grid(int64_t rows) {
+    const int64_t nb = (rows + kBlock / kWave - 1) / (kBlock / kWave);
+    return static_cast<unsigned>(nb < 65536 ? nb : 65536);
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin.  Renumber them so
 // that each XCD works on one contiguous range of logical blocks: rows that
 // are close together (and, for banded or clustered patterns, the dense rows

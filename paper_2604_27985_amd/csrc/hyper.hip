@@ -48,20 +48,20 @@ hipError_t nonempty_order_launch(int64_t m, const int32_t *rp, int32_t *order, i
     return hipGetLastError();
 }
 
-// One wave per row writes the row's number over its range.
+// One wave per row (striding over the rows past the grid) writes the row's
+// number over its range.
 __global__ __launch_bounds__(kBlock) void row_index_kernel(int64_t m, const int32_t *__restrict__ rp,
                                                            int32_t *__restrict__ rowidx) {
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
-    if (row >= m) return;
-    for (int64_t p = rp[row] + (threadIdx.x & (kWave - 1)); p < rp[row + 1]; p += kWave)
-        rowidx[p] = static_cast<int32_t>(row);
+    const int64_t step = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    for (int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave; row < m;
+         row += step)
+        for (int64_t p = rp[row] + (threadIdx.x & (kWave - 1)); p < rp[row + 1]; p += kWave)
+            rowidx[p] = static_cast<int32_t>(row);
 }
 
 hipError_t row_index_launch(int64_t m, const int32_t *rp, int32_t *rowidx, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    constexpr int rpb = kBlock / kWave;
-    hipLaunchKernelGGL(row_index_kernel, dim3(static_cast<unsigned>((m + rpb - 1) / rpb)), dim3(kBlock), 0, s, m, rp,
-                       rowidx);
+    hipLaunchKernelGGL(row_index_kernel, dim3(wave_rows_grid(m)), dim3(kBlock), 0, s, m, rp, rowidx);
     return hipGetLastError();
 }
 

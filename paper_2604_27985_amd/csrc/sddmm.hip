@@ -369,16 +369,18 @@ __global__ __launch_bounds__(kBlock) void sddmm_coo_kernel(int64_t nnz, int K, c
 // apos[s m + row] + k, where its value is read and its output written (the
 // runs of a row cover its entries once, so every output is written by one
 // group).  One launch covers every (slab, row block) item in slab-major
-// order, renumbered so that each XCD takes a contiguous range of it: an XCD
-// works through one slab (or part of one) at a time, and the rows of V it
-// gathers come from that slab alone, which its own 4 MiB L2 holds when the
-// slab fits (2 MiB: 4096 columns of 512-byte rows).  Outputs are per entry,
-// so items running at once on different XCDs never share one.
+// order (or several launches of whole slabs, each from item blk0, where the
+// items pass a grid's work-item count), renumbered so that each XCD takes a
+// contiguous range of it: an XCD works through one slab (or part of one) at a
+// time, and the rows of V it gathers come from that slab alone, which its own
+// 4 MiB L2 holds when the slab fits (2 MiB: 4096 columns of 512-byte rows).
+// Outputs are per entry, so items running at once on different XCDs never
+// share one.
 template <typename TUV, typename TV, int VW, int LANES, int NS, bool OFF32>
 __global__ __launch_bounds__(kBlock) void sddmm_s16_kernel(int64_t m, int K, const int32_t *__restrict__ seg,
                                                            const int32_t *__restrict__ apos,
                                                            const uint16_t *__restrict__ col16, int64_t nbr,
-                                                           int32_t width, const TV *__restrict__ vals,
+                                                           int64_t blk0, int32_t width, const TV *__restrict__ vals,
                                                            const TUV *__restrict__ U, int64_t ldu,
                                                            const TUV *__restrict__ V, int64_t ldv,
                                                            typename acc_of<TUV>::type *__restrict__ S) {
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void sddmm_s16_kernel(int64_t m, int K, con
     const int lane = threadIdx.x & (kWave - 1);
     const int lig = threadIdx.x & (LANES - 1);
     const int gbase = lane & ~(LANES - 1);
-    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t blk = blk0 + xcd_block(blockIdx.x, gridDim.x);
     const int64_t s = blk / nbr;
     const int64_t row = (blk - s * nbr) * GPB + threadIdx.x / LANES;
     if (row >= m) return;
@@ -739,7 +741,8 @@ static hipError_t launch_tileq_rpg(const SddmmArgs &a, hipStream_t s) {
     constexpr int64_t round = BS * 16;
     const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
     const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TUV));
-    if (nb > 0x7FFFFFFF || a.K * static_cast<int64_t>(sizeof(TUV)) != 64 * NP || a.chunk < 1 ||
+    if (!grid_fits(nb, BS)) return kGridTooLarge;
+    if (a.K * static_cast<int64_t>(sizeof(TUV)) != 64 * NP || a.chunk < 1 ||
         2 * slab_bytes > (BS == 1024 ? 2 : 1) * static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
         return hipErrorInvalidValue;
     if (slab_bytes <= 2 * round) return launch_tileq_npt<TUV, TV, NP, RPG, 2, BS>(a, s);
@@ -787,7 +790,8 @@ static hipError_t launch_tile_rpg(const SddmmArgs &a, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
     const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
     const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TUV));
-    if (nb > 0x7FFFFFFF || a.K > LANES * 4 || a.chunk < 1 || 2 * slab_bytes > kTileLds || a.n > 0x7FFFFFFF)
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
+    if (a.K > LANES * 4 || a.chunk < 1 || 2 * slab_bytes > kTileLds || a.n > 0x7FFFFFFF)
         return hipErrorInvalidValue;
     if (slab_bytes <= 2 * kTilePiece) return launch_tile_npt<TUV, TV, LANES, RPG, 2>(a, s);
     if (slab_bytes <= 4 * kTilePiece) return launch_tile_npt<TUV, TV, LANES, RPG, 4>(a, s);
@@ -812,7 +816,7 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
     if (a.variant == SPK_VAR_MERGE) {
         const int64_t ngroups = (a.nnz + a.chunk - 1) / a.chunk;
         const int64_t nb = (ngroups + GPB - 1) / GPB;
-        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        if (!grid_fits(nb, kBlock)) return kGridTooLarge;
         hipLaunchKernelGGL((sddmm_split_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
                            dim3(kBlock), 0, s, a.m, a.nnz, static_cast<int>(a.K), a.rp, a.ci,
                            static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
@@ -822,7 +826,8 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
     if (a.variant == SPK_VAR_DCSR) {
         if (a.hv.nrows <= 0) return hipSuccess;
         const int64_t nb = (a.hv.nrows + GPB - 1) / GPB;
-        if (nb > 0x7FFFFFFF || a.hv.nrows > a.m) return hipErrorInvalidValue;
+        if (!grid_fits(nb, kBlock)) return kGridTooLarge;
+        if (a.hv.nrows > a.m) return hipErrorInvalidValue;
         hipLaunchKernelGGL((sddmm_dcsr_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
                            dim3(kBlock), 0, s, a.hv.nrows, static_cast<int>(a.K), a.hv.order, a.rp, a.ci,
                            static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
@@ -832,7 +837,7 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
     if (a.variant == SPK_VAR_COO) {
         const int64_t ngroups = (a.nnz + a.chunk - 1) / a.chunk;
         const int64_t nb = (ngroups + GPB - 1) / GPB;
-        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        if (!grid_fits(nb, kBlock)) return kGridTooLarge;
         hipLaunchKernelGGL((sddmm_coo_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
                            dim3(kBlock), 0, s, a.nnz, static_cast<int>(a.K), a.hv.rowidx, a.ci,
                            static_cast<const TV *>(a.vals), static_cast<const TUV *>(a.U), a.ldu,
@@ -841,14 +846,22 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
     }
     if (a.variant == SPK_VAR_SLAB16) {
         const int64_t nbr = (a.m + GPB - 1) / GPB;  // row blocks per slab
+        if (!grid_fits(nbr, kBlock)) return kGridTooLarge;
+        if (a.s16.nslabs < 1 || a.s16.width > 65536) return hipErrorInvalidValue;
+        // Whole slabs per launch, as many as the grid's work-item count holds.
+        const int64_t per = (static_cast<int64_t>(0xFFFFFFFFu) / kBlock / nbr) * nbr;
         const int64_t nb = a.s16.nslabs * nbr;
-        if (nb > 0x7FFFFFFF || a.s16.nslabs < 1 || a.s16.width > 65536) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((sddmm_s16_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
-                           dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.s16.seg, a.s16.apos, a.s16.col16, nbr,
-                           static_cast<int32_t>(a.s16.width), static_cast<const TV *>(a.vals),
-                           static_cast<const TUV *>(a.U), a.ldu, static_cast<const TUV *>(a.V), a.ldv,
-                           static_cast<A *>(a.S));
-        return hipGetLastError();
+        for (int64_t b0 = 0; b0 < nb; b0 += per) {
+            const int64_t cnt = nb - b0 < per ? nb - b0 : per;
+            hipLaunchKernelGGL((sddmm_s16_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(cnt)),
+                               dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.s16.seg, a.s16.apos, a.s16.col16,
+                               nbr, b0, static_cast<int32_t>(a.s16.width), static_cast<const TV *>(a.vals),
+                               static_cast<const TUV *>(a.U), a.ldu, static_cast<const TUV *>(a.V), a.ldv,
+                               static_cast<A *>(a.S));
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
     int nslabs = 1;
     int64_t width = a.n > 0 ? a.n : 1;
@@ -863,7 +876,7 @@ static hipError_t launch(const SddmmArgs &a, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     const int64_t nb = (a.m + GPB - 1) / GPB;
-    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
     for (int sl = 0; sl < nslabs; ++sl) {
         hipLaunchKernelGGL((sddmm_rows_kernel<TUV, TV, VW, LANES, NS, OFF32>), dim3(static_cast<unsigned>(nb)),
                            dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.rp, bnd, nslabs, sl, a.ci,

@@ -599,7 +599,8 @@ static hipError_t launch_tileq_rpg(const SpmmArgs &a, const TV *vals, hipStream_
     constexpr int64_t round = BS * 16;
     const int64_t nb = (a.m + GPB * RPG - 1) / (GPB * RPG);
     const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TB));
-    if (nb > 0x7FFFFFFF || a.K * static_cast<int64_t>(sizeof(TB)) != 64 * NP || a.chunk < 1 ||
+    if (!grid_fits(nb, BS)) return kGridTooLarge;
+    if (a.K * static_cast<int64_t>(sizeof(TB)) != 64 * NP || a.chunk < 1 ||
         2 * slab_bytes > (BS == 1024 ? 2 : 1) * static_cast<int64_t>(kTileLds) || a.n > 0x7FFFFFFF)
         return hipErrorInvalidValue;
     if (slab_bytes <= 2 * round) return launch_tileq_npt<TB, TV, NP, RPG, 2, BS>(a, vals, s);
@@ -819,7 +820,8 @@ static hipError_t launch_rows(const SpmmArgs &a, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
     const int64_t nb = (a.m + GPB - 1) / GPB;
     const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
-    if (nb > 0x7FFFFFFF || ktiles > 65535) return hipErrorInvalidValue;
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
+    if (ktiles > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL((spmm_rows_kernel<TB, TV, VW, LANES, OFF32>), dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)),
                        dim3(kBlock), 0, s, a.m, static_cast<int>(a.K), a.rp, a.ci, static_cast<const TV *>(a.vals),
                        a.vperm, static_cast<const TB *>(a.B), a.ldb,
@@ -836,7 +838,8 @@ static hipError_t launch_slab(const SpmmArgs &a, hipStream_t s) {
     if (e0 != hipSuccess) return e0;
     const int64_t nb = (a.m + GPB - 1) / GPB;
     const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
-    if (nb > 0x7FFFFFFF || ktiles > 65535) return hipErrorInvalidValue;
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
+    if (ktiles > 65535) return hipErrorInvalidValue;
     for (int sl = 0; sl < L.nslabs; ++sl) {
         hipLaunchKernelGGL((spmm_slab_kernel<TB, TV, VW, LANES, OFF32>),
                            dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)), dim3(kBlock), 0, s, a.m,
@@ -854,7 +857,8 @@ static hipError_t launch_s16(const SpmmArgs &a, hipStream_t s) {
     constexpr int GPB = kBlock / LANES;
     const int64_t nb = (a.m + GPB - 1) / GPB;
     const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
-    if (nb > 0x7FFFFFFF || ktiles > 65535 || a.s16.nslabs < 1) return hipErrorInvalidValue;
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
+    if (ktiles > 65535 || a.s16.nslabs < 1) return hipErrorInvalidValue;
     for (int64_t sl = 0; sl < a.s16.nslabs; ++sl) {
         hipLaunchKernelGGL((spmm_s16_kernel<TB, TV, VW, LANES, OFF32>),
                            dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)), dim3(kBlock), 0, s, a.m,
@@ -876,7 +880,7 @@ static hipError_t launch_dcsr(const SpmmArgs &a, hipStream_t s) {
     if (ktiles > 65535 || nr < 0 || nr > a.m) return hipErrorInvalidValue;
     if (nr > 0) {
         const int64_t nb = (nr + GPB - 1) / GPB;
-        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        if (!grid_fits(nb, kBlock)) return kGridTooLarge;
         hipLaunchKernelGGL((spmm_dcsr_kernel<TB, TV, VW, LANES, OFF32>),
                            dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)), dim3(kBlock), 0, s, nr,
                            static_cast<int>(a.K), a.hv.order, a.rp, a.ci, static_cast<const TV *>(a.vals),
@@ -892,7 +896,7 @@ static hipError_t launch_dcsr(const SpmmArgs &a, hipStream_t s) {
         const int64_t pieces = v4 ? a.K / 4 : a.K;
         const int64_t total = empty * pieces;
         const int64_t nb = (total + kBlock - 1) / kBlock;
-        if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+        if (!grid_fits(nb, kBlock)) return kGridTooLarge;
         if (v4)
             hipLaunchKernelGGL((zero_rows_kernel<A, 4>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, empty,
                                pieces, a.hv.order + nr, static_cast<A *>(a.C), a.ldc);
@@ -913,20 +917,22 @@ static hipError_t launch_merge(const SpmmArgs &a, hipStream_t s) {
     int32_t *part = reinterpret_cast<int32_t *>(ws + L.part_off);
     int32_t *carry_row = reinterpret_cast<int32_t *>(ws + L.row_off);
     A *carry_val = reinterpret_cast<A *>(ws + L.val_off);
+    const int64_t nb = (L.ngroups + GPB - 1) / GPB;
+    const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
+    constexpr int kWpb = kBlock / kWave;  // fix-up: one wave per group
+    if (!grid_fits(nb, kBlock) || !grid_fits((L.ngroups + kWpb - 1) / kWpb, kBlock)) return kGridTooLarge;
+    if (ktiles > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(merge_partition_kernel, dim3(grid1(L.ngroups + 1, kBlock)), dim3(kBlock), 0, s, a.m, a.nnz,
                        a.rp, L.items, L.ngroups, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t nb = (L.ngroups + GPB - 1) / GPB;
-    const int64_t ktiles = (a.K + LANES * VW - 1) / (LANES * VW);
-    if (nb > 0x7FFFFFFF || ktiles > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL((spmm_merge_kernel<TB, TV, VW, LANES, OFF32>), dim3(static_cast<unsigned>(nb), static_cast<unsigned>(ktiles)),
                        dim3(kBlock), 0, s, a.m, a.nnz, static_cast<int>(a.K), a.rp, a.ci,
                        static_cast<const TV *>(a.vals), a.vperm, static_cast<const TB *>(a.B), a.ldb,
                        static_cast<A *>(a.C), a.ldc, part, L.items, L.ngroups, carry_row, carry_val);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((merge_fixup_kernel<A>), dim3(grid1(L.ngroups, kBlock / kWave)), dim3(kBlock), 0, s, L.ngroups,
+    hipLaunchKernelGGL((merge_fixup_kernel<A>), dim3(grid1(L.ngroups, kWpb)), dim3(kBlock), 0, s, L.ngroups,
                        static_cast<int>(a.K), carry_row, carry_val, static_cast<A *>(a.C), a.ldc);
     return hipGetLastError();
 }
@@ -956,7 +962,8 @@ static hipError_t launch_tile_rpg(const SpmmArgs &a, const TV *vals, hipStream_t
     const int64_t rows_per_block = (kBlock / LANES) * RPG;
     const int64_t nb = (a.m + rows_per_block - 1) / rows_per_block;
     const int64_t slab_bytes = a.chunk * a.K * static_cast<int64_t>(sizeof(TB));
-    if (nb > 0x7FFFFFFF || a.K > LANES * VW || a.chunk < 1 || 2 * slab_bytes > kTileLds || a.n > 0x7FFFFFFF)
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
+    if (a.K > LANES * VW || a.chunk < 1 || 2 * slab_bytes > kTileLds || a.n > 0x7FFFFFFF)
         return hipErrorInvalidValue;
     // copy rounds per slab: 2, 4 or 8 (a buffer of 8, 16 or 32 KiB)
     if (slab_bytes <= 2 * kTilePiece) return launch_tile_npt<TB, TV, VW, LANES, RPG, 2>(a, vals, s);
@@ -1038,7 +1045,7 @@ hipError_t zero_fill(void *C, int64_t m, int64_t K, int64_t ld, int32_t dtype, h
     const int64_t total = m * K;
     if (total == 0) return hipSuccess;
     const int64_t nb = (total + kBlock - 1) / kBlock;
-    if (nb > 0x7FFFFFFF) return hipErrorInvalidValue;
+    if (!grid_fits(nb, kBlock)) return kGridTooLarge;
     if (dtype == SPK_F64)
         hipLaunchKernelGGL((fill_zero_kernel<double>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, m, K,
                            static_cast<double *>(C), ld);

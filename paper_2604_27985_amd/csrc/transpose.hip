@@ -116,13 +116,15 @@ __global__ void fill_i32_kernel(int32_t *__restrict__ a, int64_t count, int32_t 
     if (i < count) a[i] = v;
 }
 
-// rowid[p] = row of entry p: one wave per row writes its range.
+// rowid[p] = row of entry p: one wave per row (striding over the rows past
+// the grid) writes its range.
 __global__ __launch_bounds__(kBlock) void row_ids_kernel(int64_t m, const int32_t *__restrict__ rp,
                                                          int32_t *__restrict__ rowid) {
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
-    if (row >= m) return;
-    for (int64_t p = rp[row] + (threadIdx.x & (kWave - 1)); p < rp[row + 1]; p += kWave)
-        rowid[p] = static_cast<int32_t>(row);
+    const int64_t step = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+    for (int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave; row < m;
+         row += step)
+        for (int64_t p = rp[row] + (threadIdx.x & (kWave - 1)); p < rp[row + 1]; p += kWave)
+            rowid[p] = static_cast<int32_t>(row);
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -269,7 +271,7 @@ hipError_t transpose_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
     }
     // Columns of A^T: the row of each sorted position.
     int32_t *rowid = kb[passes & 1];  // the key buffer the last pass did not write
-    hipLaunchKernelGGL(row_ids_kernel, dim3(blocks_for(m, kBlock / kWave)), dim3(kBlock), 0, s, m, rp, rowid);
+    hipLaunchKernelGGL(row_ids_kernel, dim3(wave_rows_grid(m)), dim3(kBlock), 0, s, m, rp, rowid);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(nnz, kBlock)), dim3(kBlock), 0, s, nnz, perm, rowid, tci);
     return hipGetLastError();
@@ -280,20 +282,23 @@ hipError_t transpose_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
 // Rules of canonical CSR, one bit each (the same numbering as spk.h).
 enum { kBadStart = 1, kBadEnd = 2, kBadOrder = 4, kBadCol = 8, kBadSort = 16, kBadDup = 32 };
 
-// One wave per row: the row's range is checked first; only a range inside
-// [0, nnz] is read, so a broken row_ptr never sends a load out of bounds.
+// One wave per row, striding over the rows past the grid: the row's range is
+// checked first; only a range inside [0, nnz] is read, so a broken row_ptr
+// never sends a load out of bounds.
 __global__ __launch_bounds__(kBlock) void validate_kernel(int64_t m, int64_t n, int64_t nnz, const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ ci, int32_t *__restrict__ flag) {
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    if (row >= m) return;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
     int bad = 0;
-    if (row == 0 && lane == 0 && rp[0] != 0) bad |= kBadStart;
-    if (row == m - 1 && lane == 0 && rp[m] != nnz) bad |= kBadEnd;
-    const int64_t a = rp[row], b = rp[row + 1];
-    if (b < a || a < 0 || b > nnz) {
-        if (lane == 0) bad |= kBadOrder;
-    } else {
+    for (int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave; row < m;
+         row += step) {
+        if (row == 0 && lane == 0 && rp[0] != 0) bad |= kBadStart;
+        if (row == m - 1 && lane == 0 && rp[m] != nnz) bad |= kBadEnd;
+        const int64_t a = rp[row], b = rp[row + 1];
+        if (b < a || a < 0 || b > nnz) {
+            if (lane == 0) bad |= kBadOrder;
+            continue;
+        }
         for (int64_t p = a + lane; p < b; p += kWave) {
             const int32_t c = ci[p];
             if (c < 0 || c >= n) bad |= kBadCol;
@@ -312,7 +317,7 @@ hipError_t validate_launch(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(kBlock), 0, s, flag, 1, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || m == 0) return e;  // no rows: the caller checks nnz
-    hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(m, kBlock / kWave)), dim3(kBlock), 0, s, m, n, nnz, rp, ci, flag);
+    hipLaunchKernelGGL(validate_kernel, dim3(wave_rows_grid(m)), dim3(kBlock), 0, s, m, n, nnz, rp, ci, flag);
     return hipGetLastError();
 }
 

@@ -106,3 +106,33 @@ def test_full_size_sampled(spk):
             del Bd, Ud, C, S
         del dA
         torch.cuda.empty_cache()
+
+
+def test_slab16_past_one_grid(spk):
+    """n = 2^21 at density 1e-7, K = 64, on the 2 MiB column-slab plan
+    (W = 8192, 8 lanes): its 256 slabs of 65536 row blocks hold 2^32 threads,
+    past one grid's 32-bit work-item count, so the SDDMM takes two launches of
+    whole slabs.  Every row with an entry in the last slab (the second launch),
+    the first and last rows and sampled rows against the oracle, for the SDDMM
+    and for the SpMM on the same plan."""
+    n, K, W = 1 << 21, 64, 8192
+    A = synth.bernoulli(n, n, 1e-7, 0)
+    v = synth.normal(A.nnz, 0, synth.S_VALS)
+    row_of = np.repeat(np.arange(n), np.diff(A.row_ptr.astype(np.int64)))
+    last = np.unique(row_of[A.col_idx >= n - W])
+    assert len(last) > 0
+    rows = np.unique(np.concatenate([[0, n - 1], last, synth.randint(4000, n, 13)]))
+    srp, sci, idx = sub_rows(A, rows)
+    U = synth.normal((n, K), 0, synth.S_U)
+    V = synth.normal((n, K), 0, synth.S_V)
+    S64, SM = oracle.sddmm(srp, sci, v[idx], U[rows], V)
+    C64, CM = oracle.spmm(srp, sci, v[idx], V)
+    dA = spk.CSR.from_host(A, v)
+    Ud, Vd = dev(U), dev(V)
+    plan = spk.Plan(5, 8, W)
+    S = spk.sddmm(dA, Ud, Vd, plan=plan)
+    assert_within(S[torch.from_numpy(idx).cuda()].cpu().numpy(), S64, SM, TOL_F32, "slab16 sddmm n=2^21 W=8192")
+    C = spk.spmm(dA, Vd, plan=plan)
+    assert_within(C[torch.from_numpy(rows).cuda()].cpu().numpy(), C64, CM, TOL_F32, "slab16 spmm n=2^21 W=8192")
+    del dA, Ud, Vd, S, C
+    torch.cuda.empty_cache()
