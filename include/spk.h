@@ -53,7 +53,10 @@ enum spk_dtype {
 enum spk_status {
     SPK_OK = 0,
     SPK_ERR_NULL = -1,        /* a required pointer is NULL */
-    SPK_ERR_SIZE = -2,        /* negative size, nnz >= 2^31, or n > 2^31-1 */
+    SPK_ERR_SIZE = -2,        /* negative size, nnz >= 2^31, n > 2^31-1, or a
+                                 shape whose launch under the plan would need a
+                                 grid of 2^32 or more threads (one-dimensional
+                                 grids count work-items in 32 bits) */
     SPK_ERR_DTYPE = -3,       /* unsupported dtype combination */
     SPK_ERR_LD = -4,          /* leading dimension smaller than K */
     SPK_ERR_WORKSPACE = -5,   /* workspace NULL or smaller than required */
