@@ -116,7 +116,9 @@ enum spk_variant {
                           16-lane group is split one entry per 4-lane quad
                           (the lanes field is then not used; rows of 512
                           bytes keep 4 rows per group); other shapes run the
-                          split above. */
+                          split above.  TILE reads entries at 32-bit
+                          positions plus up to 63 lanes: nnz above 2^31 - 65
+                          gives SPK_ERR_SIZE. */
     SPK_VAR_SLAB16 = 5, /* the column-slab form with 16-bit columns
                            (spmm_slab16 / sddmm_slab16 only): row-split over
                            the slabs of the form, one launch per slab */

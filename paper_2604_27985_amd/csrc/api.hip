@@ -73,6 +73,14 @@ int64_t default_slab_width(int64_t K, size_t es) {
     return w;
 }
 
+// The TILE kernels read a row's entries in chunks at 32-bit positions (the
+// row's current position plus up to 63 lanes), so they take nnz up to
+// 2^31 - 65; the other variants hold positions in 64 bits.
+constexpr int64_t kTileMaxNnz = kMaxIndex - 64;
+int32_t tile_nnz_ok(const Resolved &r, int64_t nnz) {
+    return r.variant == SPK_VAR_TILE && nnz > kTileMaxNnz ? SPK_ERR_SIZE : SPK_OK;
+}
+
 int32_t resolve_spmm(const spk_plan *plan, int64_t K, int32_t b_dtype, const void *B, int64_t ldb, const void *C,
                      int64_t ldc, Resolved &r) {
     r.variant = plan ? plan->variant : SPK_VAR_ROWS;
@@ -352,6 +360,7 @@ int32_t spmm_common(const spk_csr *A, const void *B, int64_t ldb, int32_t b_dtyp
     if (A->nnz == 0) return hip_status(zero_fill(C, A->m, K, ldc, out_dt, s));
     Resolved r;
     if ((st = resolve_spmm(plan, K, b_dtype, B, ldb, C, ldc, r))) return st;
+    if ((st = tile_nnz_ok(r, A->nnz))) return st;
     const size_t need = spmm_ws(A->m, A->n, A->nnz, K, b_dtype, r, false);
     if (from_scratch) {
         if (need > kNoAllocScratchBytes) return SPK_ERR_WORKSPACE;
@@ -395,6 +404,7 @@ int32_t sddmm_csr(const spk_csr *A, const void *U, int64_t ldu, const void *V, i
     if (K > 0 && (ldu < K || ldv < K)) return SPK_ERR_LD;
     Resolved r;
     if ((st = resolve_sddmm(plan, K, uv_dtype, U, ldu, V, ldv, r))) return st;
+    if ((st = tile_nnz_ok(r, A->nnz))) return st;
     if ((st = check_ws(sddmm_ws(A->m, A->n, r), ws, ws_bytes))) return st;
     SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, A->vals, U, ldu, V, ldv, uv_dtype, S,
                 r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group, r.quad_split};
@@ -431,6 +441,7 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
         } else {
             Resolved r;
             if ((st = resolve_spmm(plan, K, dtype, G, ldg, dB, lddb, r))) return st;
+            if ((st = tile_nnz_ok(r, A->nnz))) return st;
             const size_t need = spmm_ws(A->n, A->m, A->nnz, K, dtype, r, true);
             if ((st = check_ws(need, ws, ws_bytes))) return st;
             SpmmArgs a{A->n, A->m, A->nnz, K, at_row_ptr, at_col_idx, A->vals, perm, G, ldg, dtype, dB, lddb,
@@ -445,6 +456,7 @@ int32_t spmm_csr_backward(const spk_csr *A, const int32_t *at_row_ptr, const int
         // share the workspace
         Resolved r;
         if ((st = resolve_sddmm(dvals_plan, K, dtype, G, ldg, B, ldb, r))) return st;
+        if ((st = tile_nnz_ok(r, A->nnz))) return st;
         if ((st = check_ws(sddmm_ws(A->m, A->n, r), ws, ws_bytes))) return st;
         SddmmArgs a{A->m, A->n, A->nnz, K, A->row_ptr, A->col_idx, nullptr, G, ldg, B, ldb, dtype, dvals,
                     r.variant, r.lanes, r.vec, r.chunk, ws, r.rows_per_group, r.quad_split};

@@ -77,8 +77,9 @@ def test_spmm_argument_errors(lib):
 
 def test_tile_plan_limits(lib):
     """TILE plans are refused before launch when they do not fit: groups of K/4
-    lanes at least, slabs within the two-buffer LDS budget, and a slab spanning
-    less than 4 GiB of the dense operand (32-bit copy offsets)."""
+    lanes at least, slabs within the two-buffer LDS budget, a slab spanning
+    less than 4 GiB of the dense operand (32-bit copy offsets), and entry
+    positions that stay within 32 bits."""
     tile = lambda lanes, chunk, flags=0: _lib.spk_plan(4, lanes, chunk, flags)  # noqa: E731
     assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(8, 16)) == -6            # 8 lanes x 4 < 64
     assert spmm(csr(), K=64, ldb=64, ldc=64, plan=tile(16, 129)) == -6          # 2 x 129 x 256 B > 64 KiB
@@ -89,6 +90,12 @@ def test_tile_plan_limits(lib):
     assert f(ctypes.byref(A), FAKE, 64, FAKE, 1 << 25, 0, 64, FAKE, ctypes.byref(tile(16, 32)), None, 0,
              None) == -6
     assert f(ctypes.byref(A), FAKE, 64, FAKE, 64, 0, 64, FAKE, ctypes.byref(tile(8, 16)), None, 0, None) == -6
+    # entries are read at 32-bit positions plus up to 63 lanes: TILE takes nnz
+    # up to 2^31 - 65 and refuses more with SPK_ERR_SIZE
+    big = csr(nnz=2**31 - 64)
+    assert spmm(big, K=64, ldb=64, ldc=64, plan=tile(16, 32)) == -2
+    assert spmm(big, K=64, ldb=64, ldc=64, plan=tile(16, 32, 4)) == -2
+    assert f(ctypes.byref(big), FAKE, 64, FAKE, 64, 0, 64, FAKE, ctypes.byref(tile(16, 32)), None, 0, None) == -2
 
 
 def test_plan_rank_argument_errors(lib):
