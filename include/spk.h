@@ -478,7 +478,7 @@ int32_t selector_inputs(const int64_t *features, int64_t K, int32_t dtype, float
 /* Network y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 for `batch` rows of X
  * (device [batch x F]) into Y (device [batch x P]).  params (device) holds
  * W1[H][F], b1[H], W2[H][H], b2[H], W3[P][H], b3[P] contiguously.
- * F <= 64, H <= 128, P <= 32. */
+ * F <= 64, H <= 192, P <= 32. */
 int32_t mlp_forward(const float *params, int64_t F, int64_t H, int64_t P, const float *X, int64_t batch,
                     float *Y, void *stream);
 

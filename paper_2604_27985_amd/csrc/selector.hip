@@ -21,7 +21,9 @@ namespace spk {
 
 constexpr int kNFeat = 28;
 constexpr int kNIn = 33;
-constexpr int kMaxIn = 64, kMaxHidden = 128, kMaxOut = 32;
+// 192 hidden units: room for the average of three 64-unit networks stacked
+// into one (selector.merge_tables).
+constexpr int kMaxIn = 64, kMaxHidden = 192, kMaxOut = 32;
 constexpr int kTable = 2 * kMaxIn + kMaxHidden * kMaxIn + kMaxHidden + kMaxHidden * kMaxHidden + kMaxHidden +
                        kMaxOut * kMaxHidden + kMaxOut;
 

@@ -440,10 +440,29 @@ def train_op(records: list[dict], op: int, steps: int = 4000, lr: float = 3e-3, 
     trainer = Trainer(P, seed=seed)
     wmask = mask * time_weights(times, tr, weight_power)[:, None] if weight_power > 0 else mask
     hist = trainer.fit(Xs[tr], T[tr], wmask[tr], steps=steps, lr=lr, log=log)
-    Y = trainer.forward(torch.from_numpy(Xs).cuda()).cpu().numpy()
+    table = {"op": int(op), "F": F, "H": trainer.H, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
+             "params": trainer.params.cpu().tolist(), "seed": seed, "steps": steps, "lr": lr,
+             "plans": [p.name() for p, _ in plan_list(op, 64)]}
+    report = evaluate(records, table)
+    report.update({"loss_history": hist, "weight_power": weight_power})
+    return table, report
+
+
+def evaluate(records: list[dict], table: dict) -> dict:
+    """Regret of a network's picks on the train and test splits (first choice,
+    and the best of its first 3 and 5 choices by the recorded times)."""
+    op = table["op"]
+    X, _, mask, times = dataset(records, op)
+    split = np.array([r["split"] for r in records])
+    tr, te = split == "train", split == "test"
+    mean, scale = np.asarray(table["mean"], np.float32), np.asarray(table["scale"], np.float32)
+    Xs = np.ascontiguousarray(((X - mean) / scale).astype(np.float32))
+    net = Trainer(table["P"], table["H"])
+    net.params = torch.tensor(table["params"], dtype=torch.float32, device="cuda")
+    Y = net.forward(torch.from_numpy(Xs).cuda()).cpu().numpy()
     pick = choose(Y, mask)
     plain = np.array([plain_index(op, r["K"]) for r in records])
-    report = {"op": "spmm" if op == OP_SPMM else "sddmm", "loss_history": hist, "weight_power": weight_power,
+    report = {"op": "spmm" if op == OP_SPMM else "sddmm",
               "train": regret_stats(times[tr], pick[tr], plain[tr]),
               "test": regret_stats(times[te], pick[te], plain[te])}
     bf = np.array([r.get("dtype", "f32") == "bf16" for r in records])
@@ -453,10 +472,51 @@ def train_op(records: list[dict], op: int, steps: int = 4000, lr: float = 3e-3, 
     for k in (3, 5):
         pk = best_of_top(Y, mask, times, k)
         report[f"test_best_of_top{k}"] = regret_stats(times[te], pk[te], plain[te])
-    table = {"op": int(op), "F": F, "H": trainer.H, "P": P, "mean": mean.tolist(), "scale": scale.tolist(),
-             "params": trainer.params.cpu().tolist(), "seed": seed, "steps": steps, "lr": lr,
-             "plans": [p.name() for p, _ in plan_list(op, 64)]}
-    return table, report
+    return report
+
+
+def split_params(table: dict) -> list[np.ndarray]:
+    """W1 [H, F], b1 [H], W2 [H, H], b2 [H], W3 [P, H], b3 [P] of a table."""
+    F, H, P = table["F"], table["H"], table["P"]
+    flat = np.asarray(table["params"], np.float64)
+    shapes = [(H, F), (H,), (H, H), (H,), (P, H), (P,)]
+    out, at = [], 0
+    for s in shapes:
+        size = int(np.prod(s))
+        out.append(flat[at:at + size].reshape(s))
+        at += size
+    assert at == flat.size, "parameter count does not match F, H, P"
+    return out
+
+
+def merge_tables(tables: list[dict]) -> dict:
+    """One network whose output is the mean of the members' outputs: hidden
+    layers stacked (layer 1 rows concatenated, layer 2 block-diagonal, so each
+    member's units see only its own), layer 3 side by side scaled by 1/n and
+    the output biases averaged.  Members share op, F, P and the input
+    standardisation (trained on one split of one timing set)."""
+    t0, n = tables[0], len(tables)
+    for t in tables[1:]:
+        if (t["op"], t["F"], t["P"]) != (t0["op"], t0["F"], t0["P"]) or t["mean"] != t0["mean"] or \
+                t["scale"] != t0["scale"]:
+            raise ValueError("members differ in op, sizes or input standardisation")
+    parts = [split_params(t) for t in tables]
+    W1 = np.concatenate([q[0] for q in parts], 0)
+    b1 = np.concatenate([q[1] for q in parts])
+    Hs = [q[2].shape[0] for q in parts]
+    W2 = np.zeros((sum(Hs), sum(Hs)))
+    at = 0
+    for q, h in zip(parts, Hs):
+        W2[at:at + h, at:at + h] = q[2]
+        at += h
+    b2 = np.concatenate([q[3] for q in parts])
+    W3 = np.concatenate([q[4] for q in parts], 1) / n
+    b3 = np.mean([q[5] for q in parts], 0)
+    out = dict(t0)
+    out["H"] = int(sum(Hs))
+    out["params"] = np.concatenate([a.reshape(-1) for a in (W1, b1, W2, b2, W3, b3)]).astype(np.float32).tolist()
+    out["seed"] = [t["seed"] for t in tables]
+    return out
 
 
 # ---------------------------------------------------------------- inference
@@ -585,6 +645,12 @@ def main(argv=None) -> None:
     g.add_argument("--timings", required=True)
     g.add_argument("--ext", required=True)
     g.add_argument("--out", required=True)
+    m = sub.add_parser("ensemble", help="average trained networks of one op into one and evaluate it")
+    m.add_argument("--timings", required=True)
+    m.add_argument("--members", required=True, nargs="+", help="weight files each holding a table of the op")
+    m.add_argument("--op", choices=("spmm", "sddmm"), required=True)
+    m.add_argument("--out", default=WEIGHTS_PATH)
+    m.add_argument("--report", default=None)
     t = sub.add_parser("train", help="train the selector networks on a timing set")
     t.add_argument("--timings", required=True)
     t.add_argument("--out", default=WEIGHTS_PATH)
@@ -613,6 +679,32 @@ def main(argv=None) -> None:
         print(f"merged {merge_timings(args.timings, args.ext, args.out)} extensions", flush=True)
         return
     records = load_timings(args.timings)
+    if args.cmd == "ensemble":
+        op = OP_SPMM if args.op == "spmm" else OP_SDDMM
+        members = []
+        for path in args.members:
+            with open(path) as fh:
+                members += [t for t in json.load(fh)["tables"] if t["op"] == op]
+        table = merge_tables(members)
+        report = evaluate(records, table)
+        report["members"] = table["seed"]
+        print(json.dumps(report), flush=True)
+        tables = [table]
+        if os.path.exists(args.out):  # keep the other op's table
+            with open(args.out) as fh:
+                tables = [t for t in json.load(fh)["tables"] if t["op"] != op] + tables
+        with open(args.out, "w") as fh:
+            json.dump({"format": 1, "device": torch.cuda.get_device_name(0),
+                       "timings": os.path.basename(args.timings), "records": len(records),
+                       "tables": sorted(tables, key=lambda t: t["op"])}, fh)
+        if args.report:
+            kept = []
+            if os.path.exists(args.report):
+                with open(args.report) as fh:
+                    kept = [r for r in json.load(fh) if r["op"] != report["op"]]
+            with open(args.report, "w") as fh:
+                json.dump(sorted(kept + [report], key=lambda r: r["op"] != "spmm"), fh, indent=1)
+        return
     ops = [OP_SPMM if o == "spmm" else OP_SDDMM for o in args.ops.split(",")]
     kept = {}
     if set(ops) != {OP_SPMM, OP_SDDMM} and os.path.exists(args.out):

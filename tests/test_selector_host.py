@@ -139,3 +139,32 @@ def test_plan_names_round_trip():
             for p, _ in selector.plan_list(op, K):
                 q = Plan.from_name(p.name())
                 assert (q.variant, q.lanes, q.chunk, q.flags) == (p.variant, p.lanes, p.chunk, p.flags)
+
+
+def test_merged_network_is_the_members_mean():
+    """merge_tables stacks three networks into one of 3H hidden units whose
+    output is the mean of theirs: checked with the oracle's FP64 forward on
+    random inputs (the merged parameters are stored in binary32, so W3 / 3
+    carries one rounding)."""
+    import oracle
+
+    F, H, P = 33, 64, 30
+    rng = np.random.default_rng(7)
+    tables = []
+    for seed in range(3):
+        params = np.concatenate([rng.normal(0, 0.3, H * F), rng.normal(0, 0.1, H), rng.normal(0, 0.2, H * H),
+                                 rng.normal(0, 0.1, H), rng.normal(0, 0.2, P * H), rng.normal(0, 0.1, P)])
+        tables.append({"op": 1, "F": F, "H": H, "P": P, "mean": [0.0] * F, "scale": [1.0] * F,
+                       "params": params.astype(np.float32).tolist(), "seed": seed})
+    merged = selector.merge_tables(tables)
+    assert merged["H"] == 3 * H and merged["seed"] == [0, 1, 2]
+    assert len(merged["params"]) == 3 * H * F + 3 * H + 9 * H * H + 3 * H + P * 3 * H + P
+    X = rng.normal(0, 1, (50, F))
+    ys = [oracle.MLP(*selector.split_params(t)).forward(X) for t in tables]
+    y = oracle.MLP(*selector.split_params(merged)).forward(X)
+    want = np.mean(ys, 0)
+    assert np.max(np.abs(y - want)) <= 1e-6 * (1 + np.max(np.abs(want)))
+    # a member whose standardisation differs cannot be merged
+    other = dict(tables[0], mean=[1.0] * F)
+    with pytest.raises(ValueError):
+        selector.merge_tables([tables[0], other])
