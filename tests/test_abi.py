@@ -98,6 +98,16 @@ def test_tile_plan_limits(lib):
     assert f(ctypes.byref(big), FAKE, 64, FAKE, 64, 0, 64, FAKE, ctypes.byref(tile(16, 32)), None, 0, None) == -2
 
 
+def test_mlp_size_limits(lib):
+    """The network kernels take F <= 64, H <= 192, P <= 32; larger sizes are
+    refused before anything is launched."""
+    assert lib.mlp_workspace_bytes(33, 192, 30, 10) > 0
+    assert lib.mlp_workspace_bytes(33, 193, 30, 10) == 0
+    assert lib.mlp_forward(FAKE, 33, 193, 30, FAKE, 10, FAKE, None) == -2
+    assert lib.mlp_forward(FAKE, 65, 64, 30, FAKE, 10, FAKE, None) == -2
+    assert lib.mlp_forward(FAKE, 33, 64, 33, FAKE, 10, FAKE, None) == -2
+
+
 def test_plan_rank_argument_errors(lib):
     """Checked before the device is touched: null outputs, k outside 1..32, K, op."""
     A = csr()

@@ -67,8 +67,9 @@ def rand_params(P, H=64, F=33, seed=0):
     return [a.astype(np.float32) for a in (W1, b1, W2, b2, W3, b3)]
 
 
-def test_mlp_forward_grad_adam_match_oracle(spk, sel):
-    P, H, F, N = 16, 64, 33, 300
+@pytest.mark.parametrize("H", [64, 192])  # one network; three averaged (the largest the kernels take)
+def test_mlp_forward_grad_adam_match_oracle(spk, sel, H):
+    P, F, N = 16, 33, 300
     parts = rand_params(P, H, F, 1)
     r = np.random.default_rng(2)
     X = r.normal(size=(N, F)).astype(np.float32)
